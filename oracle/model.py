@@ -1,0 +1,669 @@
+"""One time step of the coupled phase-field lattice Boltzmann system, FP64 CPU.
+
+Test infrastructure (see the package docstring).  Every quantity is computed
+at every node with plain tensor operations; neighbour values are shifted
+copies of whole fields with the ghost rules of the boundaries.
+
+What the paper fixes and what is a reading
+------------------------------------------
+Paper:
+  * free-energy terms f1, f2, f3 and their derivatives (Sec. 2.1, double-well
+    and interaction-energy equations);
+  * the coupled equations for phi, psi, C, theta (Sec. 2.1, anisotropic
+    system), F(U), the anisotropy vector N, a_s(n) for cubic crystals
+    (Sec. 3.3);
+  * lambda p'(psi), q(psi), a(psi), h(psi) for beta_psi = 1/4, psi = +-1
+    (Sec. 2.1, specialisation paragraph); lambda = 1/(a2 Pe_D) (Sec. 3.3 with
+    Appendix A);
+  * incompressible NS with mass flux m, surface tension in potential form,
+    property interpolation (Sec. 2.2);
+  * the unified LB evolution equation (Sec. 3) and the explicit AAC and heat
+    models with their equilibria, sources, auxiliary terms and relaxation
+    relations (Appendix B); Lambda = M^-1 S M;
+  * half-way bounce-back walls (Sec. 3).
+Readings (the paper defers the CAC, solute and NS schemes and the
+fluid-solid force to other works):
+  * NS: pressure-based incompressible scheme, p recovered from the moving
+    populations, rho from phi; forcing with a v.grad(rho) zeroth moment.
+  * The mass-flux term enters as the force (drho/dphi) div(D_phi (x) v0).
+  * Fluid-solid force rho f = -2 chi rho v*, chi = clamp(h(psi), 0, 1), so
+    that v = (1 - chi) v*.
+  * CAC: f_eq = w phi (1 + c.v/cs2) with the sharpening flux and d(phi v)/dt
+    carried by the auxiliary term G.
+  * Solute: equilibrium w_i [C + c_i.B/cs2] with diffusivity
+    D q/m = (1/s - 1/2) cs2, m = 1 - (1-k) h(psi), and first moment
+    B = C v - D q C (1-k) grad(h)/m^2 + (1-k)(J_at + J), auxiliary term
+    dB/dt.  Since (1-k) grad U = grad(C/m), this is the solute equation of
+    Sec. 2.1 with the anti-trapping and vacuum fluxes.
+  * MRT: only the stress (NS) or flux (scalar) moments relax at a rate
+    other than 1.
+  * Stencils: isotropic D2Q9/D3Q19 finite differences.
+  * Time derivatives: backward differences against history; zero on the
+    first step.
+  * Time-stretched AAC streaming: linear interpolation in time,
+    a_n f(y, n+1) + (1 - a_n) f(y, n) = f*(x).
+  * Normals vanish where |grad|^2 <= delta_n2; there a_s = 1 and N = 0.
+  * F(U) = 1/Le + Mc_inf max(1 + (1-k) U, 0); q clamped to [0, 1].
+  * Stencil ghosts at walls mirror scalars and negate D_phi (x) v0.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import asymptotics
+from .lattice import lattice
+
+DT = torch.float64
+
+PHI_L, PHI_G = 1.0, 0.0
+PSI_S, PSI_L = 1.0, -1.0
+BETA_PHI = 0.25
+BETA_PSI = 0.25
+A_AT = 1.0 / (2.0 * math.sqrt(2.0))   # a(psi) for beta_psi = 1/4, psi = +-1
+
+
+def anisotropy(g, angle, eps4, delta_n2):
+    """a_s(n) and N for the cubic anisotropy of Sec. 3.3 at gradient g.
+
+    With g' = R(angle)^T g the gradient in the crystal frame, G = |g'|^2 and
+    S4 = sum g'_a^4: a_s = 1 - 3 eps + 4 eps S4 / G^2 (the Sec. 3.3 formula
+    with n = g'/|g'|), N'_a = |g|^2 a_s d a_s / d g'_a
+    = 16 eps a_s g'_a (g'_a^2 G - S4) / G^2, and N = R N'.  Where
+    |g|^2 <= delta_n2 the normal is undefined: a_s = 1, N = 0.
+    Rotation is about the z axis in 3D.
+    """
+    one = torch.ones_like(g[0])
+    mask = (g * g).sum(0) > delta_n2
+    cth, sth = torch.cos(angle), torch.sin(angle)
+    gr = g.clone()
+    gr[0] = cth * g[0] + sth * g[1]
+    gr[1] = -sth * g[0] + cth * g[1]
+    G = (gr * gr).sum(0)
+    S4 = (gr ** 4).sum(0)
+    Gs = torch.where(mask, G, one)
+    a_s = torch.where(mask, 1 - 3 * eps4 + 4 * eps4 * S4 / (Gs * Gs), one)
+    Nr = torch.where(mask, 16 * eps4 * a_s * gr * (gr * gr * Gs - S4) / (Gs * Gs), 0.0 * gr)
+    N = Nr.clone()
+    N[0] = cth * Nr[0] - sth * Nr[1]
+    N[1] = sth * Nr[0] + cth * Nr[1]
+    return a_s, N
+
+
+@dataclass
+class OracleParams:
+    """Primary inputs of a workload plus the constants derived from them."""
+    dim: int
+    shape: tuple                 # (nx, ny[, nz])
+    periodic: tuple
+    fields: tuple
+    phi_q: int
+    W0: float
+    tau0: float
+    eps4: object
+    k: object
+    PeD: float
+    Le: float
+    Mcinf: float
+    U0: object
+    theta0: object
+    rho_l: float
+    rho_g: float
+    nu_l: float
+    nu_g: float
+    sigma: float
+    M_phi: float
+    xi: float
+    beta_inter: float
+    g: float
+    delta_n2: float
+    seeds: list = field(default_factory=list)
+    bubbles: list = field(default_factory=list)
+
+    @classmethod
+    def from_workload(cls, w):
+        dim = w["dim"]
+        shape = (w["nx"], w["ny"]) if dim == 2 else (w["nx"], w["ny"], w["nz"])
+        return cls(dim=dim, shape=shape, periodic=tuple(w["periodic"][:dim]),
+                   fields=tuple(w["fields"]), phi_q=w["phi_q"], W0=w["W0"],
+                   tau0=w["tau0"], eps4=w["eps4"], k=w["k"], PeD=w["PeD"],
+                   Le=w["Le"], Mcinf=w["Mcinf"], U0=w["U0"], theta0=w["theta0"],
+                   rho_l=w["rho_l"], rho_g=w["rho_g"], nu_l=w["nu_l"], nu_g=w["nu_g"],
+                   sigma=w["sigma"], M_phi=w["M_phi"], xi=w["xi"],
+                   beta_inter=w["beta_inter"], g=w["g"], delta_n2=w["delta_n2"],
+                   seeds=[dict(s) for s in w["seeds"]],
+                   bubbles=[dict(b) for b in w["bubbles"]])
+
+    # --- derived constants -------------------------------------------------
+    @property
+    def d_psi(self):
+        """W0^2 / tau0 in lattice units (Appendix B AAC relaxation relation)."""
+        return self.W0 ** 2 / self.tau0
+
+    @property
+    def D(self):
+        """Solute diffusivity from Pe_D = W0^2/(D tau0) (Sec. 3.3)."""
+        return self.d_psi / self.PeD
+
+    @property
+    def isothermal(self):
+        return "theta" not in self.fields
+
+    @property
+    def inv_Le(self):
+        return 0.0 if (self.isothermal or math.isinf(self.Le)) else 1.0 / self.Le
+
+    @property
+    def alpha(self):
+        """Thermal diffusivity alpha = Le D (Sec. 2.1, F(U) paragraph)."""
+        return self.Le * self.D
+
+    @property
+    def lam(self):
+        """Coupling constant lambda = 1/(a2 Pe_D) (Sec. 3.3 with Appendix A)."""
+        return 1.0 / (asymptotics.closed_form()["a2"] * self.PeD)
+
+    @property
+    def W_phi(self):
+        """Interface parameter from the width xi of phi = 1/2 + 1/2 tanh(2x/xi)."""
+        return self.xi / (4.0 * math.sqrt(2.0))
+
+    @property
+    def k_s(self):
+        """Prefactor of the potential form of F_s (Sec. 2.2, last equation)."""
+        return 6.0 * self.sigma / ((PHI_L - PHI_G) ** 3 * self.W_phi * math.sqrt(2.0 * BETA_PHI))
+
+
+class OracleSim:
+    """Holds the state (populations in node form, pre-collision) and steps it."""
+
+    def __init__(self, params: OracleParams):
+        self.p = P = params
+        self.d = P.dim
+        if P.dim == 2:
+            self.L_ns = lattice("D2Q9")
+            self.L_sc = lattice("D2Q5")
+            self.L_phi = lattice("D2Q9" if P.phi_q == 9 else "D2Q5")
+            self.L_st = lattice("D2Q9")
+        else:
+            self.L_ns = lattice("D3Q19")
+            self.L_sc = lattice("D3Q7")
+            self.L_phi = lattice("D3Q7")
+            self.L_st = lattice("D3Q19")
+        if "psi" not in P.fields and ("c" in P.fields or "theta" in P.fields):
+            raise ValueError("solute/heat need the solid order parameter")
+        if P.isothermal and P.bubbles and "c" in P.fields and "phi" in P.fields:
+            raise ValueError("isothermal runs with bubbles are unsupported (F(U) -> 0 in gas)")
+        self.grid = tuple(reversed(P.shape))          # tensor shape: [z][y][x]
+        self.n = 0
+        self.first = True
+        self.state = None
+        self.an_override = None     # test hook: force a_n to a constant
+        self.S_override = None      # test hook: force S_psi to a constant
+
+    # ------------------------------------------------------------------ geometry
+    def _coords(self):
+        axes = [torch.arange(s, dtype=DT) for s in self.grid]
+        mesh = torch.meshgrid(*axes, indexing="ij")
+        return list(reversed(mesh))                   # [X, Y(, Z)]
+
+    def _dist(self, X, centre):
+        """Distance to a point with the periodic minimum image on periodic axes."""
+        d2 = torch.zeros(self.grid, dtype=DT)
+        for a in range(self.d):
+            dd = torch.abs(X[a] - centre[a])
+            if self.p.periodic[a]:
+                n = self.p.shape[a]
+                dd = torch.minimum(dd, n - dd)
+            d2 = d2 + dd * dd
+        return d2
+
+    # ------------------------------------------------------------ stencil access
+    def nb(self, f, e, anti=False):
+        """Field value at x + e; walls mirror (anti: and negate) ghost nodes."""
+        out = f
+        for a, ea in enumerate(e):
+            ea = int(ea)
+            if ea == 0:
+                continue
+            dim = f.dim() - 1 - a
+            n = f.shape[dim]
+            if self.p.periodic[a]:
+                out = torch.roll(out, shifts=-ea, dims=dim)
+            else:
+                idx = torch.arange(n) + ea
+                ghost = (idx < 0) | (idx >= n)
+                idx = torch.where(idx < 0, -1 - idx, idx)
+                idx = torch.where(idx >= n, 2 * n - 1 - idx, idx)
+                out = torch.index_select(out, dim, idx)
+                if anti:
+                    s = torch.where(ghost, -1.0, 1.0).to(DT)
+                    shp = [1] * f.dim()
+                    shp[dim] = n
+                    out = out * s.view(shp)
+        return out
+
+    def grad(self, f):
+        """Isotropic gradient (1/cs2) sum_i w_i c_i f(x + c_i)."""
+        L = self.L_st
+        out = torch.zeros((self.d,) + f.shape, dtype=DT)
+        for i in range(1, L.Q):
+            fi = self.nb(f, L.c[i])
+            for a in range(self.d):
+                if L.c[i, a] != 0:
+                    out[a] = out[a] + L.w[i] * L.c[i, a] * fi
+        return out / L.cs2
+
+    def lap(self, f):
+        """Isotropic Laplacian (2/cs2) sum_i w_i [f(x + c_i) - f(x)]."""
+        L = self.L_st
+        out = torch.zeros_like(f)
+        for i in range(1, L.Q):
+            out = out + L.w[i] * (self.nb(f, L.c[i]) - f)
+        return 2.0 * out / L.cs2
+
+    def div_tensor(self, X):
+        """(div X)_b = (1/cs2) sum_i w_i sum_a c_ia X_ab(x + c_i); X antisymmetric at walls."""
+        L = self.L_st
+        out = torch.zeros((self.d,) + X.shape[2:], dtype=DT)
+        for i in range(1, L.Q):
+            Xi = self.nb(X, L.c[i], anti=True)
+            for a in range(self.d):
+                if L.c[i, a] != 0:
+                    out = out + L.w[i] * L.c[i, a] * Xi[a]
+        return out / L.cs2
+
+    # ---------------------------------------------------------------- streaming
+    def stream(self, fs, L):
+        """out_i(y) = fs_i(y - c_i); across a wall, out_i(y) = fs_opp(i)(y)."""
+        out = torch.empty_like(fs)
+        for i in range(L.Q):
+            src = fs[i]
+            mask = torch.zeros(self.grid, dtype=torch.bool)
+            for a in range(self.d):
+                ca = int(L.c[i, a])
+                if ca == 0:
+                    continue
+                dim = self.d - 1 - a
+                src = torch.roll(src, shifts=ca, dims=dim)
+                if not self.p.periodic[a]:
+                    n = self.grid[dim]
+                    idx = torch.arange(n)
+                    edge = (idx == 0) if ca > 0 else (idx == n - 1)
+                    shp = [1] * self.d
+                    shp[dim] = n
+                    mask = mask | edge.view(shp).expand(self.grid)
+            out[i] = torch.where(mask, fs[L.opp[i]], src)
+        return out
+
+    # ------------------------------------------------------------- collision
+    @staticmethod
+    def mrt(L, f, feq, rates):
+        """Lambda (f - feq) with Lambda = M^-1 S M; rates: row -> per-node rate."""
+        m = torch.einsum("ij,j...->i...", L.M, f - feq)
+        S = torch.ones_like(m)
+        for row, s in rates.items():
+            S[row] = s
+        return torch.einsum("ij,j...->i...", L.Minv, S * m)
+
+    @staticmethod
+    def lam_apply(L, G, rates):
+        m = torch.einsum("ij,j...->i...", L.M, G)
+        S = torch.ones_like(m)
+        for row, s in rates.items():
+            S[row] = s
+        return torch.einsum("ij,j...->i...", L.Minv, S * m)
+
+    @staticmethod
+    def cdot(L, vec):
+        """c_i . vec for every velocity: (Q, *grid)."""
+        return torch.einsum("ia,a...->i...", L.c, vec)
+
+    @staticmethod
+    def wv(L, shape_like):
+        return L.w.view((-1,) + (1,) * shape_like.dim())
+
+    # -------------------------------------------------------------------- init
+    def init_fields(self):
+        """Initial profiles (Sec. 3.2 bubble profile, Sec. 2.1 psi^eq) and
+        equilibrium populations at rest with zero fluxes.  Parity pinned by the
+        flat-profile and conservation tests."""
+        P = self.p
+        X = self._coords()
+        # bubble phase
+        if "phi" in P.fields and P.bubbles:
+            db = None
+            for b in P.bubbles:
+                cen = [b["x"], b["y"], b["z"]]
+                d = torch.sqrt(self._dist(X, cen)) - b["r"]
+                db = d if db is None else torch.minimum(db, d)
+            phi = (PHI_L + PHI_G) / 2 + (PHI_L - PHI_G) / 2 * torch.tanh(
+                (PHI_L - PHI_G) * math.sqrt(2 * BETA_PHI) / (2 * P.W_phi) * db)
+        else:
+            phi = torch.full(self.grid, PHI_L, dtype=DT)
+        # solid order parameter and grain angle of the nearest seed
+        if P.seeds:
+            ds = None
+            best = None
+            ang = torch.zeros(self.grid, dtype=DT)
+            for s in P.seeds:
+                cen = [s["x"], s["y"], s["z"]]
+                d2 = self._dist(X, cen)
+                d = torch.sqrt(d2) - s["r"]
+                ds = d if ds is None else torch.minimum(ds, d)
+                if best is None:
+                    best = d2
+                    ang = torch.full(self.grid, float(s["angle"]), dtype=DT)
+                else:
+                    closer = d2 < best
+                    ang = torch.where(closer, torch.full_like(ang, float(s["angle"])), ang)
+                    best = torch.where(closer, d2, best)
+            psi = (PSI_S + PSI_L) / 2 + (PSI_S - PSI_L) / 2 * torch.tanh(
+                (PSI_S - PSI_L) * math.sqrt(2 * BETA_PSI) / (2 * P.W0) * (-ds))
+        else:
+            psi = torch.full(self.grid, PSI_L, dtype=DT)
+            ang = torch.zeros(self.grid, dtype=DT)
+        if "psi" not in P.fields:
+            psi = torch.full(self.grid, PSI_L, dtype=DT)
+        self.angle = ang
+        h = (psi - PSI_L) / (PSI_S - PSI_L)
+        st = {}
+        Ls, Lp, Ln = self.L_sc, self.L_phi, self.L_ns
+        ws = self.wv(Ls, psi)
+        if "phi" in P.fields:
+            st["f_phi"] = self.wv(Lp, phi) * phi
+        if "psi" in P.fields:
+            st["f_psi"] = ws * psi
+        if "c" in P.fields:
+            C = phi * (1 + (1 - P.k) * P.U0) * (1 - (1 - P.k) * h)
+            st["f_c"] = ws * C
+        if "theta" in P.fields:
+            theta = torch.full(self.grid, 1.0, dtype=DT) * P.theta0
+            H = theta - h
+            gth = ws * theta
+            gth[0] = H + (Ls.w[0] - 1) * theta
+            st["g_th"] = gth
+        if "ns" in P.fields:
+            st["f_ns"] = torch.zeros((Ln.Q,) + self.grid, dtype=DT)
+        z = torch.zeros(self.grid, dtype=DT)
+        zv = torch.zeros((self.d,) + self.grid, dtype=DT)
+        st["psi_prev"] = z.clone()
+        st["S_prev"] = z.clone()
+        st["phiv_prev"] = zv.clone()
+        st["B_prev"] = zv.clone()
+        st["Hv_prev"] = zv.clone()
+        self.state = st
+        self.n = 0
+        self.first = True
+
+    def init_from_macros(self, phi=None, psi=None, C=None, theta=None, v=None, angle=None):
+        """Rest-equilibrium populations of given macro fields (tensor shape
+        [z][y][x]); missing fields take the bulk liquid values.  NS
+        populations are the equilibrium at p = 0 with velocity v."""
+        P = self.p
+        one = torch.ones(self.grid, dtype=DT)
+        phi = one * PHI_L if phi is None else phi
+        psi = one * PSI_L if psi is None else psi
+        self.angle = torch.zeros(self.grid, dtype=DT) if angle is None else angle
+        h = (psi - PSI_L) / (PSI_S - PSI_L)
+        Ls, Lp, Ln = self.L_sc, self.L_phi, self.L_ns
+        ws = self.wv(Ls, psi)
+        st = {}
+        if "phi" in P.fields:
+            st["f_phi"] = self.wv(Lp, phi) * phi
+        if "psi" in P.fields:
+            st["f_psi"] = ws * psi
+        if "c" in P.fields:
+            C = one * (1 + (1 - P.k) * P.U0) * (1 - (1 - P.k) * h) * phi if C is None else C
+            st["f_c"] = ws * C
+        if "theta" in P.fields:
+            theta = one * P.theta0 if theta is None else theta
+            gth = ws * theta
+            gth[0] = (theta - h) + (Ls.w[0] - 1) * theta
+            st["g_th"] = gth
+        if "ns" in P.fields:
+            vv = torch.zeros((self.d,) + self.grid, dtype=DT) if v is None else v
+            rho = P.rho_g + (P.rho_l - P.rho_g) * (phi - PHI_G) / (PHI_L - PHI_G)
+            cv = self.cdot(Ln, vv)
+            v2 = (vv * vv).sum(0)
+            st["f_ns"] = self.wv(Ln, v2) * rho * (cv / Ln.cs2 + cv * cv / (2 * Ln.cs2 ** 2)
+                                                 - v2 / (2 * Ln.cs2))
+        z = torch.zeros(self.grid, dtype=DT)
+        zv = torch.zeros((self.d,) + self.grid, dtype=DT)
+        st.update(psi_prev=z.clone(), S_prev=z.clone(), phiv_prev=zv.clone(),
+                  B_prev=zv.clone(), Hv_prev=zv.clone())
+        self.state = st
+        self.n = 0
+        self.first = True
+
+    # -------------------------------------------------------- node quantities
+    def compute(self):
+        """Steps S1-S9 of one time step at every node (moments, stencils,
+        anisotropy, kinetics, forces, velocity, pressure)."""
+        P, st = self.p, self.state
+        d = self.d
+        one = torch.ones(self.grid, dtype=DT)
+        q = {}
+        # S1 moments (Appendix B: psi = sum f_i, H = sum g_i / rho with rho_theta = 1)
+        phi = st["f_phi"].sum(0) if "phi" in P.fields else one * PHI_L
+        psi = st["f_psi"].sum(0) if "psi" in P.fields else one * PSI_L
+        # S2 derived scalars
+        h = (psi - PSI_L) / (PSI_S - PSI_L)
+        qf = torch.clamp((PSI_S - psi) / (PSI_S - PSI_L), 0.0, 1.0)
+        chi = torch.clamp(h, 0.0, 1.0)
+        if "c" in P.fields:
+            C = st["f_c"].sum(0)
+            U = (C / (1 - (1 - P.k) * h) - 1) / (1 - P.k)
+        else:
+            C = None
+            U = one * P.U0
+        if "theta" in P.fields:
+            H = st["g_th"].sum(0)
+            theta = H + h
+        else:
+            H = None
+            theta = one * P.theta0
+        # S3 stencils
+        gphi = self.grad(phi)
+        lphi = self.lap(phi)
+        gpsi = self.grad(psi)
+        gU = self.grad(U)
+        # S4 unit normals (normal vanishes where |grad|^2 <= delta_n2)
+        gphi2 = (gphi * gphi).sum(0)
+        mphi = gphi2 > P.delta_n2
+        nphi = torch.where(mphi, gphi / torch.sqrt(torch.where(mphi, gphi2, one)), 0.0 * gphi)
+        gpsi2 = (gpsi * gpsi).sum(0)
+        mpsi = gpsi2 > P.delta_n2
+        epsi = torch.where(mpsi, gpsi / torch.sqrt(torch.where(mpsi, gpsi2, one)), 0.0 * gpsi)
+        # S5 anisotropy in the crystal frame (Sec. 3.3 a_s; Sec. 2.1 N)
+        a_s, N = anisotropy(gpsi, self.angle, P.eps4, P.delta_n2)
+        # S6 kinetics F(U) (Sec. 2.1, with max(., 0))
+        lin = 1 + (1 - P.k) * U
+        F = P.inv_Le + P.Mcinf * torch.clamp(lin, min=0.0)
+        gF = torch.where(lin > 0, P.Mcinf * (1 - P.k) * gU, 0.0 * gU)
+        # S7 psi source (Appendix B rewritten AAC)
+        f2p = 2 * BETA_PSI * (PSI_S - psi) * (psi - PSI_L) * (PSI_S + PSI_L - 2 * psi)
+        f3psi = 2 * P.beta_inter * (PHI_L - phi) ** 2 * (psi - PSI_L)
+        pprime = 30.0 / (PSI_S - PSI_L) ** 5 * (PSI_S - psi) ** 2 * (psi - PSI_L) ** 2
+        Qpsi = -(f2p + f3psi + P.lam * pprime * (theta + P.Mcinf * U))
+        a2 = a_s * a_s
+        S_psi = P.d_psi / (F * F) * (gF * (a2 * gpsi + N)).sum(0) + Qpsi / (P.tau0 * F)
+        if self.S_override is not None:
+            S_psi = one * self.S_override
+        D_psi = P.d_psi * a2 / F
+        s_psi = 1.0 / (D_psi / self.L_sc.cs2 + 0.5)
+        # S8 chemical potential, surface tension (potential form), CAC flux
+        f1p = 2 * BETA_PHI * (PHI_L - phi) * (phi - PHI_G) * (PHI_L + PHI_G - 2 * phi)
+        f3phi = -2 * P.beta_inter * (PHI_L - phi) * (psi - PSI_L) ** 2
+        mu_phi = f1p + f3phi - P.W_phi ** 2 * lphi
+        sharp = math.sqrt(2 * BETA_PHI) / P.W_phi * (PHI_L - phi) * (phi - PHI_G)
+        Dphi = P.M_phi * (gphi - sharp * nphi)
+        # S9 density, velocity, forces, pressure
+        drho = (P.rho_l - P.rho_g) / (PHI_L - PHI_G)
+        rho = P.rho_g + drho * (phi - PHI_G)
+        mu_l, mu_g = P.rho_l * P.nu_l, P.rho_g * P.nu_g
+        mu = mu_g + (mu_l - mu_g) * (phi - PHI_G) / (PHI_L - PHI_G)
+        nu = mu / rho
+        gradrho = drho * gphi
+        if "ns" in P.fields:
+            Ln = self.L_ns
+            fns = st["f_ns"]
+            j = torch.einsum("ia,i...->a...", Ln.c, fns)
+            Fs = P.k_s * mu_phi * gphi
+            Fb = torch.zeros_like(gphi)
+            Fb[1] = -rho * P.g
+            v0 = (1 - chi) * (j + 0.5 * (Fs + Fb)) / rho
+            X = Dphi.unsqueeze(1) * v0.unsqueeze(0)      # X_ab = D_a v0_b
+            Fm = drho * self.div_tensor(X)
+            rvs = j + 0.5 * (Fs + Fb + Fm)
+            v = (1 - chi) * rvs / rho
+            rf = -2 * chi * rvs
+            Ftot = Fs + Fb + Fm + rf
+            w0 = Ln.w[0]
+            s0 = -w0 * (v * v).sum(0) / (2 * Ln.cs2)
+            p = Ln.cs2 / (1 - w0) * (fns[1:].sum(0) + 0.5 * (v * gradrho).sum(0) + rho * s0)
+        else:
+            v = torch.zeros((d,) + self.grid, dtype=DT)
+            Ftot = torch.zeros_like(v)
+            p = torch.zeros(self.grid, dtype=DT)
+        q.update(phi=phi, psi=psi, h=h, qf=qf, chi=chi, C=C, U=U, H=H, theta=theta,
+                 gphi=gphi, nphi=nphi, gpsi=gpsi, epsi=epsi, a_s=a_s, N=N, F=F,
+                 S_psi=S_psi, s_psi=s_psi, sharp=sharp, rho=rho, nu=nu,
+                 gradrho=gradrho, v=v, Ftot=Ftot, p=p)
+        return q
+
+    # -------------------------------------------------------------------- step
+    def step(self, nsteps=1):
+        for _ in range(nsteps):
+            self._step()
+
+    def _step(self):
+        """S10-S12: collisions of every set, streaming, history."""
+        P, st = self.p, self.state
+        q = self.compute()
+        new = {}
+        first = self.first
+        v = q["v"]
+        # NS (pressure-based incompressible scheme with forcing)
+        if "ns" in P.fields:
+            L = self.L_ns
+            f = st["f_ns"]
+            cv = self.cdot(L, v)
+            vv = (v * v).sum(0)
+            w = self.wv(L, vv)
+            s_i = w * (cv / L.cs2 + cv * cv / (2 * L.cs2 ** 2) - vv / (2 * L.cs2))
+            feq = w * q["p"] / L.cs2 + q["rho"] * s_i
+            feq[0] = feq[0] - q["p"] / L.cs2
+            Fv = q["Ftot"]
+            cF = self.cdot(L, Fv)
+            vF = (v * Fv).sum(0)
+            # (vF + Fv):(c c - cs2 I) / (2 cs4) = [2 (c.v)(c.F) - 2 cs2 v.F] / (2 cs4)
+            Ft = w * ((v * q["gradrho"]).sum(0) + cF / L.cs2
+                      + (2 * cv * cF - 2 * L.cs2 * vF) / (2 * L.cs2 ** 2))
+            s_nu = 1.0 / (q["nu"] / L.cs2 + 0.5)
+            rates = {r: s_nu for r in L.stress_rows}
+            fstar = f - self.mrt(L, f, feq, rates) + Ft - 0.5 * self.lam_apply(L, Ft, rates)
+            new["f_ns"] = self.stream(fstar, L)
+        # CAC
+        phiv = q["phi"] * v
+        if "phi" in P.fields:
+            L = self.L_phi
+            f = st["f_phi"]
+            w = self.wv(L, q["phi"])
+            feq = w * q["phi"] * (1 + self.cdot(L, v) / L.cs2)
+            prev = phiv if first else st["phiv_prev"]
+            flux = (phiv - prev) + L.cs2 * q["sharp"] * q["nphi"]
+            G = w * self.cdot(L, flux) / L.cs2
+            s1 = 1.0 / (P.M_phi / L.cs2 + 0.5)
+            rates = {r: s1 for r in L.flux_rows}
+            fstar = f - self.mrt(L, f, feq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
+            new["f_phi"] = self.stream(fstar, L)
+        # AAC with the time-stretched streaming
+        if "psi" in P.fields:
+            L = self.L_sc
+            f = st["f_psi"]
+            w = self.wv(L, q["psi"])
+            feq = w * q["psi"]
+            Sprev = q["S_psi"] if first else st["S_prev"]
+            Fi = w * q["S_psi"]
+            dFi = 0.5 * w * (q["S_psi"] - Sprev)
+            G = -w * self.cdot(L, q["N"]) / (q["a_s"] * q["a_s"])
+            rates = {r: q["s_psi"] for r in L.flux_rows}
+            fstar = f - self.mrt(L, f, feq, rates) + Fi + dFi + G - 0.5 * self.lam_apply(L, G, rates)
+            an = q["a_s"] * q["a_s"]
+            if self.an_override is not None:
+                an = torch.ones_like(an) * self.an_override
+            fs_str = self.stream(fstar, L)
+            an_str = self.stream(an.unsqueeze(0).expand(L.Q, *an.shape).clone(), L)
+            new["f_psi"] = (fs_str - (1 - an_str) * f) / an_str
+        # solute: conserved C in the zeroth moment, diffusivity D q / m with
+        # m = 1 - (1-k) h, and the rest of (1-k) D q grad U carried as a drift
+        # in the first moment together with convection and the two fluxes
+        if "c" in P.fields:
+            L = self.L_sc
+            f = st["f_c"]
+            psi_prev = q["psi"] if first else st["psi_prev"]
+            Jat = -A_AT * P.W0 * q["a_s"] * (1 + (1 - P.k) * q["U"]) * (q["psi"] - psi_prev) * q["epsi"]
+            Jv = (P.D * q["qf"] * q["C"] * math.sqrt(2 * BETA_PHI) / P.W_phi
+                  * (PHI_L - q["phi"]) * q["nphi"])
+            m = 1 - (1 - P.k) * q["h"]
+            gh = q["gpsi"] / (PSI_S - PSI_L)
+            drift = P.D * q["qf"] * q["C"] * (1 - P.k) * gh / (m * m)
+            B = q["C"] * v - drift + (1 - P.k) * (Jat + Jv)
+            w = self.wv(L, q["C"])
+            feq = w * q["C"] + w * self.cdot(L, B) / L.cs2
+            Bprev = B if first else st["B_prev"]
+            G = w * self.cdot(L, B - Bprev) / L.cs2
+            s1 = 1.0 / (P.D * q["qf"] / (m * L.cs2) + 0.5)
+            rates = {r: s1 for r in L.flux_rows}
+            fstar = f - self.mrt(L, f, feq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
+            new["f_c"] = self.stream(fstar, L)
+            new["B_prev"] = B
+        else:
+            new["B_prev"] = st["B_prev"]
+        # heat (Appendix B, rho c_p = c_p^s = 1)
+        Hv = (q["H"] * v) if q["H"] is not None else torch.zeros_like(v)
+        if "theta" in P.fields:
+            L = self.L_sc
+            g = st["g_th"]
+            w = self.wv(L, q["H"])
+            geq = w * q["theta"] + w * self.cdot(L, Hv) / L.cs2
+            geq[0] = q["H"] + (L.w[0] - 1) * q["theta"]
+            Hprev = Hv if first else st["Hv_prev"]
+            G = w * self.cdot(L, Hv - Hprev) / L.cs2
+            s1 = 1.0 / (P.alpha / L.cs2 + 0.5)
+            rates = {r: s1 for r in L.flux_rows}
+            gstar = g - self.mrt(L, g, geq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
+            new["g_th"] = self.stream(gstar, L)
+        # history
+        new["psi_prev"] = q["psi"]
+        new["S_prev"] = q["S_psi"]
+        new["phiv_prev"] = phiv
+        new["Hv_prev"] = Hv
+        self.state = new
+        self.n += 1
+        self.first = False
+
+    # ------------------------------------------------------------------ output
+    def macros(self):
+        """phi, psi, C, theta, U, p, v of the current state."""
+        q = self.compute()
+        out = dict(phi=q["phi"], psi=q["psi"], theta=q["theta"], U=q["U"], p=q["p"], v=q["v"])
+        out["C"] = q["C"] if q["C"] is not None else torch.zeros_like(q["phi"])
+        return out
+
+    def reduce(self):
+        """Global FP64 sums: sum phi, gas volume, sum C, solid fraction, gas centroid."""
+        m = self.macros()
+        P = self.p
+        gas = (PHI_L - m["phi"]) / (PHI_L - PHI_G)
+        vol = float(gas.sum())
+        X = self._coords()
+        cen = [float((gas * X[a]).sum() / vol) if vol > 0 else 0.0 for a in range(self.d)]
+        h = (m["psi"] - PSI_L) / (PSI_S - PSI_L)
+        return dict(sum_phi=float(m["phi"].sum()), gas_volume=vol,
+                    sum_C=float(m["C"].sum()), solid_fraction=float(h.mean()),
+                    gas_centroid=cen + [0.0] * (3 - self.d),
+                    nonfinite=int(not all(torch.isfinite(t).all() for t in self.state.values())))

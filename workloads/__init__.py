@@ -1,0 +1,240 @@
+"""Seeded synthetic workloads shared by the oracle, the tests and the benchmark.
+
+This module only *describes* inputs: grid shapes, boundary types, which
+fields are active, the physical parameter values each workload uses, and the
+positions / radii / rotation angles of solid seeds and gas bubbles drawn with
+``numpy.random.default_rng``.  It holds none of the method's arithmetic: no
+derived constants, no profiles, no lattice tables.  Both the oracle and the
+GPU library derive everything they compute from these primary inputs on
+their own.
+
+Parameter values follow the paper where it fixes them:
+
+* the double-well and interaction constants (Sec. 3, numerical method
+  paragraph): phi_l = 1, phi_g = 0, psi_s = 1, psi_l = -1, beta = 1/4,
+  beta_inter = 3/4;
+* lattice spacing dx = 0.4 W0, so W0 = 2.5 nodes (Sec. 3.3 and Sec. 4);
+* time steps dt/tau0 = 0.004 (Sec. 4 coupled runs) and 0.02 (Sec. 3.3 case A);
+* k = 0.15, Omega = 0.55 (Sec. 3.3, Sec. 4), the Sec. 3.3 case A closure
+  theta = 0, Mc_inf = 1, U0 = -Omega;
+
+and follow the workload descriptions otherwise (grid sizes, density ratios,
+interface width 4 nodes, seed and bubble counts and radii).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+FIELDS_ALL = ("ns", "phi", "psi", "c", "theta")
+
+# Primary inputs common to every coupled workload.
+_BASE = dict(
+    dim=2, nx=128, ny=128, nz=1,
+    periodic=(True, False, True),       # per axis x, y, z; False = half-way walls
+    fields=FIELDS_ALL,
+    phi_q=5,                             # lattice of the bubble phase field (5/9 in 2D, 7 in 3D)
+    W0=2.5,                              # interface width in nodes (dx = 0.4 W0)
+    tau0=250.0,                          # relaxation time in steps (dt = 0.004 tau0)
+    eps4=0.05, k=0.15, PeD=0.5, Le=50.0, Mcinf=1.0,
+    U0=0.0, theta0=-0.55,
+    rho_l=1.0, rho_g=0.1, nu_l=0.1, nu_g=0.1,
+    sigma=0.005, M_phi=0.1, xi=4.0, beta_inter=0.75, g=0.0,
+    delta_n2=1e-20,
+    seeds=[], bubbles=[],
+    steps=500, store="f64",
+)
+
+
+def _place(rng, n, shape, radius_fn, min_gap_fn, placed, tries=20000):
+    """Sequential rejection sampling of non-overlapping circles/spheres."""
+    out = []
+    dim = len(shape)
+    for _ in range(n):
+        for _t in range(tries):
+            r = radius_fn(rng)
+            pos = [rng.uniform(0, shape[a]) for a in range(dim)]
+            ok = True
+            for (q, rq, kind) in placed + [(o[:dim], o[dim], "new") for o in out]:
+                d2 = 0.0
+                for a in range(dim):
+                    dd = abs(pos[a] - q[a])
+                    dd = min(dd, shape[a] - dd)
+                    d2 += dd * dd
+                if math.sqrt(d2) < min_gap_fn(r, rq, kind):
+                    ok = False
+                    break
+            if ok:
+                out.append(tuple(pos) + (r,))
+                break
+        else:
+            raise RuntimeError("could not place object without overlap")
+    return out
+
+
+def _seeds_and_bubbles(rng, shape, nseed, rseed, nbub, rbub_lo, rbub_hi,
+                       seed_gap, wall_axis=None, random_angle=False):
+    dim = len(shape)
+    seeds = _place(rng, nseed, shape, lambda g: float(rseed),
+                   lambda r, rq, kind: seed_gap, [])
+    placed = [(s[:dim], s[dim], "seed") for s in seeds]
+    bubbles = []
+    for _ in range(nbub):
+        for _t in range(20000):
+            r = float(rng.uniform(rbub_lo, rbub_hi)) if rbub_hi > rbub_lo else float(rbub_lo)
+            pos = [rng.uniform(0, shape[a]) for a in range(dim)]
+            if wall_axis is not None:
+                n = shape[wall_axis]
+                if pos[wall_axis] < r + 8 or pos[wall_axis] > n - 1 - (r + 8):
+                    continue
+            ok = True
+            for (q, rq, kind) in placed:
+                d2 = 0.0
+                for a in range(dim):
+                    dd = abs(pos[a] - q[a])
+                    dd = min(dd, shape[a] - dd)
+                    d2 += dd * dd
+                if math.sqrt(d2) < r + rq + 8:
+                    ok = False
+                    break
+            if ok:
+                bubbles.append(tuple(pos) + (r,))
+                placed.append((pos, r, "bubble"))
+                break
+        else:
+            raise RuntimeError("could not place bubble")
+    angles = ([float(rng.uniform(0.0, math.pi / 4)) for _ in seeds]
+              if random_angle else [0.0] * len(seeds))
+    seeds3 = []
+    for s, a in zip(seeds, angles):
+        pos = list(s[:dim]) + [0.0] * (3 - dim)
+        seeds3.append(dict(x=pos[0], y=pos[1], z=pos[2], r=s[dim], angle=a))
+    bubs3 = []
+    for b in bubbles:
+        pos = list(b[:dim]) + [0.0] * (3 - dim)
+        bubs3.append(dict(x=pos[0], y=pos[1], z=pos[2], r=b[dim]))
+    return seeds3, bubs3
+
+
+def coupled2d_128():
+    """Coupled 2D workload, 128 x 128, FP64, periodic x / walls y, 500 steps:
+    one seed (R 5, eps4 0.05) at the centre, one bubble (R 12) 30 nodes to
+    its right, density ratio 10, interface width 4, k 0.15, undercooling 0.55,
+    quiescent flow."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="coupled2d_128", nx=128, ny=128,
+             seeds=[dict(x=64.0, y=64.0, z=0.0, r=5.0, angle=0.0)],
+             bubbles=[dict(x=94.0, y=64.0, z=0.0, r=12.0)])
+    return c
+
+
+def alloy2d_1024(seed=1, store="f64"):
+    """Isothermal binary-alloy dendrites, 1024 x 1024, no bubbles, 20000 steps:
+    four seeds (R 4) at random positions with random rotations in [0, pi/4);
+    eps4 0.02, k 0.15, Omega 0.55 (theta = 0, Mc_inf = 1, U0 = -Omega)."""
+    c = copy.deepcopy(_BASE)
+    rng = np.random.default_rng(seed)
+    shape = (1024, 1024)
+    seeds, _ = _seeds_and_bubbles(rng, shape, 4, 4.0, 0, 0, 0, seed_gap=128.0,
+                                  random_angle=True)
+    c.update(name="alloy2d_1024", nx=1024, ny=1024, periodic=(True, True, True),
+             fields=("psi", "c"), tau0=50.0, eps4=0.02, Le=math.inf,
+             U0=-0.55, theta0=0.0, seeds=seeds, bubbles=[], steps=20000,
+             store=store, rng_seed=seed)
+    return c
+
+
+def coupled2d_2048(seed=3, store="f16"):
+    """Coupled 2D dendrites plus rising bubbles, 2048 x 2048, 10000 steps:
+    16 seeds (R 4), 24 bubbles (R uniform in [8, 24]), density ratio 100,
+    gravity -y with Bond number 10 at reference diameter 32."""
+    c = copy.deepcopy(_BASE)
+    rng = np.random.default_rng(seed)
+    shape = (2048, 2048)
+    seeds, bubs = _seeds_and_bubbles(rng, shape, 16, 4.0, 24, 8.0, 24.0,
+                                     seed_gap=96.0, wall_axis=1)
+    c.update(name="coupled2d_2048", nx=2048, ny=2048, eps4=0.02, rho_g=0.01,
+             g=10 * 0.005 / 32.0 ** 2, seeds=seeds, bubbles=bubs, steps=10000,
+             store=store, rng_seed=seed)
+    return c
+
+
+def adjoint2d_512(seed=4, store="f32"):
+    """Adjoint workload, 512 x 512, FP32, 2000 steps: 4 seeds (R 4) and
+    4 bubbles (R uniform in [8, 16])."""
+    c = copy.deepcopy(_BASE)
+    rng = np.random.default_rng(seed)
+    shape = (512, 512)
+    seeds, bubs = _seeds_and_bubbles(rng, shape, 4, 4.0, 4, 8.0, 16.0,
+                                     seed_gap=96.0, wall_axis=1)
+    c.update(name="adjoint2d_512", nx=512, ny=512, eps4=0.02, seeds=seeds,
+             bubbles=bubs, steps=2000, store=store, rng_seed=seed)
+    return c
+
+
+def adjoint2d_64():
+    """The 64 x 64 copy of the adjoint workload used for gradient checks."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="adjoint2d_64", nx=64, ny=64, eps4=0.02,
+             seeds=[dict(x=32.0, y=24.0, z=0.0, r=4.0, angle=0.0)],
+             bubbles=[dict(x=16.0, y=46.0, z=0.0, r=8.0),
+                      dict(x=48.0, y=46.0, z=0.0, r=6.0)],
+             steps=2000, store="f64")
+    return c
+
+
+def coupled3d_256(seed=5, store="f16", n=256):
+    """3D coupled workload, n^3 (256^3 by default), D3Q19 flow and D3Q7
+    scalars, 5000 steps: 8 seeds (R 4), 12 bubbles (R uniform in [6, 16]),
+    density ratio 100, gravity -y with Bond number 10 at diameter 22."""
+    c = copy.deepcopy(_BASE)
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n)
+    seeds, bubs = _seeds_and_bubbles(rng, shape, 8, 4.0, 12, 6.0, 16.0,
+                                     seed_gap=min(96.0, n / 3), wall_axis=1)
+    c.update(name=f"coupled3d_{n}", dim=3, nx=n, ny=n, nz=n, phi_q=7,
+             periodic=(True, False, True), eps4=0.02, rho_g=0.01,
+             g=10 * 0.005 / 22.0 ** 2, seeds=seeds, bubbles=bubs, steps=5000,
+             store=store, rng_seed=seed)
+    return c
+
+
+def small(dim=2, nx=12, ny=10, nz=1, fields=FIELDS_ALL, seed=0, periodic=None,
+          **over):
+    """Tiny grids for brute-force parity: one seed and one bubble placed at
+    seeded positions, every other input as in the coupled workload."""
+    c = copy.deepcopy(_BASE)
+    rng = np.random.default_rng(seed)
+    if periodic is None:
+        periodic = (True, False, True)
+    shape = (nx, ny) if dim == 2 else (nx, ny, nz)
+    cen = [rng.uniform(0.3, 0.7) * s for s in shape] + [0.0] * (3 - dim)
+    bc = [rng.uniform(0.1, 0.9) * s for s in shape] + [0.0] * (3 - dim)
+    c.update(name=f"small{dim}d_{nx}x{ny}" + (f"x{nz}" if dim == 3 else ""),
+             dim=dim, nx=nx, ny=ny, nz=nz if dim == 3 else 1,
+             periodic=tuple(periodic), fields=tuple(fields),
+             phi_q=(5 if dim == 2 else 7),
+             seeds=[dict(x=cen[0], y=cen[1], z=cen[2], r=2.5,
+                         angle=float(rng.uniform(0, math.pi / 4)))],
+             bubbles=[dict(x=bc[0], y=bc[1], z=bc[2], r=3.0)] if "phi" in fields else [],
+             steps=20)
+    c.update(over)
+    return c
+
+
+CONFIGS = {
+    "coupled2d_128": coupled2d_128,
+    "alloy2d_1024": alloy2d_1024,
+    "coupled2d_2048": coupled2d_2048,
+    "adjoint2d_512": adjoint2d_512,
+    "adjoint2d_64": adjoint2d_64,
+    "coupled3d_256": coupled3d_256,
+}
+
+
+def get(name, **over):
+    c = CONFIGS[name]()
+    c.update(over)
+    return c
