@@ -1,0 +1,154 @@
+"""Throughput of the fused phase-field LB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--store f64|f32|f16|bf16]
+
+A step is one fused time step of every active field over the whole grid
+(one kernel launch).  Default workload: the isothermal binary-alloy
+dendrite run, 1024 x 1024, four rotated seeds, FP64, timed over K steps after
+W warm-up steps with the inputs resident in HBM.  The same run in FP32 is
+timed beside it.  Prints ONE JSON line with MLUPS, the HBM roofline fraction
+of the step kernel and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="alloy2d_1024")
+    ap.add_argument("--store", default="f64")
+    ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(w, store):
+    """Per node and step: every population read once and written once, every
+    history value read once and written once (no macro-field traffic)."""
+    d = w["dim"]
+    q_ns = 9 if d == 2 else 19
+    q_sc = 5 if d == 2 else 7
+    q = 0
+    nh = 0
+    f = w["fields"]
+    if "ns" in f:
+        q += q_ns
+    if "phi" in f:
+        q += w["phi_q"]
+        nh += d
+    if "psi" in f:
+        q += q_sc
+        nh += 2
+    if "c" in f:
+        q += q_sc
+        nh += d
+    if "theta" in f:
+        q += q_sc
+        nh += d
+    sp = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[store]
+    sh = 8 if store == "f64" else 4
+    return 2 * q * sp + 2 * nh * sh
+
+
+def time_gpu(w, store, steps, warmup):
+    import torch
+    import paper_2407_01651_amd as pfl
+    sim = pfl.Sim(w, store=store)
+    sim.init_fields()
+    sim.step(warmup)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    r = sim.reduce()
+    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
+    mlups = n * steps / (ms * 1e-3) / 1e6
+    bpn = algorithmic_bytes(w, store)
+    gbs = n * bpn / (ms * 1e-3 / steps) / 1e9
+    sim.close()
+    return dict(ms=ms, ms_per_step=ms / steps, mlups=mlups, bytes_per_node=bpn,
+                achieved_gbs=gbs, nonfinite=r["nonfinite"], solid_fraction=r["solid_fraction"])
+
+
+def time_cpu(w, steps):
+    import torch
+    from oracle import OracleParams, OracleSim
+    sim = OracleSim(OracleParams.from_workload(w))
+    sim.init_fields()
+    t = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t
+    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
+    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
+                kind="oracle",
+                sample=f"{w['name']} full grid {w['nx']}x{w['ny']}, {steps} steps from init, "
+                       f"float64 PyTorch CPU, {dt:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads
+    w = workloads.get(a.config)
+    torch.cuda.init()
+    main_run = time_gpu(w, a.store, a.steps, a.warmup)
+    variants = {}
+    for st in [s for s in a.also.split(",") if s and s != a.store]:
+        variants[st] = time_gpu(w, st, a.steps, a.warmup)
+    cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
+    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
+    out = {
+        "metric": "MLUPS (all fields fused)",
+        "value": round(main_run["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}[a.store],
+        "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [w["nx"], w["ny"]] + ([w["nz"]] if w["dim"] == 3 else []),
+                   "fields": list(w["fields"]), "storage": a.store, "nodes": n},
+        "roofline": {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(main_run["achieved_gbs"] / PEAK_HBM_GBS, 4),
+                     "traffic": None,
+                     "bytes_per_node": main_run["bytes_per_node"]},
+        "variants": {k: {"mlups": round(v["mlups"], 2), "ms_per_step": round(v["ms_per_step"], 6),
+                         "achieved_gbs": round(v["achieved_gbs"], 1),
+                         "frac": round(v["achieved_gbs"] / PEAK_HBM_GBS, 4),
+                         "bytes_per_node": v["bytes_per_node"]} for k, v in variants.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * pfl.h - C ABI of the MI355X phase-field lattice Boltzmann step.
+ *
+ * The library advances the coupled system of the paper "Phase-field modeling
+ * of dendritic growth with gas bubbles in the solidification of binary
+ * alloys" (Zhan, Chai, Sun, Shi, Geng, Jiang) one lattice Boltzmann time step
+ * at a time, on one AMD GPU:
+ *   - incompressible Navier-Stokes over gas, liquid and solid with surface
+ *     tension, mass-flux correction, buoyancy and the diffuse-interface
+ *     fluid-solid force (Sec. 2.2);
+ *   - the conservative Allen-Cahn equation for the bubble phase phi
+ *     (Sec. 2.1, anisotropic system, first equation);
+ *   - the anisotropic Allen-Cahn equation for the solid order parameter psi
+ *     with the time-stretched LB scheme of Appendix B;
+ *   - solute C and heat theta convection-diffusion (Sec. 2.1; Appendix B).
+ * All collisions use Lambda = M^-1 S M (Appendix B), written as closed-form
+ * projections onto the relaxed moments.
+ *
+ * Conventions
+ *   - Every function returns 0 (PFL_OK) or a negative error code and never
+ *     throws; pfl_last_error() returns a thread-local message.
+ *   - All device memory is owned by the caller: buffer sizes come from
+ *     pfl_query_sizes(); the library never allocates or frees device memory.
+ *     A pfl_ctx holds host metadata only.
+ *   - Every call enqueues work on the caller's HIP stream (hipStream_t passed
+ *     as void*) and returns without synchronising, except pfl_reduce(), which
+ *     synchronises that stream.
+ *   - Node (x, y, z) has linear index (z * ny + y) * nx + x.  Node-form
+ *     arrays are plane-major: plane p of length n = nx*ny*nz.
+ *   - Velocity ordering (node-form population export/import):
+ *       D2Q5 : (0,0) (1,0) (0,1) (-1,0) (0,-1)
+ *       D2Q9 : D2Q5, then (1,1) (-1,1) (-1,-1) (1,-1)
+ *       D3Q7 : 0, +x, -x, +y, -y, +z, -z
+ *       D3Q19: D3Q7, then (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
+ *              (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *     Population sets are concatenated in the order NS, phi, psi, C, theta
+ *     (inactive sets omitted).  History planes, in order, for active sets:
+ *     psi^{n-1}, S_psi^{n-1} (psi); (phi v)^{n-1} (d planes, phi);
+ *     B_C^{n-1} (d planes, C); (H v)^{n-1} (d planes, theta).
+ */
+#ifndef PFL_H
+#define PFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFL_ABI_VERSION 1
+
+enum {
+  PFL_OK = 0,
+  PFL_E_INVALID_ARG = -1,  /* bad sizes, null pointers, relaxation rate outside (0,2) */
+  PFL_E_UNSUPPORTED = -2,  /* combination the library does not implement           */
+  PFL_E_HIP = -3,          /* a HIP runtime call failed; message carries its string  */
+  PFL_E_NONFINITE = -4,    /* pfl_reduce found NaN/Inf in the state                  */
+  PFL_E_STATE = -5         /* call out of order (e.g. step before init)             */
+};
+
+/* Active equation sets (bit mask). */
+enum { PFL_NS = 1, PFL_PHI = 2, PFL_PSI = 4, PFL_C = 8, PFL_THETA = 16 };
+
+/* Population storage. Compute is FP64 for PFL_F64 and FP32 otherwise. */
+enum { PFL_F64 = 0, PFL_F32 = 1, PFL_F16 = 2, PFL_BF16 = 3 };
+
+/* Macro-field planes written by pfl_get_macros (node form, in this order). */
+enum { PFL_M_PHI = 0, PFL_M_PSI, PFL_M_C, PFL_M_THETA, PFL_M_U, PFL_M_P,
+       PFL_M_VX, PFL_M_VY, PFL_M_VZ, PFL_M_COUNT };
+
+/*
+ * Physical inputs, in lattice units (dx = dt = 1).  The library derives
+ * every other constant from these:
+ *   d_psi = W0^2/tau0;  D = d_psi/PeD (Sec. 3.3, Pe_D = W0^2/(D tau0));
+ *   alpha = Le D;  lambda = 1/(a2 PeD) with a2 = (K + J H)/I from the
+ *   thin-interface constants of Appendix A;  W_phi = xi/(4 sqrt 2) for an
+ *   interface phi = 1/2 + 1/2 tanh(2x/xi);  the surface-tension prefactor
+ *   6 sigma/((phi_l-phi_g)^3 W_phi sqrt(2 beta_phi)) (Sec. 2.2).
+ * Fixed by the paper (Sec. 3): phi_l = 1, phi_g = 0, psi_s = 1, psi_l = -1,
+ * beta_phi = beta_psi = 1/4.
+ */
+typedef struct {
+  uint32_t abi_version;     /* PFL_ABI_VERSION */
+  uint32_t struct_size;     /* sizeof(pfl_params) */
+  int dim;                  /* 2 or 3 */
+  int nx, ny, nz;           /* nz = 1 in 2D */
+  int wall[3];              /* per axis: 0 periodic, 1 half-way bounce-back walls */
+  uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
+  int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
+  int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */
+  double W0, tau0, eps4, k, PeD, Le, Mcinf, U0, theta0;
+  double rho_l, rho_g, nu_l, nu_g, sigma, M_phi, xi, beta_inter, g;
+  double delta_n2;          /* > 0: unit normals g / sqrt(|g|^2 + delta_n2); anisotropy
+                               denominator (|g|^2 + delta_n2)^2 */
+} pfl_params;
+
+/* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */
+typedef struct { double x, y, z, r, angle; } pfl_seed;
+typedef struct { double x, y, z, r; } pfl_bubble;
+
+/* Bytes of each caller-owned device buffer. */
+typedef struct {
+  size_t pops_bytes;        /* one population buffer (two are needed: A and B) */
+  size_t hist_bytes;        /* history planes */
+  size_t aux_bytes;         /* grain map and angle table */
+  size_t macros_bytes;      /* PFL_M_COUNT FP64 planes for pfl_get_macros */
+  size_t state_bytes;       /* node-form FP64 populations + history (get/set_state) */
+  size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce */
+} pfl_sizes;
+
+typedef struct {
+  void *pops_a, *pops_b;    /* pops_bytes each */
+  void *hist;               /* hist_bytes */
+  void *aux;                /* aux_bytes */
+  void *reduce;             /* reduce_bytes */
+} pfl_buffers;
+
+/* Global FP64 diagnostics: sum phi, gas volume sum (phi_l - phi), sum C,
+ * solid fraction mean h(psi), gas centroid, and a NaN/Inf flag. */
+typedef struct {
+  double sum_phi, gas_volume, sum_C, solid_fraction, gas_centroid[3];
+  int nonfinite;
+} pfl_diag;
+
+typedef struct pfl_ctx pfl_ctx;
+
+/* Buffer sizes for these parameters.  Errors: PFL_E_INVALID_ARG,
+ * PFL_E_UNSUPPORTED (see pfl_create). */
+int pfl_query_sizes(const pfl_params* p, pfl_sizes* out);
+
+/* Validate parameters, derive constants, bind caller buffers and a stream.
+ * Errors: PFL_E_INVALID_ARG for bad sizes, null buffers, or a relaxation
+ * rate outside (0, 2) anywhere in the admissible range of the fields;
+ * PFL_E_UNSUPPORTED for isothermal runs with bubbles and solute (F(U) -> 0
+ * in gas), phi on D2Q9 in 3D, BF16/F16 with dim/field combinations not
+ * built, or field combinations not built. */
+int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void* hip_stream);
+
+/* Initial state (Sec. 3.2 bubble profile; Sec. 2.1 psi^eq with W0; solute
+ * C = phi (1 + (1-k) U0)(1 - (1-k) h(psi)); theta = theta0; v = p = 0) and
+ * rest-equilibrium populations.  Seeds and bubbles are copied during the
+ * call.  Each node takes the crystal angle of its nearest seed. */
+int pfl_init_fields(pfl_ctx* c, const pfl_seed* seeds, int nseed,
+                    const pfl_bubble* bubbles, int nbub);
+
+/* Rest-equilibrium populations of given FP64 node-form macro fields on the
+ * device: planes phi, psi, C, theta, v_x, v_y[, v_z] (dev_macros holds
+ * 4 + dim planes).  Seeds give the grain map.  Resets the step counter. */
+int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, const pfl_seed* seeds, int nseed);
+
+/* Advance nsteps time steps: one fused kernel launch per step on the
+ * context's stream.  Errors: PFL_E_STATE before init. */
+int pfl_step(pfl_ctx* c, int nsteps);
+
+/* Macro fields of the current state into dev_out (FP64, PFL_M_COUNT planes,
+ * node form; unused planes are zero).  Errors: PFL_E_STATE before init. */
+int pfl_get_macros(pfl_ctx* c, void* dev_out);
+
+/* Node-form FP64 copy of the pre-collision populations followed by the
+ * history planes (state_bytes), and its inverse.  set_state marks the
+ * history as valid (the next step is not a first step). */
+int pfl_get_state(pfl_ctx* c, double* dev_out);
+int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count);
+
+/* Global FP64 reductions; synchronises the stream.  Returns
+ * PFL_E_NONFINITE (with *out filled) if the state holds NaN/Inf. */
+int pfl_reduce(pfl_ctx* c, pfl_diag* out);
+
+/* Steps taken since the last init. */
+int64_t pfl_step_count(const pfl_ctx* c);
+
+int pfl_destroy(pfl_ctx* c);
+
+/* Thread-local message of the last error ("" if none). */
+const char* pfl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFL_H */

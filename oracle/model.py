@@ -42,9 +42,17 @@ fluid-solid force to other works):
     first step.
   * Time-stretched AAC streaming: linear interpolation in time,
     a_n f(y, n+1) + (1 - a_n) f(y, n) = f*(x).
-  * Normals vanish where |grad|^2 <= delta_n2; there a_s = 1 and N = 0.
+  * Normals n = g/sqrt(|g|^2 + delta_n2) and a_s with the denominator
+    (|g|^2 + delta_n2)^2: smooth where the gradient vanishes (seed centres,
+    far fields), equal to the paper's expressions where |g|^2 >> delta_n2.
   * F(U) = 1/Le + Mc_inf max(1 + (1-k) U, 0); q clamped to [0, 1].
   * Stencil ghosts at walls mirror scalars and negate D_phi (x) v0.
+  * The double-well factor (phi_l - phi)(phi - phi_g) of the sharpening flux
+    and the factor (phi_l - phi) of the vacuum flux are clamped at 0 outside
+    [phi_g, phi_l].
+  * Buoyancy F_b = -(rho - rho_l) g y^: the liquid's hydrostatic head is
+    carried by the pressure, which leaves the incompressible dynamics of
+    Sec. 2.2 unchanged and starts no pressure transient.
 """
 from __future__ import annotations
 
@@ -69,23 +77,25 @@ def anisotropy(g, angle, eps4, delta_n2):
     """a_s(n) and N for the cubic anisotropy of Sec. 3.3 at gradient g.
 
     With g' = R(angle)^T g the gradient in the crystal frame, G = |g'|^2 and
-    S4 = sum g'_a^4: a_s = 1 - 3 eps + 4 eps S4 / G^2 (the Sec. 3.3 formula
-    with n = g'/|g'|), N'_a = |g|^2 a_s d a_s / d g'_a
-    = 16 eps a_s g'_a (g'_a^2 G - S4) / G^2, and N = R N'.  Where
-    |g|^2 <= delta_n2 the normal is undefined: a_s = 1, N = 0.
-    Rotation is about the z axis in 3D.
+    S4 = sum g'_a^4, the Sec. 3.3 function written in g' is
+    a_s = 1 - 3 eps + 4 eps S4 / G^2 = 1 + eps (4 S4 - 3 G^2) / G^2.
+    The direction of a vanishing gradient is undefined, so the denominator
+    is regularised to (G + delta_n2)^2: a_s -> 1 smoothly as |g| -> 0 and
+    equals the paper's function wherever G >> delta_n2.  N is the exact
+    N_a = G a_s d a_s / d g'_a of that function (Sec. 2.1), rotated back:
+    N = R N'.  Rotation is about the z axis in 3D.
     """
-    one = torch.ones_like(g[0])
-    mask = (g * g).sum(0) > delta_n2
     cth, sth = torch.cos(angle), torch.sin(angle)
     gr = g.clone()
     gr[0] = cth * g[0] + sth * g[1]
     gr[1] = -sth * g[0] + cth * g[1]
     G = (gr * gr).sum(0)
     S4 = (gr ** 4).sum(0)
-    Gs = torch.where(mask, G, one)
-    a_s = torch.where(mask, 1 - 3 * eps4 + 4 * eps4 * S4 / (Gs * Gs), one)
-    Nr = torch.where(mask, 16 * eps4 * a_s * gr * (gr * gr * Gs - S4) / (Gs * Gs), 0.0 * gr)
+    Gd = G + delta_n2
+    a_s = 1 + eps4 * (4 * S4 - 3 * G * G) / (Gd * Gd)
+    # d a_s / d g'_a = 4 eps g'_a [4 g'_a^2 G + (4 g'_a^2 - 3 G) delta - 4 S4] / (G + delta)^3
+    da = 4 * eps4 * gr * (4 * gr * gr * G + (4 * gr * gr - 3 * G) * delta_n2 - 4 * S4) / (Gd * Gd * Gd)
+    Nr = G * a_s * da
     N = Nr.clone()
     N[0] = cth * Nr[0] - sth * Nr[1]
     N[1] = sth * Nr[0] + cth * Nr[1]
@@ -470,13 +480,10 @@ class OracleSim:
         lphi = self.lap(phi)
         gpsi = self.grad(psi)
         gU = self.grad(U)
-        # S4 unit normals (normal vanishes where |grad|^2 <= delta_n2)
-        gphi2 = (gphi * gphi).sum(0)
-        mphi = gphi2 > P.delta_n2
-        nphi = torch.where(mphi, gphi / torch.sqrt(torch.where(mphi, gphi2, one)), 0.0 * gphi)
-        gpsi2 = (gpsi * gpsi).sum(0)
-        mpsi = gpsi2 > P.delta_n2
-        epsi = torch.where(mpsi, gpsi / torch.sqrt(torch.where(mpsi, gpsi2, one)), 0.0 * gpsi)
+        # S4 unit normals, regularised where the gradient vanishes:
+        # n = g / sqrt(|g|^2 + delta_n2)
+        nphi = gphi / torch.sqrt((gphi * gphi).sum(0) + P.delta_n2)
+        epsi = gpsi / torch.sqrt((gpsi * gpsi).sum(0) + P.delta_n2)
         # S5 anisotropy in the crystal frame (Sec. 3.3 a_s; Sec. 2.1 N)
         a_s, N = anisotropy(gpsi, self.angle, P.eps4, P.delta_n2)
         # S6 kinetics F(U) (Sec. 2.1, with max(., 0))
@@ -498,7 +505,8 @@ class OracleSim:
         f1p = 2 * BETA_PHI * (PHI_L - phi) * (phi - PHI_G) * (PHI_L + PHI_G - 2 * phi)
         f3phi = -2 * P.beta_inter * (PHI_L - phi) * (psi - PSI_L) ** 2
         mu_phi = f1p + f3phi - P.W_phi ** 2 * lphi
-        sharp = math.sqrt(2 * BETA_PHI) / P.W_phi * (PHI_L - phi) * (phi - PHI_G)
+        # double-well factor of the sharpening flux, zero outside [phi_g, phi_l]
+        sharp = math.sqrt(2 * BETA_PHI) / P.W_phi * torch.clamp((PHI_L - phi) * (phi - PHI_G), min=0.0)
         Dphi = P.M_phi * (gphi - sharp * nphi)
         # S9 density, velocity, forces, pressure
         drho = (P.rho_l - P.rho_g) / (PHI_L - PHI_G)
@@ -513,7 +521,7 @@ class OracleSim:
             j = torch.einsum("ia,i...->a...", Ln.c, fns)
             Fs = P.k_s * mu_phi * gphi
             Fb = torch.zeros_like(gphi)
-            Fb[1] = -rho * P.g
+            Fb[1] = -(rho - P.rho_l) * P.g      # liquid hydrostatic head carried by p
             v0 = (1 - chi) * (j + 0.5 * (Fs + Fb)) / rho
             X = Dphi.unsqueeze(1) * v0.unsqueeze(0)      # X_ab = D_a v0_b
             Fm = drho * self.div_tensor(X)
@@ -607,7 +615,7 @@ class OracleSim:
             psi_prev = q["psi"] if first else st["psi_prev"]
             Jat = -A_AT * P.W0 * q["a_s"] * (1 + (1 - P.k) * q["U"]) * (q["psi"] - psi_prev) * q["epsi"]
             Jv = (P.D * q["qf"] * q["C"] * math.sqrt(2 * BETA_PHI) / P.W_phi
-                  * (PHI_L - q["phi"]) * q["nphi"])
+                  * torch.clamp(PHI_L - q["phi"], min=0.0) * q["nphi"])
             m = 1 - (1 - P.k) * q["h"]
             gh = q["gpsi"] / (PSI_S - PSI_L)
             drift = P.D * q["qf"] * q["C"] * (1 - P.k) * gh / (m * m)

@@ -1,0 +1,226 @@
+"""MI355X phase-field lattice Boltzmann step: Python binding of libpfl.so.
+
+Argument marshalling only.  Every step of the method runs in the HIP
+kernels of ``libpfl.so``; PyTorch provides device memory (caller-owned
+buffers sized by ``pfl_query_sizes``) and the HIP stream.  There is no CPU
+fallback: importing this package without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_01651_amd.build`"
+                      " (or __graft_entry__.build())")
+_lib = ct.CDLL(LIB_PATH)
+
+ABI_VERSION = 1
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
+NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
+F64, F32, F16, BF16 = 0, 1, 2, 3
+STORES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+FIELD_BITS = {"ns": NS, "phi": PHI, "psi": PSI, "c": CONC, "theta": THETA}
+MACROS = ("phi", "psi", "C", "theta", "U", "p", "vx", "vy", "vz")
+
+
+class PflError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pfl error {code}: {msg}")
+        self.code = code
+
+
+class Params(ct.Structure):
+    _fields_ = [("abi_version", ct.c_uint32), ("struct_size", ct.c_uint32),
+                ("dim", ct.c_int), ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
+                ("wall", ct.c_int * 3), ("fields", ct.c_uint32), ("phi_q", ct.c_int), ("store", ct.c_int)] + \
+               [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
+                                          "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
+                                          "beta_inter", "g", "delta_n2")]
+
+
+class Seed(ct.Structure):
+    _fields_ = [(n, ct.c_double) for n in ("x", "y", "z", "r", "angle")]
+
+
+class Bubble(ct.Structure):
+    _fields_ = [(n, ct.c_double) for n in ("x", "y", "z", "r")]
+
+
+class Sizes(ct.Structure):
+    _fields_ = [(n, ct.c_size_t) for n in ("pops_bytes", "hist_bytes", "aux_bytes", "macros_bytes",
+                                          "state_bytes", "reduce_bytes")]
+
+
+class Buffers(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in ("pops_a", "pops_b", "hist", "aux", "reduce")]
+
+
+class Diag(ct.Structure):
+    _fields_ = [("sum_phi", ct.c_double), ("gas_volume", ct.c_double), ("sum_C", ct.c_double),
+                ("solid_fraction", ct.c_double), ("gas_centroid", ct.c_double * 3), ("nonfinite", ct.c_int)]
+
+
+_P = ct.POINTER
+_sig = {
+    "pfl_query_sizes": ([_P(Params), _P(Sizes)], ct.c_int),
+    "pfl_create": ([_P(ct.c_void_p), _P(Params), _P(Buffers), ct.c_void_p], ct.c_int),
+    "pfl_init_fields": ([ct.c_void_p, _P(Seed), ct.c_int, _P(Bubble), ct.c_int], ct.c_int),
+    "pfl_init_from_macros": ([ct.c_void_p, ct.c_void_p, _P(Seed), ct.c_int], ct.c_int),
+    "pfl_step": ([ct.c_void_p, ct.c_int], ct.c_int),
+    "pfl_get_macros": ([ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_get_state": ([ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_set_state": ([ct.c_void_p, ct.c_void_p, ct.c_int64], ct.c_int),
+    "pfl_reduce": ([ct.c_void_p, _P(Diag)], ct.c_int),
+    "pfl_step_count": ([ct.c_void_p], ct.c_int64),
+    "pfl_destroy": ([ct.c_void_p], ct.c_int),
+    "pfl_last_error": ([], ct.c_char_p),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sig)
+
+
+def _check(rc):
+    if rc != OK:
+        raise PflError(rc, _lib.pfl_last_error().decode())
+    return rc
+
+
+def make_params(w, store=None):
+    """pfl_params from a workload description (primary inputs only)."""
+    p = Params()
+    p.abi_version = ABI_VERSION
+    p.struct_size = ct.sizeof(Params)
+    p.dim = w["dim"]
+    p.nx, p.ny, p.nz = w["nx"], w["ny"], (w["nz"] if w["dim"] == 3 else 1)
+    for a in range(3):
+        p.wall[a] = 0 if (a >= w["dim"] or w["periodic"][a]) else 1
+    bits = 0
+    for f in w["fields"]:
+        bits |= FIELD_BITS[f]
+    p.fields = bits
+    p.phi_q = w["phi_q"]
+    p.store = STORES[store or w.get("store", "f64")]
+    for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0", "rho_l", "rho_g",
+              "nu_l", "nu_g", "sigma", "M_phi", "xi", "beta_inter", "g", "delta_n2"):
+        setattr(p, n, float(w[n]))
+    return p
+
+
+def query_sizes(p):
+    s = Sizes()
+    _check(_lib.pfl_query_sizes(ct.byref(p), ct.byref(s)))
+    return s
+
+
+class Sim:
+    """One simulation on one GPU; buffers are torch tensors owned here."""
+
+    def __init__(self, w, store=None, device="cuda:0", stream=None):
+        self.w = w
+        self.device = torch.device(device)
+        self.p = make_params(w, store)
+        self.dim = w["dim"]
+        self.shape = (w["nz"], w["ny"], w["nx"]) if self.dim == 3 else (w["ny"], w["nx"])
+        self.N = w["nx"] * w["ny"] * (w["nz"] if self.dim == 3 else 1)
+        self.sizes = query_sizes(self.p)
+        s = self.sizes
+
+        def buf(n):
+            return torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
+        self.pops_a, self.pops_b = buf(s.pops_bytes), buf(s.pops_bytes)
+        self.hist, self.aux, self.red = buf(s.hist_bytes), buf(s.aux_bytes), buf(s.reduce_bytes)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        b = Buffers(self.pops_a.data_ptr(), self.pops_b.data_ptr(), self.hist.data_ptr(),
+                    self.aux.data_ptr(), self.red.data_ptr())
+        ctx = ct.c_void_p()
+        _check(_lib.pfl_create(ct.byref(ctx), ct.byref(self.p), ct.byref(b), ct.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    # geometry -------------------------------------------------------------
+    def _seeds(self, seeds=None):
+        seeds = self.w["seeds"] if seeds is None else seeds
+        arr = (Seed * max(len(seeds), 1))()
+        for i, s in enumerate(seeds):
+            arr[i] = Seed(s["x"], s["y"], s.get("z", 0.0), s["r"], s.get("angle", 0.0))
+        return arr, len(seeds)
+
+    def init_fields(self, seeds=None, bubbles=None):
+        sa, ns = self._seeds(seeds)
+        bubbles = self.w["bubbles"] if bubbles is None else bubbles
+        ba = (Bubble * max(len(bubbles), 1))()
+        for i, b in enumerate(bubbles):
+            ba[i] = Bubble(b["x"], b["y"], b.get("z", 0.0), b["r"])
+        _check(_lib.pfl_init_fields(self.ctx, sa, ns, ba, len(bubbles)))
+
+    def init_from_macros(self, phi=None, psi=None, C=None, theta=None, v=None, seeds=None):
+        """Rest-equilibrium start from node-form macro fields (CPU or GPU tensors)."""
+        n = 4 + self.dim
+        m = torch.zeros((n,) + self.shape, dtype=torch.float64, device=self.device)
+        m[0] = 1.0
+        m[1] = -1.0
+        m[2] = (1 + (1 - self.w["k"]) * self.w["U0"])
+        m[3] = self.w["theta0"]
+        for i, t in enumerate((phi, psi, C, theta)):
+            if t is not None:
+                m[i] = t.to(self.device, torch.float64)
+        if v is not None:
+            m[4:4 + self.dim] = v.to(self.device, torch.float64)
+        sa, ns = self._seeds(seeds)
+        _check(_lib.pfl_init_from_macros(self.ctx, ct.c_void_p(m.data_ptr()), sa, ns))
+        self._keep = m
+
+    # stepping ---------------------------------------------------------------
+    def step(self, n=1):
+        _check(_lib.pfl_step(self.ctx, int(n)))
+
+    @property
+    def steps(self):
+        return int(_lib.pfl_step_count(self.ctx))
+
+    def macros(self):
+        out = torch.empty((len(MACROS),) + self.shape, dtype=torch.float64, device=self.device)
+        _check(_lib.pfl_get_macros(self.ctx, ct.c_void_p(out.data_ptr())))
+        return {k: out[i] for i, k in enumerate(MACROS)}
+
+    def get_state(self):
+        nplanes = self.sizes.state_bytes // (8 * self.N)
+        out = torch.empty((nplanes,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(_lib.pfl_get_state(self.ctx, ct.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, state, step_count=0):
+        st = state.to(self.device, torch.float64).contiguous()
+        _check(_lib.pfl_set_state(self.ctx, ct.c_void_p(st.data_ptr()), int(step_count)))
+        self._keep = st
+
+    def reduce(self):
+        d = Diag()
+        rc = _lib.pfl_reduce(self.ctx, ct.byref(d))
+        out = dict(sum_phi=d.sum_phi, gas_volume=d.gas_volume, sum_C=d.sum_C,
+                   solid_fraction=d.solid_fraction, gas_centroid=list(d.gas_centroid),
+                   nonfinite=d.nonfinite)
+        if rc not in (OK, E_NONFINITE):
+            _check(rc)
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.pfl_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,54 @@
+"""Build libpfl.so (all HIP sources, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_aux.hip"]
+OUT = os.path.join(HERE, "libpfl.so")
+
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-shared",
+    "-ffp-contract=off",
+    # packed FP32 instructions disabled
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result",
+]
+
+
+def build(verbose=False, jobs=None):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objs = []
+    procs = []
+    for s in SRC:
+        obj = os.path.join(HERE, "csrc", s.replace(".hip", ".o"))
+        cmd = [hipcc, "-c", os.path.join(HERE, "csrc", s), "-o", obj] + [f for f in FLAGS if f != "-shared"] + inc
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    err = False
+    for s, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            err = True
+            sys.stderr.write(f"--- {s} failed ---\n" + out.decode(errors="replace"))
+        elif verbose and out:
+            sys.stderr.write(out.decode(errors="replace"))
+    if err:
+        raise RuntimeError("hipcc failed")
+    tmp = OUT + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, OUT)
+    for o in objs:
+        os.remove(o)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

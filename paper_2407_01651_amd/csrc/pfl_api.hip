@@ -1,0 +1,390 @@
+// Host side of the C ABI declared in include/pfl.h: parameter validation,
+// derived constants, buffer layout, launch sequencing and error reporting.
+#include "pfl.h"
+#include "pfl_kernels.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace pfl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PFL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Layout {
+  int q_ns, q_phi, q_sc;
+  int n_pop_planes, n_hist_planes;
+  int o_ns, o_phi, o_psi, o_c, o_th;
+  int h_psi, h_S, h_phiv, h_B, h_Hv;
+  size_t elem, helem;
+  long long N;
+  size_t pops_bytes, hist_bytes, aux_bytes, macros_bytes, state_bytes, reduce_bytes;
+  size_t aux_cs, aux_seeds, aux_bub;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int validate(const pfl_params* p) {
+  if (!p) return fail(PFL_E_INVALID_ARG, "null parameters");
+  if (p->abi_version != PFL_ABI_VERSION || p->struct_size != sizeof(pfl_params))
+    return fail(PFL_E_INVALID_ARG, "parameter struct version/size mismatch");
+  if (p->dim != 2 && p->dim != 3) return fail(PFL_E_INVALID_ARG, "dim must be 2 or 3");
+  if (p->nx < 4 || p->ny < 4) return fail(PFL_E_INVALID_ARG, "nx and ny must be >= 4");
+  if (p->dim == 2 && p->nz != 1) return fail(PFL_E_INVALID_ARG, "nz must be 1 in 2D");
+  if (p->dim == 3 && p->nz < 4) return fail(PFL_E_INVALID_ARG, "nz must be >= 4 in 3D");
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 31))
+    return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
+  for (int a = 0; a < 3; ++a)
+    if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PFL_E_INVALID_ARG, "wall flags must be 0 or 1");
+  const uint32_t f = p->fields;
+  if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
+  if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");
+  if (p->dim == 3 && p->phi_q == 9) return fail(PFL_E_UNSUPPORTED, "phi on a 9-velocity lattice is 2D only");
+  if (p->dim == 3 && p->phi_q != 7) return fail(PFL_E_INVALID_ARG, "phi_q must be 7 in 3D");
+  if (p->store < PFL_F64 || p->store > PFL_BF16) return fail(PFL_E_INVALID_ARG, "bad storage type");
+  if (p->dim == 3) return fail(PFL_E_UNSUPPORTED, "3D step not built");
+  if (!step2d_supported((int)f)) return fail(PFL_E_UNSUPPORTED, "field combination not built");
+  if ((f & PFL_PHI) && (f & PFL_C) && !(f & PFL_THETA))
+    return fail(PFL_E_UNSUPPORTED, "isothermal runs with bubbles and solute: F(U) vanishes in gas");
+  if (!(p->W0 > 0) || !(p->tau0 > 0) || !(p->PeD > 0))
+    return fail(PFL_E_INVALID_ARG, "W0, tau0 and PeD must be positive (relaxation rates in (0,2))");
+  if (!(p->k > 0 && p->k < 1)) return fail(PFL_E_INVALID_ARG, "partition coefficient must lie in (0,1)");
+  if ((f & PFL_THETA) && !(p->Le > 0)) return fail(PFL_E_INVALID_ARG, "Le must be positive");
+  if ((f & PFL_THETA) && std::isinf(p->Le)) return fail(PFL_E_INVALID_ARG, "Le must be finite when heat is solved");
+  if (!(p->Mcinf >= 0)) return fail(PFL_E_INVALID_ARG, "Mcinf must be >= 0");
+  if (!(p->xi > 0) || !(p->M_phi > 0)) return fail(PFL_E_INVALID_ARG, "xi and M_phi must be positive");
+  if (!(p->rho_l > 0) || !(p->rho_g > 0)) return fail(PFL_E_INVALID_ARG, "densities must be positive");
+  if (!(p->nu_l > 0) || !(p->nu_g > 0)) return fail(PFL_E_INVALID_ARG, "viscosities must be positive (relaxation rate in (0,2))");
+  if (!(p->sigma >= 0) || !(p->beta_inter >= 0))
+    return fail(PFL_E_INVALID_ARG, "sigma and beta_inter must be >= 0");
+  if (!(p->delta_n2 > 0) || !std::isfinite(p->delta_n2))
+    return fail(PFL_E_INVALID_ARG, "delta_n2 must be positive (regularisation of unit normals)");
+  if (!std::isfinite(p->U0) || !std::isfinite(p->theta0) || !std::isfinite(p->eps4) || !std::isfinite(p->g))
+    return fail(PFL_E_INVALID_ARG, "non-finite parameter");
+  if (!(p->eps4 >= 0 && p->eps4 < 1.0 / 3)) return fail(PFL_E_INVALID_ARG, "eps4 must lie in [0, 1/3)");
+  return PFL_OK;
+}
+
+Layout layout(const pfl_params* p) {
+  Layout L{};
+  const uint32_t f = p->fields;
+  L.N = (long long)p->nx * p->ny * p->nz;
+  L.q_ns = p->dim == 2 ? 9 : 19;
+  L.q_phi = p->phi_q;
+  L.q_sc = p->dim == 2 ? 5 : 7;
+  int o = 0;
+  L.o_ns = (f & PFL_NS) ? (o += 0, o) : -1; if (f & PFL_NS) o += L.q_ns;
+  L.o_phi = (f & PFL_PHI) ? o : -1; if (f & PFL_PHI) o += L.q_phi;
+  L.o_psi = (f & PFL_PSI) ? o : -1; if (f & PFL_PSI) o += L.q_sc;
+  L.o_c = (f & PFL_C) ? o : -1; if (f & PFL_C) o += L.q_sc;
+  L.o_th = (f & PFL_THETA) ? o : -1; if (f & PFL_THETA) o += L.q_sc;
+  L.n_pop_planes = o;
+  int h = 0;
+  L.h_psi = (f & PFL_PSI) ? h : -1; if (f & PFL_PSI) h += 1;
+  L.h_S = (f & PFL_PSI) ? h : -1; if (f & PFL_PSI) h += 1;
+  L.h_phiv = (f & PFL_PHI) ? h : -1; if (f & PFL_PHI) h += p->dim;
+  L.h_B = (f & PFL_C) ? h : -1; if (f & PFL_C) h += p->dim;
+  L.h_Hv = (f & PFL_THETA) ? h : -1; if (f & PFL_THETA) h += p->dim;
+  L.n_hist_planes = h;
+  L.elem = p->store == PFL_F64 ? 8 : (p->store == PFL_F32 ? 4 : 2);
+  L.helem = p->store == PFL_F64 ? 8 : 4;
+  L.pops_bytes = round_up((size_t)L.n_pop_planes * L.N * L.elem, 256);
+  L.hist_bytes = round_up((size_t)std::max(L.n_hist_planes, 1) * L.N * L.helem, 256);
+  L.aux_cs = round_up((size_t)L.N, 256);
+  L.aux_seeds = L.aux_cs + sizeof(double) * 2 * MAX_SEEDS;
+  L.aux_bub = L.aux_seeds + sizeof(double) * 5 * MAX_SEEDS;
+  L.aux_bytes = round_up(L.aux_bub + sizeof(double) * 4 * MAX_BUBBLES, 256);
+  L.macros_bytes = (size_t)PFL_M_COUNT * L.N * sizeof(double);
+  L.state_bytes = (size_t)(L.n_pop_planes + L.n_hist_planes) * L.N * sizeof(double);
+  L.reduce_bytes = (size_t)(RED_BLOCKS + 1) * RED_VALS * sizeof(double);
+  return L;
+}
+
+// Thin-interface constants of Appendix A for beta_psi = 1/4, psi_s - psi_l = 2:
+// I = sqrt(2 beta) (psi_s - psi_l)^3 / 6, J = 1, H = ln 2 / (sqrt(2 beta) dpsi),
+// K = (47/60 - ln 2) / (sqrt(2 beta) dpsi);  a2 = (K + J H) / I.
+double a2_const() {
+  const double r = std::sqrt(0.5), dpsi = 2.0;
+  const double I = r / 6.0 * dpsi * dpsi * dpsi;
+  const double H = std::log(2.0) / (r * dpsi);
+  const double K = (47.0 / 60.0 - std::log(2.0)) / (r * dpsi);
+  return (K + H) / I;
+}
+
+}  // namespace
+
+struct pfl_ctx {
+  pfl_params p;
+  Layout L;
+  DevParams d;
+  pfl_buffers b;
+  hipStream_t s;
+  int cur;               // 0: state in pops_a, 1: in pops_b
+  bool inited;
+  int64_t steps;
+  std::vector<double> cs, seeds, bubbles;   // host copies kept alive for async uploads
+};
+
+extern "C" {
+
+const char* pfl_last_error(void) { return g_err.c_str(); }
+
+int pfl_query_sizes(const pfl_params* p, pfl_sizes* out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return fail(PFL_E_INVALID_ARG, "null output");
+  const Layout L = layout(p);
+  out->pops_bytes = L.pops_bytes;
+  out->hist_bytes = L.hist_bytes;
+  out->aux_bytes = L.aux_bytes;
+  out->macros_bytes = L.macros_bytes;
+  out->state_bytes = L.state_bytes;
+  out->reduce_bytes = L.reduce_bytes;
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void* hip_stream) {
+  if (!out) return fail(PFL_E_INVALID_ARG, "null context pointer");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bufs || !bufs->pops_a || !bufs->pops_b || !bufs->hist || !bufs->aux || !bufs->reduce)
+    return fail(PFL_E_INVALID_ARG, "null device buffer");
+  if (bufs->pops_a == bufs->pops_b) return fail(PFL_E_INVALID_ARG, "pops_a and pops_b must differ");
+  pfl_ctx* c = new pfl_ctx();
+  c->p = *p;
+  c->L = layout(p);
+  c->b = *bufs;
+  c->s = (hipStream_t)hip_stream;
+  c->cur = 0;
+  c->inited = false;
+  c->steps = 0;
+  const Layout& L = c->L;
+  DevParams& d = c->d;
+  std::memset(&d, 0, sizeof(d));
+  d.nx = p->nx; d.ny = p->ny; d.nz = p->nz; d.dim = p->dim;
+  for (int a = 0; a < 3; ++a) d.wall[a] = p->wall[a];
+  d.N = L.N;
+  d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;
+  d.q_ns = L.q_ns; d.q_phi = L.q_phi; d.q_sc = L.q_sc;
+  d.h_psi = L.h_psi; d.h_S = L.h_S; d.h_phiv = L.h_phiv; d.h_B = L.h_B; d.h_Hv = L.h_Hv;
+  d.first = 1;
+  const bool th = p->fields & PFL_THETA;
+  const double cs2_sc = p->dim == 2 ? 1.0 / 3 : 0.25;
+  const double cs2_phi = p->dim == 2 ? 1.0 / 3 : 0.25;
+  d.W0 = p->W0; d.tau0 = p->tau0;
+  d.d_psi = p->W0 * p->W0 / p->tau0;
+  d.eps4 = p->eps4; d.k = p->k;
+  d.D = d.d_psi / p->PeD;
+  d.inv_Le = th ? 1.0 / p->Le : 0.0;
+  d.alpha = th ? p->Le * d.D : 0.0;
+  d.Mcinf = p->Mcinf;
+  d.lam = 1.0 / (a2_const() * p->PeD);
+  d.U0 = p->U0; d.theta0 = p->theta0;
+  d.rho_l = p->rho_l; d.rho_g = p->rho_g; d.drho = p->rho_l - p->rho_g;
+  d.mu_l = p->rho_l * p->nu_l; d.mu_g = p->rho_g * p->nu_g;
+  d.W_phi = p->xi / (4.0 * std::sqrt(2.0));
+  d.sharp = std::sqrt(0.5) / d.W_phi;
+  d.k_s = 6.0 * p->sigma / (d.W_phi * std::sqrt(0.5));
+  d.M_phi = p->M_phi; d.beta_inter = p->beta_inter; d.g = p->g;
+  d.delta_n2 = p->delta_n2;
+  d.s_phi = 1.0 / (p->M_phi / cs2_phi + 0.5);
+  d.s_th = th ? 1.0 / (d.alpha / cs2_sc + 0.5) : 1.0;
+  d.a_at = 1.0 / (2.0 * std::sqrt(2.0));
+  d.phi_tanh = std::sqrt(0.5) / (2.0 * d.W_phi);
+  d.psi_tanh = 2.0 * std::sqrt(0.5) / (2.0 * p->W0);
+  uint8_t* aux = (uint8_t*)bufs->aux;
+  d.grain = aux;
+  d.grain_cs = (const double*)(aux + L.aux_cs);
+  d.seeds = (const double*)(aux + L.aux_seeds);
+  d.bubbles = (const double*)(aux + L.aux_bub);
+  // deviation-storage references: rest equilibria of the bulk liquid
+  // (phi = 1, psi = -1, C = 1 + (1-k) U0, theta = theta0, v = p = 0)
+  const double w2_5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  const double w2_9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const bool lowp = p->store == PFL_F16 || p->store == PFL_BF16;
+  if (lowp) {
+    const double* wsc = w2_5;
+    const double* wph = p->phi_q == 9 ? w2_9 : w2_5;
+    const double Cref = 1.0 + (1.0 - p->k) * p->U0;
+    for (int i = 0; i < L.q_ns; ++i) d.ref_ns[i] = 0.0f;
+    for (int i = 0; i < L.q_phi; ++i) d.ref_phi[i] = (float)wph[i];
+    for (int i = 0; i < L.q_sc; ++i) {
+      d.ref_psi[i] = (float)(-wsc[i]);
+      d.ref_c[i] = (float)(wsc[i] * Cref);
+      d.ref_th[i] = (float)(wsc[i] * p->theta0);
+    }
+    d.ref_th[0] = (float)(p->theta0 + (wsc[0] - 1.0) * p->theta0);
+  }
+  *out = c;
+  g_err.clear();
+  return PFL_OK;
+}
+
+static int upload_geometry(pfl_ctx* c, const pfl_seed* seeds, int nseed, const pfl_bubble* bubbles, int nbub) {
+  if (nseed < 0 || nseed > MAX_SEEDS || nbub < 0 || nbub > MAX_BUBBLES)
+    return fail(PFL_E_INVALID_ARG, "too many seeds or bubbles");
+  if ((nseed && !seeds) || (nbub && !bubbles)) return fail(PFL_E_INVALID_ARG, "null seed/bubble array");
+  c->cs.assign(2 * MAX_SEEDS, 0.0);
+  c->seeds.assign(5 * MAX_SEEDS, 0.0);
+  c->bubbles.assign(4 * MAX_BUBBLES, 0.0);
+  c->cs[0] = 1.0;
+  for (int i = 0; i < nseed; ++i) {
+    const pfl_seed& s = seeds[i];
+    if (!std::isfinite(s.x) || !std::isfinite(s.y) || !std::isfinite(s.z) || !(s.r >= 0) || !std::isfinite(s.angle))
+      return fail(PFL_E_INVALID_ARG, "bad seed");
+    c->seeds[5 * i + 0] = s.x; c->seeds[5 * i + 1] = s.y; c->seeds[5 * i + 2] = s.z;
+    c->seeds[5 * i + 3] = s.r; c->seeds[5 * i + 4] = s.angle;
+    c->cs[2 * i] = std::cos(s.angle);
+    c->cs[2 * i + 1] = std::sin(s.angle);
+  }
+  for (int i = 0; i < nbub; ++i) {
+    const pfl_bubble& b = bubbles[i];
+    if (!std::isfinite(b.x) || !std::isfinite(b.y) || !std::isfinite(b.z) || !(b.r >= 0))
+      return fail(PFL_E_INVALID_ARG, "bad bubble");
+    c->bubbles[4 * i + 0] = b.x; c->bubbles[4 * i + 1] = b.y; c->bubbles[4 * i + 2] = b.z;
+    c->bubbles[4 * i + 3] = b.r;
+  }
+  c->d.nseed = nseed;
+  c->d.nbub = nbub;
+  hipError_t e;
+  e = hipMemcpyAsync((void*)c->d.grain_cs, c->cs.data(), c->cs.size() * sizeof(double), hipMemcpyHostToDevice, c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(angles)");
+  e = hipMemcpyAsync((void*)c->d.seeds, c->seeds.data(), c->seeds.size() * sizeof(double), hipMemcpyHostToDevice, c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(seeds)");
+  e = hipMemcpyAsync((void*)c->d.bubbles, c->bubbles.data(), c->bubbles.size() * sizeof(double), hipMemcpyHostToDevice, c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(bubbles)");
+  return PFL_OK;
+}
+
+int pfl_init_fields(pfl_ctx* c, const pfl_seed* seeds, int nseed, const pfl_bubble* bubbles, int nbub) {
+  if (!c) return fail(PFL_E_INVALID_ARG, "null context");
+  if ((c->p.fields & PFL_PHI) && (c->p.fields & PFL_C) && !(c->p.fields & PFL_THETA) && nbub > 0)
+    return fail(PFL_E_UNSUPPORTED, "isothermal runs with bubbles: F(U) vanishes in gas");
+  int rc = upload_geometry(c, seeds, nseed, bubbles, nbub);
+  if (rc) return rc;
+  c->cur = 0;
+  hipError_t e = launch_init(c->d, (int)c->p.fields, c->p.store, 0, nullptr, c->b.pops_a, c->b.hist,
+                             (uint8_t*)c->d.grain, c->s);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  c->d.first = 1;
+  c->steps = 0;
+  c->inited = true;
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, const pfl_seed* seeds, int nseed) {
+  if (!c || !dev_macros) return fail(PFL_E_INVALID_ARG, "null argument");
+  int rc = upload_geometry(c, seeds, nseed, nullptr, 0);
+  if (rc) return rc;
+  c->cur = 0;
+  hipError_t e = launch_init(c->d, (int)c->p.fields, c->p.store, 1, dev_macros, c->b.pops_a, c->b.hist,
+                             (uint8_t*)c->d.grain, c->s);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  c->d.first = 1;
+  c->steps = 0;
+  c->inited = true;
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_step(pfl_ctx* c, int nsteps) {
+  if (!c) return fail(PFL_E_INVALID_ARG, "null context");
+  if (!c->inited) return fail(PFL_E_STATE, "step before init");
+  if (nsteps < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  for (int n = 0; n < nsteps; ++n) {
+    void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+    void* fout = c->cur == 0 ? c->b.pops_b : c->b.pops_a;
+    bool ok = true;
+    hipError_t e = launch_step2d(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
+    if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+    c->cur ^= 1;
+    c->d.first = 0;
+    c->steps++;
+  }
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_get_macros(pfl_ctx* c, void* dev_out) {
+  if (!c || !dev_out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "get_macros before init");
+  void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  bool ok = true;
+  hipError_t e = launch_step2d(c->d, (int)c->p.fields, c->p.store, fin, nullptr, c->b.hist, (double*)dev_out, 1, c->s, ok);
+  if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
+  if (e != hipSuccess) return hip_fail(e, "macros kernel");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_get_state(pfl_ctx* c, double* dev_out) {
+  if (!c || !dev_out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "get_state before init");
+  const void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  hipError_t e = launch_get_state(c->d, (int)c->p.fields, c->p.store, pops, c->b.hist, dev_out, c->s);
+  if (e != hipSuccess) return hip_fail(e, "state export kernel");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count) {
+  if (!c || !dev_in) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "set_state before init (the grain map comes from init)");
+  if (step_count < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  hipError_t e = launch_set_state(c->d, (int)c->p.fields, c->p.store, dev_in, pops, c->b.hist, c->s);
+  if (e != hipSuccess) return hip_fail(e, "state import kernel");
+  c->d.first = 0;
+  c->steps = step_count;
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_reduce(pfl_ctx* c, pfl_diag* out) {
+  if (!c || !out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "reduce before init");
+  const void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  double* red = (double*)c->b.reduce;
+  hipError_t e = launch_reduce(c->d, (int)c->p.fields, c->p.store, pops, c->b.hist, c->L.n_hist_planes, red, c->s);
+  if (e != hipSuccess) return hip_fail(e, "reduce kernel");
+  double v[RED_VALS];
+  e = hipMemcpyAsync(v, red + (size_t)RED_BLOCKS * RED_VALS, sizeof(v), hipMemcpyDeviceToHost, c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(reduce)");
+  e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  out->sum_phi = v[0];
+  out->gas_volume = v[1];
+  out->sum_C = v[2];
+  out->solid_fraction = v[3] / (double)c->L.N;
+  for (int a = 0; a < 3; ++a) out->gas_centroid[a] = v[1] > 0 ? v[4 + a] / v[1] : 0.0;
+  out->nonfinite = v[7] != 0.0 || !std::isfinite(v[0]) || !std::isfinite(v[2]);
+  if (out->nonfinite) return fail(PFL_E_NONFINITE, "non-finite values in the state");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int64_t pfl_step_count(const pfl_ctx* c) { return c ? c->steps : -1; }
+
+int pfl_destroy(pfl_ctx* c) {
+  delete c;
+  return PFL_OK;
+}
+
+}  // extern "C"

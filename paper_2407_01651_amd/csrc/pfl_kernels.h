@@ -1,0 +1,31 @@
+// Launchers of the device kernels, called by the host C ABI.
+#pragma once
+#include "pfl_dev.h"
+
+namespace pfl {
+
+// mode 0: one time step fin -> fout (history updated in place);
+// mode 1: macro fields of fin into mout (no population or history writes).
+hipError_t launch_step2d(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                         void* hist, double* mout, int mode, hipStream_t s, bool& ok);
+bool step2d_supported(int fields);
+
+// Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
+// planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium
+// populations into pops (pull storage) and zero history.
+hipError_t launch_init(const DevParams& P, int fields, int store, int mode, const double* macros,
+                       void* pops, void* hist, uint8_t* grain, hipStream_t s);
+
+// Node-form FP64 export / import of populations followed by history.
+hipError_t launch_get_state(const DevParams& P, int fields, int store, const void* pops,
+                            const void* hist, double* out, hipStream_t s);
+hipError_t launch_set_state(const DevParams& P, int fields, int store, const double* in, void* pops,
+                            void* hist, hipStream_t s);
+
+// Two-stage deterministic FP64 reduction into red[RED_BLOCKS * 8 .. +8].
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_VALS = 8;
+hipError_t launch_reduce(const DevParams& P, int fields, int store, const void* pops,
+                         const void* hist, int hist_planes, double* red, hipStream_t s);
+
+}  // namespace pfl

@@ -1,0 +1,624 @@
+// Fused 2D time step: one launch advances every active population set by
+// one step (pull streaming, moments, isotropic stencils, anisotropy,
+// forces, MRT collisions in closed form, time-stretched AAC store, history).
+//
+// Work decomposition: a 256-thread workgroup owns a TX x TY tile of nodes,
+// one node per thread.  Moments of the tile plus a halo of R rings
+// (R = 2 when the flow and bubble phase are both active, else 1) are staged
+// in LDS; the flow phase then evaluates D_phi (x) v0 on the tile plus one
+// ring (LDS), and each thread finishes its own node from registers and LDS.
+// Populations live in SoA planes (x fastest), post-collision at their source
+// node, so a node pulls f_i(x) from x - c_i; a population that would cross a
+// wall is read back from the node's own opposite slot (half-way bounce-back).
+#include "pfl_kernels.h"
+
+namespace pfl {
+
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+
+template <class CT>
+__device__ __forceinline__ CT clamp01(CT v) { return v < CT(0) ? CT(0) : (v > CT(1) ? CT(1) : v); }
+
+// Map a (possibly out-of-domain) coordinate to the node whose value it
+// holds: periodic wrap, or mirror across a half-way wall (clamped so that
+// positions no valid node needs stay in range).
+__device__ __forceinline__ int map_coord(int g, int n, int wall, bool& ghost) {
+  ghost = false;
+  if (g >= 0 && g < n) return g;
+  if (!wall) { g %= n; if (g < 0) g += n; return g; }
+  ghost = true;
+  g = g < 0 ? -1 - g : 2 * n - 1 - g;
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
+// Pull the pre-collision populations of one set at node (x, y).
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull2d(const typename Store<ST>::raw* __restrict__ base,
+                                       const DevParams& P, const float* ref, int x, int y,
+                                       CT f[Q]) {
+  using L = Lat<Q>;
+  const long long N = P.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int sx = x - L::c[i][0], sy = y - L::c[i][1];
+    bool bounce = false;
+    if (sx < 0) { if (P.wall[0]) bounce = true; else sx += P.nx; }
+    else if (sx >= P.nx) { if (P.wall[0]) bounce = true; else sx -= P.nx; }
+    if (sy < 0) { if (P.wall[1]) bounce = true; else sy += P.ny; }
+    else if (sy >= P.ny) { if (P.wall[1]) bounce = true; else sy -= P.ny; }
+    long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
+    int plane = bounce ? L::opp[i] : i;
+    f[i] = Store<ST>::template ld<CT>(base + plane * N + idx, ref[plane]);
+  }
+}
+
+// Isotropic D2Q9 gradient and Laplacian from an LDS array.
+template <class CT, int RX>
+__device__ __forceinline__ void grad9(const CT (*s)[RX], int ry, int rx, CT& gx, CT& gy) {
+  const CT e = s[ry][rx + 1], wv = s[ry][rx - 1], n = s[ry + 1][rx], so = s[ry - 1][rx];
+  const CT ne = s[ry + 1][rx + 1], nw = s[ry + 1][rx - 1], sw = s[ry - 1][rx - 1], se = s[ry - 1][rx + 1];
+  gx = CT(3) * (CT(1.0 / 9) * (e - wv) + CT(1.0 / 36) * ((ne - nw) + (se - sw)));
+  gy = CT(3) * (CT(1.0 / 9) * (n - so) + CT(1.0 / 36) * ((ne + nw) - (sw + se)));
+}
+template <class CT, int RX>
+__device__ __forceinline__ CT lap9(const CT (*s)[RX], int ry, int rx) {
+  const CT c = s[ry][rx];
+  const CT ax = (s[ry][rx + 1] - c) + (s[ry][rx - 1] - c) + (s[ry + 1][rx] - c) + (s[ry - 1][rx] - c);
+  const CT dg = (s[ry + 1][rx + 1] - c) + (s[ry + 1][rx - 1] - c) + (s[ry - 1][rx - 1] - c) + (s[ry - 1][rx + 1] - c);
+  return CT(6) * (CT(1.0 / 9) * ax + CT(1.0 / 36) * dg);
+}
+
+// Flow quantities at one LDS position (node or ring 1): chemical potential,
+// surface tension, phi diffusion flux, velocity without the mass-flux force.
+template <class CT, int RX>
+struct FlowNode {
+  CT gx, gy, lap, nx, ny, Fsx, Fsy, Dx, Dy, rho, chi, v0x, v0y, sharp;
+};
+
+template <bool NS, bool PHI, class CT, int RX, class JA>
+__device__ __forceinline__ void flow_node(const DevParams& P, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
+                                          const JA& s_jx, const JA& s_jy, int ry, int rx,
+                                          FlowNode<CT, RX>& o) {
+  const CT phi = s_phi[ry][rx];
+  const CT psi = s_psi[ry][rx];
+  if constexpr (PHI) {
+    grad9<CT, RX>(s_phi, ry, rx, o.gx, o.gy);
+    o.lap = lap9<CT, RX>(s_phi, ry, rx);
+  } else {
+    o.gx = o.gy = o.lap = CT(0);
+  }
+  // unit normal, regularised where the gradient vanishes
+  const CT inv = CT(1) / sqrt(o.gx * o.gx + o.gy * o.gy + CT(P.delta_n2));
+  o.nx = o.gx * inv;
+  o.ny = o.gy * inv;
+  // phi_l = 1, phi_g = 0, psi_l = -1, beta_phi = 1/4
+  const CT one_m = CT(1) - phi;
+  // double-well factor of the sharpening flux, zero outside [phi_g, phi_l]
+  const CT dw = one_m * phi;
+  o.sharp = CT(P.sharp) * (dw > CT(0) ? dw : CT(0));
+  o.Dx = CT(P.M_phi) * (o.gx - o.sharp * o.nx);
+  o.Dy = CT(P.M_phi) * (o.gy - o.sharp * o.ny);
+  const CT h = (psi + CT(1)) * CT(0.5);
+  o.chi = clamp01(h);
+  o.rho = CT(P.rho_g) + CT(P.drho) * phi;
+  if constexpr (NS) {
+    const CT f1p = CT(0.5) * one_m * phi * (CT(1) - CT(2) * phi);
+    const CT ps1 = psi + CT(1);
+    const CT f3p = CT(-2) * CT(P.beta_inter) * one_m * ps1 * ps1;
+    const CT mu = f1p + f3p - CT(P.W_phi * P.W_phi) * o.lap;
+    o.Fsx = CT(P.k_s) * mu * o.gx;
+    o.Fsy = CT(P.k_s) * mu * o.gy;
+    // buoyancy relative to the liquid: its hydrostatic head is carried by p
+    const CT Fbx = CT(0), Fby = -(o.rho - CT(P.rho_l)) * CT(P.g);
+    const CT s = (CT(1) - o.chi) / o.rho;
+    o.v0x = s * (s_jx[ry][rx] + CT(0.5) * (o.Fsx + Fbx));
+    o.v0y = s * (s_jy[ry][rx] + CT(0.5) * (o.Fsy + Fby));
+  } else {
+    o.Fsx = o.Fsy = o.v0x = o.v0y = CT(0);
+  }
+}
+
+template <int FIELDS, int QP, class ST, class HT, class CT>
+__global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
+                                                    const typename Store<ST>::raw* __restrict__ fin,
+                                                    typename Store<ST>::raw* __restrict__ fout,
+                                                    HT* __restrict__ hist, double* __restrict__ mout,
+                                                    int mode) {
+  constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
+  constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
+  constexpr bool FLOWX = NS && PHI;          // mass-flux force needs D_phi (x) v0 on ring 1
+  constexpr int R = FLOWX ? 2 : 1;
+  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  constexpr int QN = 9, QS = 5;
+  using LN = Lat<9>;
+  using LS = Lat<5>;
+  using LP = Lat<QP>;
+  using raw = typename Store<ST>::raw;
+
+  __shared__ CT s_phi[RY][RX];
+  __shared__ CT s_psi[RY][RX];
+  __shared__ CT s_U[RY][RX];
+  __shared__ CT s_jx[NS ? RY : 1][NS ? RX : 1];
+  __shared__ CT s_jy[NS ? RY : 1][NS ? RX : 1];
+  __shared__ CT s_X[FLOWX ? 4 : 1][FLOWX ? RY : 1][FLOWX ? RX : 1];
+
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  const int x = bx0 + lx, y = by0 + ly;
+  const bool own = (x < P.nx) && (y < P.ny);
+  const long long N = P.N;
+  const long long idx = (long long)y * P.nx + x;
+
+  const raw* fin_ns = fin + (long long)(NS ? P.o_ns : 0) * N;
+  const raw* fin_phi = fin + (long long)(PHI ? P.o_phi : 0) * N;
+  const raw* fin_psi = fin + (long long)(PSI ? P.o_psi : 0) * N;
+  const raw* fin_c = fin + (long long)(CC ? P.o_c : 0) * N;
+  const raw* fin_th = fin + (long long)(TH ? P.o_th : 0) * N;
+
+  const CT k1 = CT(1) - CT(P.k);
+
+  // ---- phase A1: own node populations and moments
+  CT fns[NS ? QN : 1], fph[PHI ? QP : 1], fps[PSI ? QS : 1], fc[CC ? QS : 1], fth[TH ? QS : 1];
+  CT phi = CT(1), psi = CT(-1), C = CT(0), H = CT(0), U = CT(P.U0), jx = CT(0), jy = CT(0);
+  if (own) {
+    if constexpr (NS) {
+      pull2d<QN, ST, CT>(fin_ns, P, P.ref_ns, x, y, fns);
+#pragma unroll
+      for (int i = 0; i < QN; ++i) { jx += CT(LN::c[i][0]) * fns[i]; jy += CT(LN::c[i][1]) * fns[i]; }
+    }
+    if constexpr (PHI) {
+      pull2d<QP, ST, CT>(fin_phi, P, P.ref_phi, x, y, fph);
+      phi = CT(0);
+#pragma unroll
+      for (int i = 0; i < QP; ++i) phi += fph[i];
+    }
+    if constexpr (PSI) {
+      pull2d<QS, ST, CT>(fin_psi, P, P.ref_psi, x, y, fps);
+      psi = CT(0);
+#pragma unroll
+      for (int i = 0; i < QS; ++i) psi += fps[i];
+    }
+    if constexpr (CC) {
+      pull2d<QS, ST, CT>(fin_c, P, P.ref_c, x, y, fc);
+#pragma unroll
+      for (int i = 0; i < QS; ++i) C += fc[i];
+      const CT h = (psi + CT(1)) * CT(0.5);
+      U = (C / (CT(1) - k1 * h) - CT(1)) / k1;
+    }
+    if constexpr (TH) {
+      pull2d<QS, ST, CT>(fin_th, P, P.ref_th, x, y, fth);
+#pragma unroll
+      for (int i = 0; i < QS; ++i) H += fth[i];
+    }
+    s_phi[ly + R][lx + R] = phi;
+    s_psi[ly + R][lx + R] = psi;
+    s_U[ly + R][lx + R] = U;
+    if constexpr (NS) { s_jx[ly + R][lx + R] = jx; s_jy[ly + R][lx + R] = jy; }
+  }
+
+  // ---- phase A2: halo (and tile positions past a ragged domain edge)
+  for (int k = tid; k < RX * RY; k += NT) {
+    const int rx = k % RX, ry = k / RX;
+    const int tx = rx - R, ty = ry - R;
+    const int gx0 = bx0 + tx, gy0 = by0 + ty;
+    const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
+    if (inner && gx0 < P.nx && gy0 < P.ny) continue;   // filled in A1
+    bool gh;
+    const int gx = map_coord(gx0, P.nx, P.wall[0], gh);
+    const int gy = map_coord(gy0, P.ny, P.wall[1], gh);
+    const bool ring1 = rx >= R - 1 && rx <= RX - R && ry >= R - 1 && ry <= RY - R;
+    CT hphi = CT(1), hpsi = CT(-1), hU = CT(P.U0), hjx = CT(0), hjy = CT(0);
+    if constexpr (PHI) {
+      CT f[QP];
+      pull2d<QP, ST, CT>(fin_phi, P, P.ref_phi, gx, gy, f);
+      hphi = CT(0);
+#pragma unroll
+      for (int i = 0; i < QP; ++i) hphi += f[i];
+    }
+    if (ring1) {
+      if constexpr (PSI) {
+        CT f[QS];
+        pull2d<QS, ST, CT>(fin_psi, P, P.ref_psi, gx, gy, f);
+        hpsi = CT(0);
+#pragma unroll
+        for (int i = 0; i < QS; ++i) hpsi += f[i];
+      }
+      if constexpr (CC) {
+        CT f[QS];
+        pull2d<QS, ST, CT>(fin_c, P, P.ref_c, gx, gy, f);
+        CT hC = CT(0);
+#pragma unroll
+        for (int i = 0; i < QS; ++i) hC += f[i];
+        const CT h = (hpsi + CT(1)) * CT(0.5);
+        hU = (hC / (CT(1) - k1 * h) - CT(1)) / k1;
+      }
+      if constexpr (NS) {
+        CT f[QN];
+        pull2d<QN, ST, CT>(fin_ns, P, P.ref_ns, gx, gy, f);
+#pragma unroll
+        for (int i = 0; i < QN; ++i) { hjx += CT(LN::c[i][0]) * f[i]; hjy += CT(LN::c[i][1]) * f[i]; }
+      }
+    }
+    s_phi[ry][rx] = hphi;
+    s_psi[ry][rx] = hpsi;
+    s_U[ry][rx] = hU;
+    if constexpr (NS) { s_jx[ry][rx] = hjx; s_jy[ry][rx] = hjy; }
+  }
+  __syncthreads();
+
+  // ---- phase B: D_phi (x) v0 on the tile and ring 1 (mass-flux force)
+  FlowNode<CT, RX> fo;
+  if constexpr (FLOWX) {
+    if (own) {
+      flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
+      s_X[0][ly + R][lx + R] = fo.Dx * fo.v0x;
+      s_X[1][ly + R][lx + R] = fo.Dx * fo.v0y;
+      s_X[2][ly + R][lx + R] = fo.Dy * fo.v0x;
+      s_X[3][ly + R][lx + R] = fo.Dy * fo.v0y;
+    }
+    constexpr int AX = TX + 2, AY = TY + 2;
+    for (int k = tid; k < AX * AY; k += NT) {
+      const int rx = k % AX + R - 1, ry = k / AX + R - 1;
+      const int tx = rx - R, ty = ry - R;
+      const int gx0 = bx0 + tx, gy0 = by0 + ty;
+      const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
+      if (inner && gx0 < P.nx && gy0 < P.ny) continue;
+      // ghosts across a wall take minus the value at their mirror node
+      int mx = rx, my = ry;
+      CT sgn = CT(1);
+      bool skip = false;
+      if (P.wall[0] && (gx0 < 0 || gx0 >= P.nx)) {
+        if (gx0 == -1) mx = rx + 1; else if (gx0 == P.nx) mx = rx - 1; else skip = true;
+        sgn = -sgn;
+      }
+      if (P.wall[1] && (gy0 < 0 || gy0 >= P.ny)) {
+        if (gy0 == -1) my = ry + 1; else if (gy0 == P.ny) my = ry - 1; else skip = true;
+        sgn = -sgn;
+      }
+      CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
+      if (!skip) {
+        FlowNode<CT, RX> h;
+        flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, my, mx, h);
+        X0 = sgn * h.Dx * h.v0x; X1 = sgn * h.Dx * h.v0y;
+        X2 = sgn * h.Dy * h.v0x; X3 = sgn * h.Dy * h.v0y;
+      }
+      s_X[0][ry][rx] = X0; s_X[1][ry][rx] = X1; s_X[2][ry][rx] = X2; s_X[3][ry][rx] = X3;
+    }
+    __syncthreads();
+  } else {
+    if (own) flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
+  }
+  if (!own) return;
+
+  // ---- phase C: the rest of the step at the own node
+  const int ry = ly + R, rx = lx + R;
+  const CT h = (psi + CT(1)) * CT(0.5);
+  const CT q = clamp01((CT(1) - psi) * CT(0.5));
+  CT theta = TH ? (H + h) : CT(P.theta0);
+
+  // gradients of psi and U
+  CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
+  if constexpr (PSI) grad9<CT, RX>(s_psi, ry, rx, gpx, gpy);
+  if constexpr (CC) grad9<CT, RX>(s_U, ry, rx, gUx, gUy);
+  // unit normal and cubic anisotropy in the crystal frame of the nearest
+  // seed: a_s = 1 + eps (4 S4 - 3 G^2) / (G + delta)^2, N' = G a_s d a_s/d g'
+  const CT dn = CT(P.delta_n2);
+  const CT invp = CT(1) / sqrt(gpx * gpx + gpy * gpy + dn);
+  const CT ex = gpx * invp, ey = gpy * invp;
+  CT a_s, Nx, Ny;
+  {
+    const int gid = P.grain[idx];
+    const CT cth = CT(P.grain_cs[2 * gid]), sth = CT(P.grain_cs[2 * gid + 1]);
+    const CT rx_ = cth * gpx + sth * gpy;
+    const CT ry_ = -sth * gpx + cth * gpy;
+    const CT rx2 = rx_ * rx_, ry2 = ry_ * ry_;
+    const CT G = rx2 + ry2;
+    const CT S4 = rx2 * rx2 + ry2 * ry2;
+    const CT Gd = G + dn;
+    const CT inv2 = CT(1) / (Gd * Gd);
+    const CT eps = CT(P.eps4);
+    a_s = CT(1) + eps * (CT(4) * S4 - CT(3) * G * G) * inv2;
+    const CT pre = CT(4) * eps * G * a_s * inv2 / Gd;
+    const CT Nrx = pre * rx_ * (CT(4) * rx2 * G + (CT(4) * rx2 - CT(3) * G) * dn - CT(4) * S4);
+    const CT Nry = pre * ry_ * (CT(4) * ry2 * G + (CT(4) * ry2 - CT(3) * G) * dn - CT(4) * S4);
+    Nx = cth * Nrx - sth * Nry;
+    Ny = sth * Nrx + cth * Nry;
+  }
+  const CT an = a_s * a_s;
+
+  // kinetics F(U)
+  const CT lin = CT(1) + k1 * U;
+  const CT F = CT(P.inv_Le) + CT(P.Mcinf) * (lin > CT(0) ? lin : CT(0));
+  const CT gFx = lin > CT(0) ? CT(P.Mcinf) * k1 * gUx : CT(0);
+  const CT gFy = lin > CT(0) ? CT(P.Mcinf) * k1 * gUy : CT(0);
+
+  // psi source
+  const CT om = CT(1) - phi;
+  const CT ps1 = psi + CT(1);
+  const CT f2p = CT(0.5) * (CT(1) - psi) * ps1 * (CT(-2) * psi);
+  const CT f3psi = CT(2) * CT(P.beta_inter) * om * om * ps1;
+  const CT s1m = (CT(1) - psi) * ps1;
+  const CT pprime = CT(30.0 / 32.0) * s1m * s1m;
+  const CT Qpsi = -(f2p + f3psi + CT(P.lam) * pprime * (theta + CT(P.Mcinf) * U));
+  const CT invF = CT(1) / F;
+  const CT S_psi = CT(P.d_psi) * invF * invF * (gFx * (an * gpx + Nx) + gFy * (an * gpy + Ny)) +
+                   Qpsi * invF / CT(P.tau0);
+  const CT D_psi = CT(P.d_psi) * an * invF;
+  const CT rate_psi = CT(1) / (D_psi * CT(3) + CT(0.5));
+
+  // velocity, forces, pressure
+  CT vx = CT(0), vy = CT(0), Fx = CT(0), Fy = CT(0), p = CT(0);
+  const CT rho = fo.rho;
+  const CT grx = CT(P.drho) * fo.gx, gry = CT(P.drho) * fo.gy;
+  if constexpr (NS) {
+    CT Fmx = CT(0), Fmy = CT(0);
+    if constexpr (FLOWX) {
+      // (div X)_b = 3 sum_i w_i sum_a c_ia X_ab(x + c_i), X = D (x) v0
+      const CT w1 = CT(1.0 / 9), w2 = CT(1.0 / 36);
+      auto Xs = [&](int c, int dy, int dx) { return s_X[c][ry + dy][rx + dx]; };
+      // a = x components (X0: D_x v0_x, X1: D_x v0_y); a = y (X2, X3)
+      const CT ax0 = w1 * (Xs(0, 0, 1) - Xs(0, 0, -1)) + w2 * ((Xs(0, 1, 1) - Xs(0, 1, -1)) + (Xs(0, -1, 1) - Xs(0, -1, -1)));
+      const CT ax1 = w1 * (Xs(1, 0, 1) - Xs(1, 0, -1)) + w2 * ((Xs(1, 1, 1) - Xs(1, 1, -1)) + (Xs(1, -1, 1) - Xs(1, -1, -1)));
+      const CT ay2 = w1 * (Xs(2, 1, 0) - Xs(2, -1, 0)) + w2 * ((Xs(2, 1, 1) + Xs(2, 1, -1)) - (Xs(2, -1, -1) + Xs(2, -1, 1)));
+      const CT ay3 = w1 * (Xs(3, 1, 0) - Xs(3, -1, 0)) + w2 * ((Xs(3, 1, 1) + Xs(3, 1, -1)) - (Xs(3, -1, -1) + Xs(3, -1, 1)));
+      Fmx = CT(P.drho) * CT(3) * (ax0 + ay2);
+      Fmy = CT(P.drho) * CT(3) * (ax1 + ay3);
+    }
+    const CT Fby = -(rho - CT(P.rho_l)) * CT(P.g);
+    const CT rvx = jx + CT(0.5) * (fo.Fsx + Fmx);
+    const CT rvy = jy + CT(0.5) * (fo.Fsy + Fby + Fmy);
+    const CT onechi = CT(1) - fo.chi;
+    vx = onechi * rvx / rho;
+    vy = onechi * rvy / rho;
+    Fx = fo.Fsx + Fmx - CT(2) * fo.chi * rvx;
+    Fy = fo.Fsy + Fby + Fmy - CT(2) * fo.chi * rvy;
+    const CT vv = vx * vx + vy * vy;
+    const CT s0 = -CT(LN::w[0]) * vv * CT(1.5);
+    CT sum = CT(0);
+#pragma unroll
+    for (int i = 1; i < QN; ++i) sum += fns[i];
+    p = CT(LN::cs2) / (CT(1) - CT(LN::w[0])) * (sum + CT(0.5) * (vx * grx + vy * gry) + rho * s0);
+  }
+
+  if (mode == 1) {
+    const long long NN = N;
+    mout[0 * NN + idx] = (double)phi;
+    mout[1 * NN + idx] = (double)psi;
+    mout[2 * NN + idx] = (double)C;
+    mout[3 * NN + idx] = (double)theta;
+    mout[4 * NN + idx] = (double)U;
+    mout[5 * NN + idx] = (double)p;
+    mout[6 * NN + idx] = (double)vx;
+    mout[7 * NN + idx] = (double)vy;
+    mout[8 * NN + idx] = 0.0;
+    return;
+  }
+
+  const bool first = P.first != 0;
+  raw* fo_ns = fout + (long long)(NS ? P.o_ns : 0) * N;
+  raw* fo_phi = fout + (long long)(PHI ? P.o_phi : 0) * N;
+  raw* fo_psi = fout + (long long)(PSI ? P.o_psi : 0) * N;
+  raw* fo_c = fout + (long long)(CC ? P.o_c : 0) * N;
+  raw* fo_th = fout + (long long)(TH ? P.o_th : 0) * N;
+
+  // ---- NS collision: f* = feq + F/2 + (1 - s_nu) P_s (f - feq + F/2),
+  // P_s the orthogonal projector on the moments c_x^2 - c_y^2 and c_x c_y
+  if constexpr (NS) {
+    const CT nu = (CT(P.mu_g) + (CT(P.mu_l) - CT(P.mu_g)) * phi) / rho;
+    const CT s_nu = CT(1) / (nu * CT(3) + CT(0.5));
+    const CT vv = vx * vx + vy * vy;
+    const CT vgr = vx * grx + vy * gry;
+    const CT vF = vx * Fx + vy * Fy;
+    CT fneq[QN], fhalf[QN];
+    CT m1 = CT(0), m2 = CT(0);   // projections on c_x^2 - c_y^2 and c_x c_y
+#pragma unroll
+    for (int i = 0; i < QN; ++i) {
+      const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
+      const CT cv = cx * vx + cy * vy;
+      const CT cF = cx * Fx + cy * Fy;
+      const CT w = CT(LN::w[i]);
+      CT feq = w * p * CT(3) + rho * w * (cv * CT(3) + cv * cv * CT(4.5) - vv * CT(1.5));
+      if (i == 0) feq -= p * CT(3);
+      const CT Ft = w * (vgr + cF * CT(3) + (cv * cF - vF * CT(1.0 / 3)) * CT(9));
+      fhalf[i] = feq + CT(0.5) * Ft;
+      fneq[i] = fns[i] - feq + CT(0.5) * Ft;
+      m1 += (cx * cx - cy * cy) * fneq[i];
+      m2 += (cx * cy) * fneq[i];
+    }
+    const CT r = CT(1) - s_nu;
+#pragma unroll
+    for (int i = 0; i < QN; ++i) {
+      const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
+      const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
+      Store<ST>::st(fo_ns + (long long)i * N + idx, fs, P.ref_ns[i]);
+    }
+  }
+
+  // ---- CAC collision
+  const CT phivx = phi * vx, phivy = phi * vy;
+  if constexpr (PHI) {
+    CT pvx0 = phivx, pvy0 = phivy;
+    if (!first) { pvx0 = CT(hist[(long long)P.h_phiv * N + idx]); pvy0 = CT(hist[(long long)(P.h_phiv + 1) * N + idx]); }
+    const CT gx_ = (phivx - pvx0) + CT(LP::cs2) * fo.sharp * fo.nx;
+    const CT gy_ = (phivy - pvy0) + CT(LP::cs2) * fo.sharp * fo.ny;
+    const CT s1 = CT(P.s_phi);
+    CT feq[QP], G[QP];
+    CT jx_ = CT(0), jy_ = CT(0), gjx = CT(0), gjy = CT(0);
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]);
+      const CT w = CT(LP::w[i]);
+      feq[i] = w * phi * (CT(1) + (cx * vx + cy * vy) / CT(LP::cs2));
+      G[i] = w * (cx * gx_ + cy * gy_) / CT(LP::cs2);
+      jx_ += cx * (fph[i] - feq[i]); jy_ += cy * (fph[i] - feq[i]);
+      gjx += cx * G[i]; gjy += cy * G[i];
+    }
+    const CT inv_fn = CT(1) / CT(LP::flux_norm);
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]);
+      const CT Pf = (cx * jx_ + cy * jy_) * inv_fn;        // projector on the flux moments
+      const CT PG = (cx * gjx + cy * gjy) * inv_fn;
+      const CT fs = feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG;
+      Store<ST>::st(fo_phi + (long long)i * N + idx, fs, P.ref_phi[i]);
+    }
+    hist[(long long)P.h_phiv * N + idx] = (HT)phivx;
+    hist[(long long)(P.h_phiv + 1) * N + idx] = (HT)phivy;
+  }
+
+  // ---- AAC collision with the time-stretched store
+  if constexpr (PSI) {
+    CT Sprev = S_psi;
+    if (!first) Sprev = CT(hist[(long long)P.h_S * N + idx]);
+    const CT inv_an = CT(1) / an;
+    CT jx_ = CT(0), jy_ = CT(0);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const CT d = fps[i] - CT(LS::w[i]) * psi;
+      jx_ += CT(LS::c[i][0]) * d; jy_ += CT(LS::c[i][1]) * d;
+    }
+    const CT gNx = -Nx * inv_an, gNy = -Ny * inv_an;    // first moment of G / cs2 ... (G_i = -w_i c_i.N / a_s^2)
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
+      const CT w = CT(LS::w[i]);
+      const CT G = w * (cx * gNx + cy * gNy);
+      const CT fstar = w * psi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
+                       CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
+      const CT old = Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx, P.ref_psi[i]);
+      const CT fs = (fstar - (CT(1) - an) * old) * inv_an;
+      Store<ST>::st(fo_psi + (long long)i * N + idx, fs, P.ref_psi[i]);
+    }
+  }
+
+  // ---- solute collision
+  if constexpr (CC) {
+    CT psi_prev = psi;
+    if (!first) psi_prev = CT(hist[(long long)P.h_psi * N + idx]);
+    const CT at = -CT(P.a_at) * CT(P.W0) * a_s * lin * (psi - psi_prev);
+    const CT Jat_x = at * ex, Jat_y = at * ey;
+    const CT jv = CT(P.D) * q * C * CT(P.sharp) * (om > CT(0) ? om : CT(0));   // sqrt(2 beta_phi)/W_phi (phi_l - phi)+
+    const CT Jx = jv * fo.nx, Jy = jv * fo.ny;
+    const CT m = CT(1) - k1 * h;
+    const CT dr = CT(P.D) * q * C * k1 / (m * m) * CT(0.5);   // grad h = grad psi / 2
+    const CT Bx = C * vx - dr * gpx + k1 * (Jat_x + Jx);
+    const CT By = C * vy - dr * gpy + k1 * (Jat_y + Jy);
+    CT Bpx = Bx, Bpy = By;
+    if (!first) { Bpx = CT(hist[(long long)P.h_B * N + idx]); Bpy = CT(hist[(long long)(P.h_B + 1) * N + idx]); }
+    const CT s1 = CT(1) / (CT(P.D) * q / m * CT(3) + CT(0.5));
+    CT jx_ = CT(0), jy_ = CT(0);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fc[i]; jy_ += CT(LS::c[i][1]) * fc[i]; }
+    jx_ -= Bx; jy_ -= By;
+    const CT dBx = Bx - Bpx, dBy = By - Bpy;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
+      const CT w = CT(LS::w[i]);
+      const CT feq = w * C + w * (cx * Bx + cy * By) * CT(3);
+      const CT G = w * (cx * dBx + cy * dBy) * CT(3);
+      const CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      Store<ST>::st(fo_c + (long long)i * N + idx, fs, P.ref_c[i]);
+    }
+    hist[(long long)P.h_B * N + idx] = (HT)Bx;
+    hist[(long long)(P.h_B + 1) * N + idx] = (HT)By;
+  }
+
+  // ---- heat collision
+  if constexpr (TH) {
+    const CT Hvx = H * vx, Hvy = H * vy;
+    CT Hpx = Hvx, Hpy = Hvy;
+    if (!first) { Hpx = CT(hist[(long long)P.h_Hv * N + idx]); Hpy = CT(hist[(long long)(P.h_Hv + 1) * N + idx]); }
+    const CT s1 = CT(P.s_th);
+    CT jx_ = CT(0), jy_ = CT(0);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fth[i]; jy_ += CT(LS::c[i][1]) * fth[i]; }
+    jx_ -= Hvx; jy_ -= Hvy;
+    const CT dx_ = Hvx - Hpx, dy_ = Hvy - Hpy;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
+      const CT w = CT(LS::w[i]);
+      CT geq = w * theta + w * (cx * Hvx + cy * Hvy) * CT(3);
+      if (i == 0) geq = H + (w - CT(1)) * theta;
+      const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
+      const CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      Store<ST>::st(fo_th + (long long)i * N + idx, gs, P.ref_th[i]);
+    }
+    hist[(long long)P.h_Hv * N + idx] = (HT)Hvx;
+    hist[(long long)(P.h_Hv + 1) * N + idx] = (HT)Hvy;
+  }
+
+  if constexpr (PSI) {
+    hist[(long long)P.h_psi * N + idx] = (HT)psi;
+    hist[(long long)P.h_S * N + idx] = (HT)S_psi;
+  }
+}
+
+// ------------------------------------------------------------------ launch
+template <int FIELDS, int QP, class ST, class HT, class CT>
+hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void* hist,
+                           double* mout, int mode, hipStream_t s) {
+  dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY);
+  using raw = typename Store<ST>::raw;
+  hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT>), grid, dim3(NT), 0, s, P,
+                     (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  return hipGetLastError();
+}
+
+template <class ST, class HT, class CT>
+static hipError_t dispatch_fields(const DevParams& P, int fields, const void* fin, void* fout,
+                                  void* hist, double* mout, int mode, hipStream_t s, bool& ok) {
+  ok = true;
+  const bool q9 = P.q_phi == 9;
+#define PFL_CASE(F)                                                                              \
+  case F:                                                                                        \
+    return q9 ? launch_step2d_t<F, 9, ST, HT, CT>(P, fin, fout, hist, mout, mode, s)             \
+              : launch_step2d_t<F, 5, ST, HT, CT>(P, fin, fout, hist, mout, mode, s);
+  switch (fields) {
+    PFL_CASE(F_NS | F_PHI | F_PSI | F_C | F_TH)
+    PFL_CASE(F_PSI | F_C)
+    PFL_CASE(F_PSI | F_C | F_TH)
+    PFL_CASE(F_NS | F_PHI)
+    PFL_CASE(F_PHI | F_PSI | F_C | F_TH)
+    PFL_CASE(F_PSI)
+    PFL_CASE(F_PHI)
+    PFL_CASE(F_NS | F_PSI | F_TH)
+    PFL_CASE(F_PSI | F_TH)
+    default:
+      ok = false;
+      return hipSuccess;
+  }
+#undef PFL_CASE
+}
+
+hipError_t launch_step2d(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                         void* hist, double* mout, int mode, hipStream_t s, bool& ok) {
+  switch (store) {
+    case 0: return dispatch_fields<double, double, double>(P, fields, fin, fout, hist, mout, mode, s, ok);
+    case 1: return dispatch_fields<float, float, float>(P, fields, fin, fout, hist, mout, mode, s, ok);
+    case 2: return dispatch_fields<half_dev, float, float>(P, fields, fin, fout, hist, mout, mode, s, ok);
+    case 3: return dispatch_fields<bf16_dev, float, float>(P, fields, fin, fout, hist, mout, mode, s, ok);
+    default: ok = false; return hipSuccess;
+  }
+}
+
+bool step2d_supported(int fields) {
+  switch (fields) {
+    case F_NS | F_PHI | F_PSI | F_C | F_TH:
+    case F_PSI | F_C:
+    case F_PSI | F_C | F_TH:
+    case F_NS | F_PHI:
+    case F_PHI | F_PSI | F_C | F_TH:
+    case F_PSI:
+    case F_PHI:
+    case F_NS | F_PSI | F_TH:
+    case F_PSI | F_TH:
+      return true;
+    default:
+      return false;
+  }
+}
+
+}  // namespace pfl

@@ -1,0 +1,128 @@
+"""GPU FP64 step against the CPU FP64 oracle through the C ABI.
+
+Bar: 1e-12 normwise relative error per field (max|gpu - oracle| / max|oracle|)
+after N steps, on every macro field and on the full node-form state
+(populations of every set plus history).  Grids are small enough for the
+oracle to finish in seconds yet span several 32 x 8 tiles with ragged tails;
+walls, periodic axes, every field combination the library builds, and both
+lattices for phi are covered.
+"""
+import math
+
+import pytest
+import torch
+
+import workloads
+from tests.parity_util import (compare_macros, gpu_run, log, oracle_macros, oracle_run,
+                               oracle_state, rel_err)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+CASES = [
+    # name, workload overrides, steps
+    ("all_walls_12x10", dict(nx=12, ny=10), 20),
+    ("all_ragged_37x19", dict(nx=37, ny=19, seed=1), 30),
+    ("all_periodic_40x24", dict(nx=40, ny=24, seed=2, periodic=(True, True, True)), 30),
+    ("all_xwalls_20x36", dict(nx=20, ny=36, seed=3, periodic=(False, True, True)), 30),
+    ("all_phiq9_33x17", dict(nx=33, ny=17, seed=4, phi_q=9), 30),
+    ("all_gravity_30x40", dict(nx=30, ny=40, seed=5, g=2e-4, rho_g=0.01), 30),
+    ("alloy_35x21", dict(nx=35, ny=21, seed=6, fields=("psi", "c"), Le=math.inf, U0=-0.55,
+                         theta0=0.0, tau0=50.0, periodic=(True, True, True)), 40),
+    ("alloy_theta_26x18", dict(nx=26, ny=18, seed=7, fields=("psi", "c", "theta")), 30),
+    ("nsphi_33x33", dict(nx=33, ny=33, seed=8, fields=("ns", "phi")), 40),
+    ("noflow_29x15", dict(nx=29, ny=15, seed=9, fields=("phi", "psi", "c", "theta")), 30),
+    ("psi_only_16x16", dict(nx=16, ny=16, seed=10, fields=("psi",), Le=math.inf, theta0=-0.3), 30),
+    ("phi_only_18x14", dict(nx=18, ny=14, seed=11, fields=("phi",)), 30),
+    ("ns_psi_theta_22x12", dict(nx=22, ny=12, seed=12, fields=("ns", "psi", "theta")), 30),
+    ("psi_theta_21x13", dict(nx=21, ny=13, seed=13, fields=("psi", "theta")), 30),
+]
+
+
+def _small(over):
+    over = dict(over)
+    seed = over.pop("seed", 0)
+    nx, ny = over.pop("nx"), over.pop("ny")
+    fields = over.pop("fields", workloads.FIELDS_ALL)
+    periodic = over.pop("periodic", None)
+    w = workloads.small(nx=nx, ny=ny, fields=fields, seed=seed, periodic=periodic)
+    w.update(over)
+    if "c" in fields and "phi" in fields and "theta" not in fields:
+        w["bubbles"] = []
+    return w
+
+
+@pytest.mark.parametrize("name,over,steps", CASES, ids=[c[0] for c in CASES])
+def test_small_grids_fp64(name, over, steps):
+    w = _small(over)
+    log(f"[parity] {name} steps={steps} fields={w['fields']}")
+    osim = oracle_run(w, steps)
+    gsim = gpu_run(w, steps)
+    errs = compare_macros(gsim.macros(), oracle_macros(osim))
+    log(f"[parity] {name} macros {errs}")
+    st_err = rel_err(gsim.get_state(), oracle_state(osim, w["fields"]))
+    log(f"[parity] {name} state {st_err:.3e}")
+    assert max(errs.values()) < TOL, errs
+    assert st_err < TOL
+
+
+def test_initial_state_matches_oracle():
+    w = _small(dict(nx=40, ny=30, seed=21))
+    osim = oracle_run(w, 0)
+    gsim = gpu_run(w, 0)
+    errs = compare_macros(gsim.macros(), oracle_macros(osim))
+    log(f"[parity] init macros {errs}")
+    assert max(errs.values()) < TOL
+    assert rel_err(gsim.get_state(), oracle_state(osim, w["fields"])) < TOL
+
+
+def test_set_state_roundtrip_and_restart():
+    """Exporting the GPU state into the oracle (and back) continues identically."""
+    w = _small(dict(nx=24, ny=20, seed=22))
+    gsim = gpu_run(w, 10)
+    st = gsim.get_state()
+    gsim.set_state(st, 10)
+    assert rel_err(gsim.get_state(), st) == 0.0
+    gsim.step(10)
+    osim = oracle_run(w, 20)
+    errs = compare_macros(gsim.macros(), oracle_macros(osim))
+    assert max(errs.values()) < TOL, errs
+
+
+def test_reduce_matches_oracle():
+    w = _small(dict(nx=36, ny=28, seed=23))
+    osim = oracle_run(w, 25)
+    gsim = gpu_run(w, 25)
+    r = gsim.reduce()
+    o = osim.reduce()
+    for k in ("sum_phi", "gas_volume", "sum_C", "solid_fraction"):
+        assert abs(r[k] - o[k]) <= 1e-12 * max(abs(o[k]), 1.0), (k, r[k], o[k])
+    for a in range(2):
+        assert abs(r["gas_centroid"][a] - o["gas_centroid"][a]) < 1e-9
+    assert r["nonfinite"] == 0
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN planted in the initial macros is caught by the FP64 reduction."""
+    import paper_2407_01651_amd as pfl
+    w = _small(dict(nx=16, ny=12, seed=24))
+    g = pfl.Sim(w)
+    phi = torch.ones(12, 16, dtype=torch.float64)
+    phi[5, 7] = float("nan")
+    g.init_from_macros(phi=phi)
+    r = g.reduce()
+    assert r["nonfinite"] == 1
+
+
+def test_coupled_128_full_500_steps():
+    """The coupled 128 x 128 workload, all 500 steps, FP64, full fields."""
+    w = workloads.get("coupled2d_128")
+    log("[parity] coupled2d_128 500 steps")
+    osim = oracle_run(w, 500)
+    gsim = gpu_run(w, 500)
+    errs = compare_macros(gsim.macros(), oracle_macros(osim))
+    log(f"[parity] coupled2d_128 macros {errs}")
+    st_err = rel_err(gsim.get_state(), oracle_state(osim, w["fields"]))
+    log(f"[parity] coupled2d_128 state {st_err:.3e}")
+    assert max(errs.values()) < TOL, errs
+    assert st_err < TOL

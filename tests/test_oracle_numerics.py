@@ -106,13 +106,13 @@ def test_anisotropy_3d_fd_and_threshold():
     g = torch.randn(3, 50, generator=gen, dtype=DT)
     ang = torch.rand(50, generator=gen, dtype=DT)
     eps = 0.02
-    a_s, N = anisotropy(g, ang, eps, 1e-20)
+    a_s, N = anisotropy(g, ang, eps, 1e-8)
     h = 1e-6
     for a in range(3):
         gp, gm = g.clone(), g.clone()
         gp[a] += h
         gm[a] -= h
-        fd = (anisotropy(gp, ang, eps, 1e-20)[0] - anisotropy(gm, ang, eps, 1e-20)[0]) / (2 * h)
+        fd = (anisotropy(gp, ang, eps, 1e-8)[0] - anisotropy(gm, ang, eps, 1e-8)[0]) / (2 * h)
         assert torch.allclose(N[a], (g * g).sum(0) * a_s * fd, atol=1e-8)
     # cube axes and body diagonals: a_s = 1 + eps and 1 - 3 eps + 4 eps / 3
     ax = torch.tensor([[1.0], [0.0], [0.0]], dtype=DT)
@@ -120,9 +120,19 @@ def test_anisotropy_3d_fd_and_threshold():
     z = torch.zeros(1, dtype=DT)
     assert abs(float(anisotropy(ax, z, eps, 1e-20)[0]) - (1 + eps)) < 1e-15
     assert abs(float(anisotropy(dg, z, eps, 1e-20)[0]) - (1 - 3 * eps + 4 * eps / 3)) < 1e-15
+    # regularised where the gradient vanishes: a_s -> 1 and N -> 0 smoothly
     tiny = torch.full((3, 1), 1e-11, dtype=DT)
-    a0, N0 = anisotropy(tiny, z, eps, 1e-20)
-    assert float(a0) == 1.0 and float(N0.abs().max()) == 0.0
+    a0, N0 = anisotropy(tiny, z, eps, 1e-8)
+    assert abs(float(a0) - 1.0) < 1e-20 and float(N0.abs().max()) < 1e-20
+    # and N stays the exact derivative of the regularised a_s at small |g|
+    gs = torch.randn(3, 20, generator=gen, dtype=DT) * 1e-4
+    a_s, N = anisotropy(gs, ang[:20], eps, 1e-8)
+    for a in range(3):
+        gp, gm = gs.clone(), gs.clone()
+        gp[a] += 1e-9
+        gm[a] -= 1e-9
+        fd = (anisotropy(gp, ang[:20], eps, 1e-8)[0] - anisotropy(gm, ang[:20], eps, 1e-8)[0]) / 2e-9
+        assert torch.allclose(N[a], (gs * gs).sum(0) * a_s * fd, atol=1e-13)
 
 
 def test_thin_interface_constants():

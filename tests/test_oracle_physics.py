@@ -200,6 +200,10 @@ def test_conservation_with_walls():
 
 
 def test_solute_vacuum_in_bubble():
+    """The vacuum flux J (Sec. 2.1) empties a static bubble of solute.  With
+    no flow and psi = psi_l the zero-flux steady state of the solute equation
+    is (1-k) C J-term = D q grad(C): d ln C / d ln phi = (1 - k) wherever the
+    phi gradient is resolved, i.e. C ~ phi^(1-k) across the interface."""
     n = 48
     w = workloads.small(nx=n, ny=n, fields=("phi", "psi", "c", "theta"), periodic=(True, True, True),
                         tau0=50.0, Le=1.0)
@@ -210,12 +214,15 @@ def test_solute_vacuum_in_bubble():
     phi = sim.macros()["phi"]
     sim.init_from_macros(phi=phi, C=torch.ones_like(phi))
     c0 = float(sim.macros()["C"].sum())
-    sim.step(1500)
+    sim.step(1000)
     m = sim.macros()
-    centre = float(m["C"][24, 24])
-    assert centre < 1e-3, centre
+    sel = (m["phi"] > 0.02) & (m["phi"] < 0.5)
+    slope = np.polyfit(torch.log(m["phi"][sel]).numpy(), torch.log(m["C"][sel]).numpy(), 1)[0]
+    assert abs(slope / (1 - w["k"]) - 1) < 0.03, slope
+    # the core is emptied by more than two orders of magnitude, mass is kept,
+    # and the liquid far from the bubble gained the solute
+    assert float(m["C"][24, 24]) < 5e-3
     assert abs(float(m["C"].sum()) / c0 - 1) < 1e-12
-    # the liquid far from the bubble gained the solute
     assert float(m["C"][0, 0]) > 1.0
 
 
@@ -232,8 +239,12 @@ def test_centred_seed_d4_symmetry(angle):
     U = sim.macros()["U"]
     for f in (psi, U):
         mirror_x = torch.roll(torch.flip(f, dims=[1]), shifts=1, dims=1)   # x -> 40 - x
-        assert float((f - f.T).abs().max()) < 1e-13
-        assert float((f - mirror_x).abs().max()) < 1e-13
+        # exact up to summation-order roundoff, which the normal
+        # regularisation (Lipschitz constant 1/delta) amplifies at the seed
+        # centre where the gradient vanishes; a wrong sign or a transposed
+        # operand breaks the symmetry at O(1e-3)
+        assert float((f - mirror_x).abs().max()) < 1e-10
+        assert float((f - f.T).abs().max()) < 1e-10
     # and the seed grew, fastest along its crystal axes
     h = (psi + 1) / 2
     assert float(h.sum()) > math.pi * 16

@@ -42,7 +42,7 @@ _BASE = dict(
     U0=0.0, theta0=-0.55,
     rho_l=1.0, rho_g=0.1, nu_l=0.1, nu_g=0.1,
     sigma=0.005, M_phi=0.1, xi=4.0, beta_inter=0.75, g=0.0,
-    delta_n2=1e-20,
+    delta_n2=1e-6,                       # regularisation of unit normals (|g|^2 + delta_n2)
     seeds=[], bubbles=[],
     steps=500, store="f64",
 )
