@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--calib", action="store_true",
+                    help="run a plain 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
@@ -115,6 +117,14 @@ def main():
     import workloads
     w = workloads.get(a.config)
     torch.cuda.init()
+    if a.calib:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_run = time_gpu(w, a.store, a.steps, a.warmup)
     variants = {}
     for st in [s for s in a.also.split(",") if s and s != a.store]:

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace pfl;
@@ -207,6 +208,24 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   d.a_at = 1.0 / (2.0 * std::sqrt(2.0));
   d.phi_tanh = std::sqrt(0.5) / (2.0 * d.W_phi);
   d.psi_tanh = 2.0 * std::sqrt(0.5) / (2.0 * p->W0);
+  // constants in both compute precisions
+  {
+    auto fill = [&](auto& K) {
+      using T = std::remove_reference_t<decltype(K.k1)>;
+      K.k1 = (T)(1.0 - p->k); K.inv_k1 = (T)(1.0 / (1.0 - p->k));
+      K.U0 = (T)p->U0; K.theta0 = (T)p->theta0; K.eps4 = (T)p->eps4; K.dn = (T)p->delta_n2;
+      K.d_psi = (T)d.d_psi; K.inv_tau0 = (T)(1.0 / p->tau0); K.D = (T)d.D; K.lam = (T)d.lam;
+      K.Mcinf = (T)p->Mcinf; K.inv_Le = (T)d.inv_Le; K.beta_inter = (T)p->beta_inter;
+      K.sharp = (T)d.sharp; K.M_phi = (T)p->M_phi; K.Wphi2 = (T)(d.W_phi * d.W_phi); K.k_s = (T)d.k_s;
+      K.rho_l = (T)p->rho_l; K.rho_g = (T)p->rho_g; K.drho = (T)d.drho; K.mu_l = (T)d.mu_l;
+      K.mu_g = (T)d.mu_g; K.g = (T)p->g; K.s_phi = (T)d.s_phi; K.s_th = (T)d.s_th;
+      K.aW0 = (T)(d.a_at * p->W0);
+    };
+    fill(d.kd);
+    fill(d.kf);
+    const size_t lim = (size_t)1 << 32;
+    d.fast = (L.pops_bytes < lim && L.hist_bytes < lim) ? 1 : 0;
+  }
   uint8_t* aux = (uint8_t*)bufs->aux;
   d.grain = aux;
   d.grain_cs = (const double*)(aux + L.aux_cs);

@@ -62,6 +62,13 @@ template <> struct Lat<19> {
 };
 
 // ------------------------------------------------------------- parameters
+// Constants of the step in the compute precision, reciprocals precomputed.
+template <class CT>
+struct KP {
+  CT k1, inv_k1, U0, theta0, eps4, dn, d_psi, inv_tau0, D, lam, Mcinf, inv_Le, beta_inter;
+  CT sharp, M_phi, Wphi2, k_s, rho_l, rho_g, drho, mu_l, mu_g, g, s_phi, s_th, aW0;
+};
+
 // Everything a kernel needs, passed by value (well under the 4 KB limit).
 struct DevParams {
   int nx, ny, nz, dim;
@@ -84,6 +91,9 @@ struct DevParams {
   const double* grain_cs;      // cos, sin of each seed's angle
   const double* seeds;         // x, y, z, r, angle per seed
   const double* bubbles;       // x, y, z, r per bubble
+  int fast;                    // byte offsets of every buffer fit in 32 bits
+  KP<double> kd;
+  KP<float> kf;
   // reference populations of the deviation storage (per set, per direction)
   float ref_ns[19], ref_phi[19], ref_psi[7], ref_c[7], ref_th[7];
 };
@@ -122,5 +132,9 @@ template <> struct Store<bf16_dev> {
     *p = __float2bfloat16((float)v - ref);
   }
 };
+
+template <class CT> __device__ __forceinline__ const KP<CT>& kp(const DevParams& P);
+template <> __device__ __forceinline__ const KP<double>& kp<double>(const DevParams& P) { return P.kd; }
+template <> __device__ __forceinline__ const KP<float>& kp<float>(const DevParams& P) { return P.kf; }
 
 }  // namespace pfl

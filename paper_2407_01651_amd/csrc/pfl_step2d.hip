@@ -10,6 +10,10 @@
 // Populations live in SoA planes (x fastest), post-collision at their source
 // node, so a node pulls f_i(x) from x - c_i; a population that would cross a
 // wall is read back from the node's own opposite slot (half-way bounce-back).
+//
+// Tiles whose pulls stay inside the domain take a fast path: every load and
+// store is a scalar base plus a 32-bit byte offset, one integer add per
+// access.  Tiles on the domain edge use the general wrap/bounce addressing.
 #include "pfl_kernels.h"
 
 namespace pfl {
@@ -19,23 +23,52 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 template <class CT>
 __device__ __forceinline__ CT clamp01(CT v) { return v < CT(0) ? CT(0) : (v > CT(1) ? CT(1) : v); }
 
+// Reciprocal and inverse square root: correctly rounded in FP64 (the parity
+// path), the hardware approximations (1 ulp) in FP32.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs (workgroup b runs on XCD b mod 8), and each XCD has its own L2.  Give
+// XCD k a contiguous range of logical tiles in row-major order, i.e. a
+// horizontal band of the grid walked row by row, so tiles that share halo
+// rows and columns run on the same XCD at about the same time.
+constexpr int NXCD = 8;
+__device__ __forceinline__ void tile_of_block(int b, int gx, int gy, int& tx, int& ty) {
+  const int T = gx * gy;
+  const int q = T / NXCD, r = T % NXCD;
+  const int k = b % NXCD, j = b / NXCD;
+  const int L = k * q + (k < r ? k : r) + j;
+  ty = L / gx;
+  tx = L % gx;
+}
+
 // Map a (possibly out-of-domain) coordinate to the node whose value it
 // holds: periodic wrap, or mirror across a half-way wall (clamped so that
 // positions no valid node needs stay in range).
-__device__ __forceinline__ int map_coord(int g, int n, int wall, bool& ghost) {
-  ghost = false;
+__device__ __forceinline__ int map_coord(int g, int n, int wall) {
   if (g >= 0 && g < n) return g;
   if (!wall) { g %= n; if (g < 0) g += n; return g; }
-  ghost = true;
   g = g < 0 ? -1 - g : 2 * n - 1 - g;
   return g < 0 ? 0 : (g >= n ? n - 1 : g);
 }
 
-// Pull the pre-collision populations of one set at node (x, y).
+template <class ST>
+__device__ __forceinline__ const typename Store<ST>::raw* at_byte(const typename Store<ST>::raw* base, uint32_t b) {
+  return (const typename Store<ST>::raw*)((const char*)base + b);
+}
+template <class ST>
+__device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::raw* base, uint32_t b) {
+  return (typename Store<ST>::raw*)((char*)base + b);
+}
+
+// Pull the pre-collision populations of one set at node (x, y), general
+// addressing: periodic wrap or half-way bounce-back on each axis.
 template <int Q, class ST, class CT>
-__device__ __forceinline__ void pull2d(const typename Store<ST>::raw* __restrict__ base,
-                                       const DevParams& P, const float* ref, int x, int y,
-                                       CT f[Q]) {
+__device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
+                                             const DevParams& P, const float* ref, int x, int y, CT f[Q]) {
   using L = Lat<Q>;
   const long long N = P.N;
 #pragma unroll
@@ -46,10 +79,48 @@ __device__ __forceinline__ void pull2d(const typename Store<ST>::raw* __restrict
     else if (sx >= P.nx) { if (P.wall[0]) bounce = true; else sx -= P.nx; }
     if (sy < 0) { if (P.wall[1]) bounce = true; else sy += P.ny; }
     else if (sy >= P.ny) { if (P.wall[1]) bounce = true; else sy -= P.ny; }
-    long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
-    int plane = bounce ? L::opp[i] : i;
+    const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
+    const int plane = bounce ? L::opp[i] : i;
     f[i] = Store<ST>::template ld<CT>(base + plane * N + idx, ref[plane]);
   }
+}
+
+// Pull at an interior node: source x - c_i lies inside the domain.
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull_fast(const typename Store<ST>::raw* __restrict__ base,
+                                          const DevParams& P, const float* ref, uint32_t nbyte, CT f[Q]) {
+  using L = Lat<Q>;
+  constexpr uint32_t S = sizeof(typename Store<ST>::raw);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t rel = ((uint32_t)i * (uint32_t)P.N - (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx)) * S;
+    f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, rel + nbyte), ref[i]);
+  }
+}
+
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull(bool fast, const typename Store<ST>::raw* __restrict__ base,
+                                     const DevParams& P, const float* ref, int x, int y, CT f[Q]) {
+  if (fast) {
+    const uint32_t nbyte = ((uint32_t)y * (uint32_t)P.nx + (uint32_t)x) * (uint32_t)sizeof(typename Store<ST>::raw);
+    pull_fast<Q, ST, CT>(base, P, ref, nbyte, f);
+  } else {
+    pull_general<Q, ST, CT>(base, P, ref, x, y, f);
+  }
+}
+
+// Halo position k (0 <= k < RX*RY - TX*TY) of an R-ring tile: the R top
+// rows, the R bottom rows, then the side columns.
+template <int R>
+__device__ __forceinline__ void halo_pos(int k, int& rx, int& ry) {
+  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  if (k < R * RX) { ry = k / RX; rx = k % RX; return; }
+  k -= R * RX;
+  if (k < R * RX) { ry = RY - R + k / RX; rx = k % RX; return; }
+  k -= R * RX;
+  ry = R + k / (2 * R);
+  const int c = k % (2 * R);
+  rx = c < R ? c : TX + c;
 }
 
 // Isotropic D2Q9 gradient and Laplacian from an LDS array.
@@ -70,15 +141,14 @@ __device__ __forceinline__ CT lap9(const CT (*s)[RX], int ry, int rx) {
 
 // Flow quantities at one LDS position (node or ring 1): chemical potential,
 // surface tension, phi diffusion flux, velocity without the mass-flux force.
-template <class CT, int RX>
+template <class CT>
 struct FlowNode {
   CT gx, gy, lap, nx, ny, Fsx, Fsy, Dx, Dy, rho, chi, v0x, v0y, sharp;
 };
 
 template <bool NS, bool PHI, class CT, int RX, class JA>
-__device__ __forceinline__ void flow_node(const DevParams& P, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
-                                          const JA& s_jx, const JA& s_jy, int ry, int rx,
-                                          FlowNode<CT, RX>& o) {
+__device__ __forceinline__ void flow_node(const KP<CT>& K, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
+                                          const JA& s_jx, const JA& s_jy, int ry, int rx, FlowNode<CT>& o) {
   const CT phi = s_phi[ry][rx];
   const CT psi = s_psi[ry][rx];
   if constexpr (PHI) {
@@ -88,29 +158,29 @@ __device__ __forceinline__ void flow_node(const DevParams& P, const CT (*s_phi)[
     o.gx = o.gy = o.lap = CT(0);
   }
   // unit normal, regularised where the gradient vanishes
-  const CT inv = CT(1) / sqrt(o.gx * o.gx + o.gy * o.gy + CT(P.delta_n2));
+  const CT inv = rsq(o.gx * o.gx + o.gy * o.gy + K.dn);
   o.nx = o.gx * inv;
   o.ny = o.gy * inv;
   // phi_l = 1, phi_g = 0, psi_l = -1, beta_phi = 1/4
   const CT one_m = CT(1) - phi;
   // double-well factor of the sharpening flux, zero outside [phi_g, phi_l]
   const CT dw = one_m * phi;
-  o.sharp = CT(P.sharp) * (dw > CT(0) ? dw : CT(0));
-  o.Dx = CT(P.M_phi) * (o.gx - o.sharp * o.nx);
-  o.Dy = CT(P.M_phi) * (o.gy - o.sharp * o.ny);
+  o.sharp = K.sharp * (dw > CT(0) ? dw : CT(0));
+  o.Dx = K.M_phi * (o.gx - o.sharp * o.nx);
+  o.Dy = K.M_phi * (o.gy - o.sharp * o.ny);
   const CT h = (psi + CT(1)) * CT(0.5);
   o.chi = clamp01(h);
-  o.rho = CT(P.rho_g) + CT(P.drho) * phi;
+  o.rho = K.rho_g + K.drho * phi;
   if constexpr (NS) {
     const CT f1p = CT(0.5) * one_m * phi * (CT(1) - CT(2) * phi);
     const CT ps1 = psi + CT(1);
-    const CT f3p = CT(-2) * CT(P.beta_inter) * one_m * ps1 * ps1;
-    const CT mu = f1p + f3p - CT(P.W_phi * P.W_phi) * o.lap;
-    o.Fsx = CT(P.k_s) * mu * o.gx;
-    o.Fsy = CT(P.k_s) * mu * o.gy;
+    const CT f3p = CT(-2) * K.beta_inter * one_m * ps1 * ps1;
+    const CT mu = f1p + f3p - K.Wphi2 * o.lap;
+    o.Fsx = K.k_s * mu * o.gx;
+    o.Fsy = K.k_s * mu * o.gy;
     // buoyancy relative to the liquid: its hydrostatic head is carried by p
-    const CT Fbx = CT(0), Fby = -(o.rho - CT(P.rho_l)) * CT(P.g);
-    const CT s = (CT(1) - o.chi) / o.rho;
+    const CT Fbx = CT(0), Fby = -(o.rho - K.rho_l) * K.g;
+    const CT s = (CT(1) - o.chi) * rcp(o.rho);
     o.v0x = s * (s_jx[ry][rx] + CT(0.5) * (o.Fsx + Fbx));
     o.v0y = s * (s_jy[ry][rx] + CT(0.5) * (o.Fsy + Fby));
   } else {
@@ -134,21 +204,31 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   using LS = Lat<5>;
   using LP = Lat<QP>;
   using raw = typename Store<ST>::raw;
+  constexpr uint32_t S = sizeof(raw), HS = sizeof(HT);
+  const KP<CT>& K = kp<CT>(P);
 
   __shared__ CT s_phi[RY][RX];
   __shared__ CT s_psi[RY][RX];
   __shared__ CT s_U[RY][RX];
+  // psi populations of the tile and ring 1: the time-stretched store needs
+  // f_i(x + c_i) at the start of the step
+  __shared__ CT s_fps[PSI ? QS : 1][PSI ? RY : 1][PSI ? RX : 1];
   __shared__ CT s_jx[NS ? RY : 1][NS ? RX : 1];
   __shared__ CT s_jy[NS ? RY : 1][NS ? RX : 1];
   __shared__ CT s_X[FLOWX ? 4 : 1][FLOWX ? RY : 1][FLOWX ? RX : 1];
 
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
-  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  int tile_x, tile_y;
+  tile_of_block(blockIdx.x, (P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, tile_x, tile_y);
+  const int bx0 = tile_x * TX, by0 = tile_y * TY;
   const int x = bx0 + lx, y = by0 + ly;
   const bool own = (x < P.nx) && (y < P.ny);
   const long long N = P.N;
   const long long idx = (long long)y * P.nx + x;
+  // every pull of the tile and its halo stays inside the domain
+  const bool fast = P.fast && bx0 >= R + 1 && by0 >= R + 1 && bx0 + TX + R + 1 <= P.nx &&
+                    by0 + TY + R + 1 <= P.ny;
 
   const raw* fin_ns = fin + (long long)(NS ? P.o_ns : 0) * N;
   const raw* fin_phi = fin + (long long)(PHI ? P.o_phi : 0) * N;
@@ -156,38 +236,59 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const raw* fin_c = fin + (long long)(CC ? P.o_c : 0) * N;
   const raw* fin_th = fin + (long long)(TH ? P.o_th : 0) * N;
 
-  const CT k1 = CT(1) - CT(P.k);
+  const CT k1 = K.k1;
 
   // ---- phase A1: own node populations and moments
   CT fns[NS ? QN : 1], fph[PHI ? QP : 1], fps[PSI ? QS : 1], fc[CC ? QS : 1], fth[TH ? QS : 1];
-  CT phi = CT(1), psi = CT(-1), C = CT(0), H = CT(0), U = CT(P.U0), jx = CT(0), jy = CT(0);
+  CT phi = CT(1), psi = CT(-1), C = CT(0), H = CT(0), U = K.U0, jx = CT(0), jy = CT(0);
+  // history and grain id of the own node, loaded early so that their latency
+  // overlaps with the pulls
+  const bool first = P.first != 0;
+  const uint32_t hbyte = (uint32_t)idx * HS;
+  const uint32_t hplane = (uint32_t)N * HS;
+  auto hld = [&](int plane) -> CT {
+    if (P.fast) return CT(*(const HT*)((const char*)hist + (uint32_t)plane * hplane + hbyte));
+    return CT(hist[(long long)plane * N + idx]);
+  };
+  CT h_psi = CT(0), h_S = CT(0), h_pv0 = CT(0), h_pv1 = CT(0), h_B0 = CT(0), h_B1 = CT(0);
+  CT h_Hv0 = CT(0), h_Hv1 = CT(0);
+  int gid = 0;
+  if (own) {
+    if (PSI) gid = P.grain[idx];
+    if (!first && mode == 0) {
+      if constexpr (PSI) { h_psi = hld(P.h_psi); h_S = hld(P.h_S); }
+      if constexpr (PHI) { h_pv0 = hld(P.h_phiv); h_pv1 = hld(P.h_phiv + 1); }
+      if constexpr (CC) { h_B0 = hld(P.h_B); h_B1 = hld(P.h_B + 1); }
+      if constexpr (TH) { h_Hv0 = hld(P.h_Hv); h_Hv1 = hld(P.h_Hv + 1); }
+    }
+  }
   if (own) {
     if constexpr (NS) {
-      pull2d<QN, ST, CT>(fin_ns, P, P.ref_ns, x, y, fns);
+      pull<QN, ST, CT>(fast, fin_ns, P, P.ref_ns, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) { jx += CT(LN::c[i][0]) * fns[i]; jy += CT(LN::c[i][1]) * fns[i]; }
     }
     if constexpr (PHI) {
-      pull2d<QP, ST, CT>(fin_phi, P, P.ref_phi, x, y, fph);
+      pull<QP, ST, CT>(fast, fin_phi, P, P.ref_phi, x, y, fph);
       phi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) phi += fph[i];
     }
     if constexpr (PSI) {
-      pull2d<QS, ST, CT>(fin_psi, P, P.ref_psi, x, y, fps);
+      pull<QS, ST, CT>(fast, fin_psi, P, P.ref_psi, x, y, fps);
       psi = CT(0);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) psi += fps[i];
+      for (int i = 0; i < QS; ++i) { psi += fps[i]; s_fps[i][ly + R][lx + R] = fps[i]; }
     }
     if constexpr (CC) {
-      pull2d<QS, ST, CT>(fin_c, P, P.ref_c, x, y, fc);
+      pull<QS, ST, CT>(fast, fin_c, P, P.ref_c, x, y, fc);
 #pragma unroll
       for (int i = 0; i < QS; ++i) C += fc[i];
       const CT h = (psi + CT(1)) * CT(0.5);
-      U = (C / (CT(1) - k1 * h) - CT(1)) / k1;
+      U = (C * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull2d<QS, ST, CT>(fin_th, P, P.ref_th, x, y, fth);
+      pull<QS, ST, CT>(fast, fin_th, P, P.ref_th, x, y, fth);
 #pragma unroll
       for (int i = 0; i < QS; ++i) H += fth[i];
     }
@@ -197,21 +298,13 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     if constexpr (NS) { s_jx[ly + R][lx + R] = jx; s_jy[ly + R][lx + R] = jy; }
   }
 
-  // ---- phase A2: halo (and tile positions past a ragged domain edge)
-  for (int k = tid; k < RX * RY; k += NT) {
-    const int rx = k % RX, ry = k / RX;
-    const int tx = rx - R, ty = ry - R;
-    const int gx0 = bx0 + tx, gy0 = by0 + ty;
-    const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
-    if (inner && gx0 < P.nx && gy0 < P.ny) continue;   // filled in A1
-    bool gh;
-    const int gx = map_coord(gx0, P.nx, P.wall[0], gh);
-    const int gy = map_coord(gy0, P.ny, P.wall[1], gh);
+  // ---- phase A2: halo (and, on edge tiles, tile positions past the domain)
+  auto halo_node = [&](int rx, int ry, int gx, int gy, bool hfast) {
     const bool ring1 = rx >= R - 1 && rx <= RX - R && ry >= R - 1 && ry <= RY - R;
-    CT hphi = CT(1), hpsi = CT(-1), hU = CT(P.U0), hjx = CT(0), hjy = CT(0);
+    CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hjx = CT(0), hjy = CT(0);
     if constexpr (PHI) {
       CT f[QP];
-      pull2d<QP, ST, CT>(fin_phi, P, P.ref_phi, gx, gy, f);
+      pull<QP, ST, CT>(hfast, fin_phi, P, P.ref_phi, gx, gy, f);
       hphi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) hphi += f[i];
@@ -219,23 +312,23 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull2d<QS, ST, CT>(fin_psi, P, P.ref_psi, gx, gy, f);
+        pull<QS, ST, CT>(hfast, fin_psi, P, P.ref_psi, gx, gy, f);
         hpsi = CT(0);
 #pragma unroll
-        for (int i = 0; i < QS; ++i) hpsi += f[i];
+        for (int i = 0; i < QS; ++i) { hpsi += f[i]; s_fps[i][ry][rx] = f[i]; }
       }
       if constexpr (CC) {
         CT f[QS];
-        pull2d<QS, ST, CT>(fin_c, P, P.ref_c, gx, gy, f);
+        pull<QS, ST, CT>(hfast, fin_c, P, P.ref_c, gx, gy, f);
         CT hC = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) hC += f[i];
         const CT h = (hpsi + CT(1)) * CT(0.5);
-        hU = (hC / (CT(1) - k1 * h) - CT(1)) / k1;
+        hU = (hC * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
       }
       if constexpr (NS) {
         CT f[QN];
-        pull2d<QN, ST, CT>(fin_ns, P, P.ref_ns, gx, gy, f);
+        pull<QN, ST, CT>(hfast, fin_ns, P, P.ref_ns, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) { hjx += CT(LN::c[i][0]) * f[i]; hjy += CT(LN::c[i][1]) * f[i]; }
       }
@@ -244,14 +337,31 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     s_psi[ry][rx] = hpsi;
     s_U[ry][rx] = hU;
     if constexpr (NS) { s_jx[ry][rx] = hjx; s_jy[ry][rx] = hjy; }
+  };
+  if (fast) {
+    constexpr int NH = RX * RY - TX * TY;
+    for (int k = tid; k < NH; k += NT) {
+      int rx, ry;
+      halo_pos<R>(k, rx, ry);
+      halo_node(rx, ry, bx0 + rx - R, by0 + ry - R, true);
+    }
+  } else {
+    for (int k = tid; k < RX * RY; k += NT) {
+      const int rx = k % RX, ry = k / RX;
+      const int tx = rx - R, ty = ry - R;
+      const int gx0 = bx0 + tx, gy0 = by0 + ty;
+      const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
+      if (inner && gx0 < P.nx && gy0 < P.ny) continue;   // filled in A1
+      halo_node(rx, ry, map_coord(gx0, P.nx, P.wall[0]), map_coord(gy0, P.ny, P.wall[1]), false);
+    }
   }
   __syncthreads();
 
   // ---- phase B: D_phi (x) v0 on the tile and ring 1 (mass-flux force)
-  FlowNode<CT, RX> fo;
+  FlowNode<CT> fo;
   if constexpr (FLOWX) {
     if (own) {
-      flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
+      flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
       s_X[0][ly + R][lx + R] = fo.Dx * fo.v0x;
       s_X[1][ly + R][lx + R] = fo.Dx * fo.v0y;
       s_X[2][ly + R][lx + R] = fo.Dy * fo.v0x;
@@ -278,8 +388,8 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       }
       CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
       if (!skip) {
-        FlowNode<CT, RX> h;
-        flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, my, mx, h);
+        FlowNode<CT> h;
+        flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, my, mx, h);
         X0 = sgn * h.Dx * h.v0x; X1 = sgn * h.Dx * h.v0y;
         X2 = sgn * h.Dy * h.v0x; X3 = sgn * h.Dy * h.v0y;
       }
@@ -287,7 +397,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     }
     __syncthreads();
   } else {
-    if (own) flow_node<NS, PHI, CT, RX>(P, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
+    if (own) flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, ly + R, lx + R, fo);
   }
   if (!own) return;
 
@@ -295,7 +405,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const int ry = ly + R, rx = lx + R;
   const CT h = (psi + CT(1)) * CT(0.5);
   const CT q = clamp01((CT(1) - psi) * CT(0.5));
-  CT theta = TH ? (H + h) : CT(P.theta0);
+  CT theta = TH ? (H + h) : K.theta0;
 
   // gradients of psi and U
   CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
@@ -303,23 +413,22 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   if constexpr (CC) grad9<CT, RX>(s_U, ry, rx, gUx, gUy);
   // unit normal and cubic anisotropy in the crystal frame of the nearest
   // seed: a_s = 1 + eps (4 S4 - 3 G^2) / (G + delta)^2, N' = G a_s d a_s/d g'
-  const CT dn = CT(P.delta_n2);
-  const CT invp = CT(1) / sqrt(gpx * gpx + gpy * gpy + dn);
+  const CT dn = K.dn;
+  const CT invp = rsq(gpx * gpx + gpy * gpy + dn);
   const CT ex = gpx * invp, ey = gpy * invp;
   CT a_s, Nx, Ny;
   {
-    const int gid = P.grain[idx];
     const CT cth = CT(P.grain_cs[2 * gid]), sth = CT(P.grain_cs[2 * gid + 1]);
     const CT rx_ = cth * gpx + sth * gpy;
     const CT ry_ = -sth * gpx + cth * gpy;
     const CT rx2 = rx_ * rx_, ry2 = ry_ * ry_;
     const CT G = rx2 + ry2;
     const CT S4 = rx2 * rx2 + ry2 * ry2;
-    const CT Gd = G + dn;
-    const CT inv2 = CT(1) / (Gd * Gd);
-    const CT eps = CT(P.eps4);
+    const CT invGd = rcp(G + dn);
+    const CT inv2 = invGd * invGd;
+    const CT eps = K.eps4;
     a_s = CT(1) + eps * (CT(4) * S4 - CT(3) * G * G) * inv2;
-    const CT pre = CT(4) * eps * G * a_s * inv2 / Gd;
+    const CT pre = CT(4) * eps * G * a_s * inv2 * invGd;
     const CT Nrx = pre * rx_ * (CT(4) * rx2 * G + (CT(4) * rx2 - CT(3) * G) * dn - CT(4) * S4);
     const CT Nry = pre * ry_ * (CT(4) * ry2 * G + (CT(4) * ry2 - CT(3) * G) * dn - CT(4) * S4);
     Nx = cth * Nrx - sth * Nry;
@@ -329,28 +438,28 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 
   // kinetics F(U)
   const CT lin = CT(1) + k1 * U;
-  const CT F = CT(P.inv_Le) + CT(P.Mcinf) * (lin > CT(0) ? lin : CT(0));
-  const CT gFx = lin > CT(0) ? CT(P.Mcinf) * k1 * gUx : CT(0);
-  const CT gFy = lin > CT(0) ? CT(P.Mcinf) * k1 * gUy : CT(0);
+  const CT F = K.inv_Le + K.Mcinf * (lin > CT(0) ? lin : CT(0));
+  const CT gFx = lin > CT(0) ? K.Mcinf * k1 * gUx : CT(0);
+  const CT gFy = lin > CT(0) ? K.Mcinf * k1 * gUy : CT(0);
 
   // psi source
   const CT om = CT(1) - phi;
   const CT ps1 = psi + CT(1);
   const CT f2p = CT(0.5) * (CT(1) - psi) * ps1 * (CT(-2) * psi);
-  const CT f3psi = CT(2) * CT(P.beta_inter) * om * om * ps1;
+  const CT f3psi = CT(2) * K.beta_inter * om * om * ps1;
   const CT s1m = (CT(1) - psi) * ps1;
   const CT pprime = CT(30.0 / 32.0) * s1m * s1m;
-  const CT Qpsi = -(f2p + f3psi + CT(P.lam) * pprime * (theta + CT(P.Mcinf) * U));
-  const CT invF = CT(1) / F;
-  const CT S_psi = CT(P.d_psi) * invF * invF * (gFx * (an * gpx + Nx) + gFy * (an * gpy + Ny)) +
-                   Qpsi * invF / CT(P.tau0);
-  const CT D_psi = CT(P.d_psi) * an * invF;
-  const CT rate_psi = CT(1) / (D_psi * CT(3) + CT(0.5));
+  const CT Qpsi = -(f2p + f3psi + K.lam * pprime * (theta + K.Mcinf * U));
+  const CT invF = rcp(F);
+  const CT S_psi = K.d_psi * invF * invF * (gFx * (an * gpx + Nx) + gFy * (an * gpy + Ny)) +
+                   Qpsi * invF * K.inv_tau0;
+  const CT D_psi = K.d_psi * an * invF;
+  const CT rate_psi = rcp(D_psi * CT(3) + CT(0.5));
 
-  // velocity, forces, pressure
+  // velocity, forces, pressure (pressure recovered in FP64 in every mode)
   CT vx = CT(0), vy = CT(0), Fx = CT(0), Fy = CT(0), p = CT(0);
   const CT rho = fo.rho;
-  const CT grx = CT(P.drho) * fo.gx, gry = CT(P.drho) * fo.gy;
+  const CT grx = K.drho * fo.gx, gry = K.drho * fo.gy;
   if constexpr (NS) {
     CT Fmx = CT(0), Fmy = CT(0);
     if constexpr (FLOWX) {
@@ -362,23 +471,25 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT ax1 = w1 * (Xs(1, 0, 1) - Xs(1, 0, -1)) + w2 * ((Xs(1, 1, 1) - Xs(1, 1, -1)) + (Xs(1, -1, 1) - Xs(1, -1, -1)));
       const CT ay2 = w1 * (Xs(2, 1, 0) - Xs(2, -1, 0)) + w2 * ((Xs(2, 1, 1) + Xs(2, 1, -1)) - (Xs(2, -1, -1) + Xs(2, -1, 1)));
       const CT ay3 = w1 * (Xs(3, 1, 0) - Xs(3, -1, 0)) + w2 * ((Xs(3, 1, 1) + Xs(3, 1, -1)) - (Xs(3, -1, -1) + Xs(3, -1, 1)));
-      Fmx = CT(P.drho) * CT(3) * (ax0 + ay2);
-      Fmy = CT(P.drho) * CT(3) * (ax1 + ay3);
+      Fmx = K.drho * CT(3) * (ax0 + ay2);
+      Fmy = K.drho * CT(3) * (ax1 + ay3);
     }
-    const CT Fby = -(rho - CT(P.rho_l)) * CT(P.g);
+    const CT Fby = -(rho - K.rho_l) * K.g;
     const CT rvx = jx + CT(0.5) * (fo.Fsx + Fmx);
     const CT rvy = jy + CT(0.5) * (fo.Fsy + Fby + Fmy);
     const CT onechi = CT(1) - fo.chi;
-    vx = onechi * rvx / rho;
-    vy = onechi * rvy / rho;
+    const CT irho = rcp(rho);
+    vx = onechi * rvx * irho;
+    vy = onechi * rvy * irho;
     Fx = fo.Fsx + Fmx - CT(2) * fo.chi * rvx;
     Fy = fo.Fsy + Fby + Fmy - CT(2) * fo.chi * rvy;
-    const CT vv = vx * vx + vy * vy;
-    const CT s0 = -CT(LN::w[0]) * vv * CT(1.5);
-    CT sum = CT(0);
+    const double vvd = (double)vx * vx + (double)vy * vy;
+    const double s0 = -LN::w[0] * vvd * 1.5;
+    double sum = 0.0;
 #pragma unroll
-    for (int i = 1; i < QN; ++i) sum += fns[i];
-    p = CT(LN::cs2) / (CT(1) - CT(LN::w[0])) * (sum + CT(0.5) * (vx * grx + vy * gry) + rho * s0);
+    for (int i = 1; i < QN; ++i) sum += (double)fns[i];
+    p = CT(LN::cs2 / (1.0 - LN::w[0]) *
+           (sum + 0.5 * ((double)vx * grx + (double)vy * gry) + (double)rho * s0));
   }
 
   if (mode == 1) {
@@ -395,18 +506,22 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     return;
   }
 
-  const bool first = P.first != 0;
-  raw* fo_ns = fout + (long long)(NS ? P.o_ns : 0) * N;
-  raw* fo_phi = fout + (long long)(PHI ? P.o_phi : 0) * N;
-  raw* fo_psi = fout + (long long)(PSI ? P.o_psi : 0) * N;
-  raw* fo_c = fout + (long long)(CC ? P.o_c : 0) * N;
-  raw* fo_th = fout + (long long)(TH ? P.o_th : 0) * N;
+  // stores: plane i of a set at byte (o + i) * N * S + idx * S
+  const uint32_t nbyte = (uint32_t)idx * S;
+  auto st = [&](int plane, CT v, float ref) {
+    if (P.fast) Store<ST>::st(at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte), v, ref);
+    else Store<ST>::st(fout + (long long)plane * N + idx, v, ref);
+  };
+  auto hst = [&](int plane, CT v) {
+    if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;
+    else hist[(long long)plane * N + idx] = (HT)v;
+  };
 
   // ---- NS collision: f* = feq + F/2 + (1 - s_nu) P_s (f - feq + F/2),
   // P_s the orthogonal projector on the moments c_x^2 - c_y^2 and c_x c_y
   if constexpr (NS) {
-    const CT nu = (CT(P.mu_g) + (CT(P.mu_l) - CT(P.mu_g)) * phi) / rho;
-    const CT s_nu = CT(1) / (nu * CT(3) + CT(0.5));
+    const CT nu = (K.mu_g + (K.mu_l - K.mu_g) * phi) * rcp(rho);
+    const CT s_nu = rcp(nu * CT(3) + CT(0.5));
     const CT vv = vx * vx + vy * vy;
     const CT vgr = vx * grx + vy * gry;
     const CT vF = vx * Fx + vy * Fy;
@@ -431,7 +546,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QN; ++i) {
       const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
       const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
-      Store<ST>::st(fo_ns + (long long)i * N + idx, fs, P.ref_ns[i]);
+      st(P.o_ns + i, fs, P.ref_ns[i]);
     }
   }
 
@@ -439,46 +554,46 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const CT phivx = phi * vx, phivy = phi * vy;
   if constexpr (PHI) {
     CT pvx0 = phivx, pvy0 = phivy;
-    if (!first) { pvx0 = CT(hist[(long long)P.h_phiv * N + idx]); pvy0 = CT(hist[(long long)(P.h_phiv + 1) * N + idx]); }
+    if (!first) { pvx0 = h_pv0; pvy0 = h_pv1; }
     const CT gx_ = (phivx - pvx0) + CT(LP::cs2) * fo.sharp * fo.nx;
     const CT gy_ = (phivy - pvy0) + CT(LP::cs2) * fo.sharp * fo.ny;
-    const CT s1 = CT(P.s_phi);
+    const CT s1 = K.s_phi;
     CT feq[QP], G[QP];
     CT jx_ = CT(0), jy_ = CT(0), gjx = CT(0), gjy = CT(0);
 #pragma unroll
     for (int i = 0; i < QP; ++i) {
       const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]);
       const CT w = CT(LP::w[i]);
-      feq[i] = w * phi * (CT(1) + (cx * vx + cy * vy) / CT(LP::cs2));
-      G[i] = w * (cx * gx_ + cy * gy_) / CT(LP::cs2);
+      feq[i] = w * phi * (CT(1) + (cx * vx + cy * vy) * CT(1.0 / LP::cs2));
+      G[i] = w * (cx * gx_ + cy * gy_) * CT(1.0 / LP::cs2);
       jx_ += cx * (fph[i] - feq[i]); jy_ += cy * (fph[i] - feq[i]);
       gjx += cx * G[i]; gjy += cy * G[i];
     }
-    const CT inv_fn = CT(1) / CT(LP::flux_norm);
+    const CT inv_fn = CT(1.0 / LP::flux_norm);
 #pragma unroll
     for (int i = 0; i < QP; ++i) {
       const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]);
       const CT Pf = (cx * jx_ + cy * jy_) * inv_fn;        // projector on the flux moments
       const CT PG = (cx * gjx + cy * gjy) * inv_fn;
       const CT fs = feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG;
-      Store<ST>::st(fo_phi + (long long)i * N + idx, fs, P.ref_phi[i]);
+      st(P.o_phi + i, fs, P.ref_phi[i]);
     }
-    hist[(long long)P.h_phiv * N + idx] = (HT)phivx;
-    hist[(long long)(P.h_phiv + 1) * N + idx] = (HT)phivy;
+    hst(P.h_phiv, phivx);
+    hst(P.h_phiv + 1, phivy);
   }
 
   // ---- AAC collision with the time-stretched store
   if constexpr (PSI) {
     CT Sprev = S_psi;
-    if (!first) Sprev = CT(hist[(long long)P.h_S * N + idx]);
-    const CT inv_an = CT(1) / an;
+    if (!first) Sprev = h_S;
+    const CT inv_an = rcp(an);
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT d = fps[i] - CT(LS::w[i]) * psi;
       jx_ += CT(LS::c[i][0]) * d; jy_ += CT(LS::c[i][1]) * d;
     }
-    const CT gNx = -Nx * inv_an, gNy = -Ny * inv_an;    // first moment of G / cs2 ... (G_i = -w_i c_i.N / a_s^2)
+    const CT gNx = -Nx * inv_an, gNy = -Ny * inv_an;    // G_i = -w_i c_i.N / a_s^2
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
@@ -486,27 +601,32 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT G = w * (cx * gNx + cy * gNy);
       const CT fstar = w * psi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
                        CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
-      const CT old = Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx, P.ref_psi[i]);
+      // f_i(x + c_i) before this step; across a wall it is the own f_opp(i)
+      const int dx = LS::c[i][0], dy = LS::c[i][1];
+      const bool across = !fast && ((P.wall[0] && (x + dx < 0 || x + dx >= P.nx)) ||
+                                    (P.wall[1] && (y + dy < 0 || y + dy >= P.ny)));
+      const CT old = across ? fps[LS::opp[i]] : s_fps[i][ry + dy][rx + dx];
       const CT fs = (fstar - (CT(1) - an) * old) * inv_an;
-      Store<ST>::st(fo_psi + (long long)i * N + idx, fs, P.ref_psi[i]);
+      st(P.o_psi + i, fs, P.ref_psi[i]);
     }
   }
 
   // ---- solute collision
   if constexpr (CC) {
     CT psi_prev = psi;
-    if (!first) psi_prev = CT(hist[(long long)P.h_psi * N + idx]);
-    const CT at = -CT(P.a_at) * CT(P.W0) * a_s * lin * (psi - psi_prev);
+    if (!first) psi_prev = h_psi;
+    const CT at = -K.aW0 * a_s * lin * (psi - psi_prev);
     const CT Jat_x = at * ex, Jat_y = at * ey;
-    const CT jv = CT(P.D) * q * C * CT(P.sharp) * (om > CT(0) ? om : CT(0));   // sqrt(2 beta_phi)/W_phi (phi_l - phi)+
+    const CT jv = K.D * q * C * K.sharp * (om > CT(0) ? om : CT(0));   // sqrt(2 beta_phi)/W_phi (phi_l - phi)+
     const CT Jx = jv * fo.nx, Jy = jv * fo.ny;
     const CT m = CT(1) - k1 * h;
-    const CT dr = CT(P.D) * q * C * k1 / (m * m) * CT(0.5);   // grad h = grad psi / 2
+    const CT invm = rcp(m);
+    const CT dr = K.D * q * C * k1 * invm * invm * CT(0.5);   // grad h = grad psi / 2
     const CT Bx = C * vx - dr * gpx + k1 * (Jat_x + Jx);
     const CT By = C * vy - dr * gpy + k1 * (Jat_y + Jy);
     CT Bpx = Bx, Bpy = By;
-    if (!first) { Bpx = CT(hist[(long long)P.h_B * N + idx]); Bpy = CT(hist[(long long)(P.h_B + 1) * N + idx]); }
-    const CT s1 = CT(1) / (CT(P.D) * q / m * CT(3) + CT(0.5));
+    if (!first) { Bpx = h_B0; Bpy = h_B1; }
+    const CT s1 = rcp(K.D * q * invm * CT(3) + CT(0.5));
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fc[i]; jy_ += CT(LS::c[i][1]) * fc[i]; }
@@ -519,18 +639,18 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT feq = w * C + w * (cx * Bx + cy * By) * CT(3);
       const CT G = w * (cx * dBx + cy * dBy) * CT(3);
       const CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      Store<ST>::st(fo_c + (long long)i * N + idx, fs, P.ref_c[i]);
+      st(P.o_c + i, fs, P.ref_c[i]);
     }
-    hist[(long long)P.h_B * N + idx] = (HT)Bx;
-    hist[(long long)(P.h_B + 1) * N + idx] = (HT)By;
+    hst(P.h_B, Bx);
+    hst(P.h_B + 1, By);
   }
 
   // ---- heat collision
   if constexpr (TH) {
     const CT Hvx = H * vx, Hvy = H * vy;
     CT Hpx = Hvx, Hpy = Hvy;
-    if (!first) { Hpx = CT(hist[(long long)P.h_Hv * N + idx]); Hpy = CT(hist[(long long)(P.h_Hv + 1) * N + idx]); }
-    const CT s1 = CT(P.s_th);
+    if (!first) { Hpx = h_Hv0; Hpy = h_Hv1; }
+    const CT s1 = K.s_th;
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fth[i]; jy_ += CT(LS::c[i][1]) * fth[i]; }
@@ -544,15 +664,15 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       if (i == 0) geq = H + (w - CT(1)) * theta;
       const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
       const CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      Store<ST>::st(fo_th + (long long)i * N + idx, gs, P.ref_th[i]);
+      st(P.o_th + i, gs, P.ref_th[i]);
     }
-    hist[(long long)P.h_Hv * N + idx] = (HT)Hvx;
-    hist[(long long)(P.h_Hv + 1) * N + idx] = (HT)Hvy;
+    hst(P.h_Hv, Hvx);
+    hst(P.h_Hv + 1, Hvy);
   }
 
   if constexpr (PSI) {
-    hist[(long long)P.h_psi * N + idx] = (HT)psi;
-    hist[(long long)P.h_S * N + idx] = (HT)S_psi;
+    hst(P.h_psi, psi);
+    hst(P.h_S, S_psi);
   }
 }
 
@@ -560,7 +680,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 template <int FIELDS, int QP, class ST, class HT, class CT>
 hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void* hist,
                            double* mout, int mode, hipStream_t s) {
-  dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY);
+  dim3 grid(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   using raw = typename Store<ST>::raw;
   hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT>), grid, dim3(NT), 0, s, P,
                      (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
