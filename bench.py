@@ -22,6 +22,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "step2d_alloy2d_1024.md")
+KERNEL_SOURCES = ("paper_2407_01651_amd/csrc/pfl_step2d.hip", "paper_2407_01651_amd/csrc/pfl_dev.h")
+
+
+def measured_traffic(store):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when the step kernel changed since those counters were taken."""
+    import hashlib
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    kv = dict(l.strip().split(": ", 1) for l in txt.splitlines() if ": " in l and l.startswith("    "))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    v = kv.get(f"traffic_bytes_per_launch_{store}")
+    return float(v) if v else None
 
 
 def parse():
@@ -149,7 +169,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_run["achieved_gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(a.store) if a.config == "alloy2d_1024" else None,
                      "bytes_per_node": main_run["bytes_per_node"]},
         "variants": {k: {"mlups": round(v["mlups"], 2), "ms_per_step": round(v["ms_per_step"], 6),
                          "achieved_gbs": round(v["achieved_gbs"], 1),
