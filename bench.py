@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--config", default="alloy2d_1024")
     ap.add_argument("--store", default="f64")
     ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
+    ap.add_argument("--extra", default="coupled2d_2048:f16,coupled2d_2048:bf16,coupled2d_2048:f32",
+                    help="comma list of config:storage pairs timed beside (variants)")
+    ap.add_argument("--rounding", default="stochastic", choices=("stochastic", "nearest"),
+                    help="rounding into 16-bit storage")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--calib", action="store_true",
@@ -87,10 +91,10 @@ def algorithmic_bytes(w, store):
     return 2 * q * sp + 2 * nh * sh
 
 
-def time_gpu(w, store, steps, warmup):
+def time_gpu(w, store, steps, warmup, rounding=None):
     import torch
     import paper_2407_01651_amd as pfl
-    sim = pfl.Sim(w, store=store)
+    sim = pfl.Sim(w, store=store, rounding=rounding)
     sim.init_fields()
     sim.step(warmup)
     stream = torch.cuda.current_stream()
@@ -145,10 +149,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_run = time_gpu(w, a.store, a.steps, a.warmup)
+    main_run = time_gpu(w, a.store, a.steps, a.warmup, a.rounding)
     variants = {}
     for st in [s for s in a.also.split(",") if s and s != a.store]:
-        variants[st] = time_gpu(w, st, a.steps, a.warmup)
+        variants[st] = time_gpu(w, st, a.steps, a.warmup, a.rounding)
+    for item in [s for s in a.extra.split(",") if s]:
+        cfg, st = item.split(":")
+        variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding)
     cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
     n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
     out = {

@@ -62,8 +62,18 @@ enum {
 /* Active equation sets (bit mask). */
 enum { PFL_NS = 1, PFL_PHI = 2, PFL_PSI = 4, PFL_C = 8, PFL_THETA = 16 };
 
-/* Population storage. Compute is FP64 for PFL_F64 and FP32 otherwise. */
+/* Population storage. Compute is FP64 for PFL_F64 and FP32 otherwise.
+ * PFL_F32, PFL_F16 and PFL_BF16 store each population as its deviation from
+ * the rest equilibrium of the bulk liquid; PFL_F64 stores it whole. */
 enum { PFL_F64 = 0, PFL_F32 = 1, PFL_F16 = 2, PFL_BF16 = 3 };
+
+/* Rounding of the FP32 step results into PFL_F16 / PFL_BF16 storage
+ * (ignored for PFL_F64 and PFL_F32).  Stochastic: round up with probability
+ * equal to the discarded fraction of an ulp, the random bits from a
+ * counter-based hash of (node, step counter, plane), so a run is reproducible;
+ * NaN and Inf are stored unchanged.  Nearest: the hardware conversion
+ * (round to nearest, ties to even). */
+enum { PFL_ROUND_STOCHASTIC = 0, PFL_ROUND_NEAREST = 1 };
 
 /* Macro-field planes written by pfl_get_macros (node form, in this order). */
 enum { PFL_M_PHI = 0, PFL_M_PSI, PFL_M_C, PFL_M_THETA, PFL_M_U, PFL_M_P,
@@ -89,6 +99,7 @@ typedef struct {
   uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
   int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
   int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */
+  int rounding;             /* PFL_ROUND_STOCHASTIC (default) or PFL_ROUND_NEAREST */
   double W0, tau0, eps4, k, PeD, Le, Mcinf, U0, theta0;
   double rho_l, rho_g, nu_l, nu_g, sigma, M_phi, xi, beta_inter, g;
   double delta_n2;          /* > 0: unit normals g / sqrt(|g|^2 + delta_n2); anisotropy

@@ -26,6 +26,7 @@ OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -
 NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
 F64, F32, F16, BF16 = 0, 1, 2, 3
 STORES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+ROUNDINGS = {"stochastic": 0, "nearest": 1}
 FIELD_BITS = {"ns": NS, "phi": PHI, "psi": PSI, "c": CONC, "theta": THETA}
 MACROS = ("phi", "psi", "C", "theta", "U", "p", "vx", "vy", "vz")
 
@@ -39,7 +40,8 @@ class PflError(RuntimeError):
 class Params(ct.Structure):
     _fields_ = [("abi_version", ct.c_uint32), ("struct_size", ct.c_uint32),
                 ("dim", ct.c_int), ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
-                ("wall", ct.c_int * 3), ("fields", ct.c_uint32), ("phi_q", ct.c_int), ("store", ct.c_int)] + \
+                ("wall", ct.c_int * 3), ("fields", ct.c_uint32), ("phi_q", ct.c_int), ("store", ct.c_int),
+                ("rounding", ct.c_int)] + \
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
                                           "beta_inter", "g", "delta_n2")]
@@ -96,8 +98,9 @@ def _check(rc):
     return rc
 
 
-def make_params(w, store=None):
-    """pfl_params from a workload description (primary inputs only)."""
+def make_params(w, store=None, rounding=None):
+    """pfl_params from a workload description (primary inputs only).
+    rounding: "stochastic" (default) or "nearest", for 16-bit storage."""
     p = Params()
     p.abi_version = ABI_VERSION
     p.struct_size = ct.sizeof(Params)
@@ -111,6 +114,7 @@ def make_params(w, store=None):
     p.fields = bits
     p.phi_q = w["phi_q"]
     p.store = STORES[store or w.get("store", "f64")]
+    p.rounding = ROUNDINGS[rounding or w.get("rounding", "stochastic")]
     for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0", "rho_l", "rho_g",
               "nu_l", "nu_g", "sigma", "M_phi", "xi", "beta_inter", "g", "delta_n2"):
         setattr(p, n, float(w[n]))
@@ -126,10 +130,10 @@ def query_sizes(p):
 class Sim:
     """One simulation on one GPU; buffers are torch tensors owned here."""
 
-    def __init__(self, w, store=None, device="cuda:0", stream=None):
+    def __init__(self, w, store=None, device="cuda:0", stream=None, rounding=None):
         self.w = w
         self.device = torch.device(device)
-        self.p = make_params(w, store)
+        self.p = make_params(w, store, rounding)
         self.dim = w["dim"]
         self.shape = (w["nz"], w["ny"], w["nx"]) if self.dim == 3 else (w["ny"], w["nx"])
         self.N = w["nx"] * w["ny"] * (w["nz"] if self.dim == 3 else 1)

@@ -56,6 +56,8 @@ int validate(const pfl_params* p) {
   if (p->dim == 3 && p->phi_q == 9) return fail(PFL_E_UNSUPPORTED, "phi on a 9-velocity lattice is 2D only");
   if (p->dim == 3 && p->phi_q != 7) return fail(PFL_E_INVALID_ARG, "phi_q must be 7 in 3D");
   if (p->store < PFL_F64 || p->store > PFL_BF16) return fail(PFL_E_INVALID_ARG, "bad storage type");
+  if (p->rounding != PFL_ROUND_STOCHASTIC && p->rounding != PFL_ROUND_NEAREST)
+    return fail(PFL_E_INVALID_ARG, "bad rounding mode");
   if (p->dim == 3) return fail(PFL_E_UNSUPPORTED, "3D step not built");
   if (!step2d_supported((int)f)) return fail(PFL_E_UNSUPPORTED, "field combination not built");
   if ((f & PFL_PHI) && (f & PFL_C) && !(f & PFL_THETA))
@@ -225,29 +227,35 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
     fill(d.kf);
     const size_t lim = (size_t)1 << 32;
     d.fast = (L.pops_bytes < lim && L.hist_bytes < lim) ? 1 : 0;
+    d.sr = ((p->store == PFL_F16 || p->store == PFL_BF16) && p->rounding == PFL_ROUND_STOCHASTIC) ? 1 : 0;
+    d.step_ctr = 0;
   }
   uint8_t* aux = (uint8_t*)bufs->aux;
   d.grain = aux;
   d.grain_cs = (const double*)(aux + L.aux_cs);
   d.seeds = (const double*)(aux + L.aux_seeds);
   d.bubbles = (const double*)(aux + L.aux_bub);
-  // deviation-storage references: rest equilibria of the bulk liquid
-  // (phi = 1, psi = -1, C = 1 + (1-k) U0, theta = theta0, v = p = 0)
-  const double w2_5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
-  const double w2_9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  const bool lowp = p->store == PFL_F16 || p->store == PFL_BF16;
-  if (lowp) {
-    const double* wsc = w2_5;
-    const double* wph = p->phi_q == 9 ? w2_9 : w2_5;
+  // rest equilibria r_i of the bulk liquid for the deviation storage
+  // (phi = 1, psi = -1, C = C_ref = 1 + (1-k) U0, theta = theta0, v = p = 0):
+  // r_i = w_i m_ref for every scalar set, 0 for the flow populations.  FP64
+  // storage keeps full populations (r_i = 0): it is the parity form.
+  {
+    const double on = p->store == PFL_F64 ? 0.0 : 1.0;
+    const double w2_5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    const double w2_9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double w3_7[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
+    const double* wsc = p->dim == 2 ? w2_5 : w3_7;
+    const double* wph = p->dim == 2 ? (p->phi_q == 9 ? w2_9 : w2_5) : w3_7;
     const double Cref = 1.0 + (1.0 - p->k) * p->U0;
-    for (int i = 0; i < L.q_ns; ++i) d.ref_ns[i] = 0.0f;
-    for (int i = 0; i < L.q_phi; ++i) d.ref_phi[i] = (float)wph[i];
+    for (int i = 0; i < L.q_ns; ++i) d.ref_ns[i] = 0.0;
+    for (int i = 0; i < L.q_phi; ++i) d.ref_phi[i] = on * wph[i] * 1.0;
     for (int i = 0; i < L.q_sc; ++i) {
-      d.ref_psi[i] = (float)(-wsc[i]);
-      d.ref_c[i] = (float)(wsc[i] * Cref);
-      d.ref_th[i] = (float)(wsc[i] * p->theta0);
+      d.ref_psi[i] = on * wsc[i] * -1.0;
+      d.ref_c[i] = on * wsc[i] * Cref;
+      d.ref_th[i] = on * wsc[i] * p->theta0;
     }
-    d.ref_th[0] = (float)(p->theta0 + (wsc[0] - 1.0) * p->theta0);
+    d.kd.C_ref = Cref;
+    d.kf.C_ref = (float)Cref;
   }
   *out = c;
   g_err.clear();
@@ -330,6 +338,7 @@ int pfl_step(pfl_ctx* c, int nsteps) {
     void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
     void* fout = c->cur == 0 ? c->b.pops_b : c->b.pops_a;
     bool ok = true;
+    c->d.step_ctr = (uint32_t)c->steps;
     hipError_t e = launch_step2d(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
     if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
     if (e != hipSuccess) return hip_fail(e, "step kernel");

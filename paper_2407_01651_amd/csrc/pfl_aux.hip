@@ -30,22 +30,24 @@ __device__ __forceinline__ long long slot(const DevParams& P, int x, int y, int 
 __device__ __forceinline__ int plane_of(long long sl, long long N) { return (int)(sl / N); }
 
 template <int Q, class ST>
-__device__ void scatter_set(const DevParams& P, typename Store<ST>::raw* base, const float* ref,
+__device__ void scatter_set(const DevParams& P, typename Store<ST>::raw* base, const double* ref,
                             int x, int y, int z, const double f[Q]) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const long long sl = slot<Q>(P, x, y, z, i);
-    Store<ST>::st(base + sl, f[i], ref[plane_of(sl, P.N)]);
+    // population i of this node lands in plane i, or opp(i) across a wall:
+    // either way it is a population of direction plane_of(sl) at its slot
+    Store<ST>::st(base + sl, f[i] - ref[i]);
   }
 }
 
 template <int Q, class ST>
-__device__ void gather_set(const DevParams& P, const typename Store<ST>::raw* base, const float* ref,
+__device__ void gather_set(const DevParams& P, const typename Store<ST>::raw* base, const double* ref,
                            int x, int y, int z, double f[Q]) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const long long sl = slot<Q>(P, x, y, z, i);
-    f[i] = Store<ST>::template ld<double>(base + sl, ref[plane_of(sl, P.N)]);
+    f[i] = Store<ST>::template ld<double>(base + sl) + ref[i];
   }
 }
 
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(BT) void state_kernel(const DevParams P, int fields
   const int y = (int)((n / P.nx) % P.ny);
   const int z = (int)(n / ((long long)P.nx * P.ny));
   long long plane = 0;
-  auto set = [&](auto qtag, int off, const float* ref) {
+  auto set = [&](auto qtag, int off, const double* ref) {
     constexpr int Q = decltype(qtag)::value;
     double f[Q];
     if (dir == 0) {
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(BT) void reduce_kernel(const DevParams P, int field
     const int z = (int)(n / ((long long)P.nx * P.ny));
     bool bad = false;
     double phi = 1.0, psi = -1.0, C = 0.0;
-    auto zeroth = [&](auto qtag, int off, const float* ref) {
+    auto zeroth = [&](auto qtag, int off, const double* ref) {
       constexpr int Q = decltype(qtag)::value;
       double f[Q];
       gather_set<Q, ST>(P, pops + (long long)off * P.N, ref, x, y, z, f);

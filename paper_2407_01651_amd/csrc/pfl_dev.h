@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace pfl {
 
@@ -67,6 +68,7 @@ template <class CT>
 struct KP {
   CT k1, inv_k1, U0, theta0, eps4, dn, d_psi, inv_tau0, D, lam, Mcinf, inv_Le, beta_inter;
   CT sharp, M_phi, Wphi2, k_s, rho_l, rho_g, drho, mu_l, mu_g, g, s_phi, s_th, aW0;
+  CT C_ref;                     // bulk solute 1 + (1-k) U0 of the deviation storage
 };
 
 // Everything a kernel needs, passed by value (well under the 4 KB limit).
@@ -92,44 +94,72 @@ struct DevParams {
   const double* seeds;         // x, y, z, r, angle per seed
   const double* bubbles;       // x, y, z, r per bubble
   int fast;                    // byte offsets of every buffer fit in 32 bits
+  int sr;                      // stochastic rounding of 16-bit stores
+  uint32_t step_ctr;           // step counter, part of the rounding key
   KP<double> kd;
   KP<float> kf;
-  // reference populations of the deviation storage (per set, per direction)
-  float ref_ns[19], ref_phi[19], ref_psi[7], ref_c[7], ref_th[7];
+  // rest equilibria r_i of the deviation storage (per set, per direction)
+  double ref_ns[19], ref_phi[19], ref_psi[7], ref_c[7], ref_th[7];
 };
 
 // --------------------------------------------------------- storage types
-// FP16/BF16 hold deviations from a per-direction reference value.
+// FP32, FP16 and BF16 storage hold deviations f_i - r_i from the rest
+// equilibrium r_i of the bulk liquid (phi = 1, psi = -1, C = C_ref,
+// theta = theta0, v = p = 0); FP64 storage holds full populations (r_i = 0).
+// The step kernel works on the stored values directly; the init and export
+// kernels add or remove r_i.
+// PCG hash (Jarzynski and Olano, "Hash Functions for GPU Rendering", JCGT
+// 2020): one LCG step of PCG followed by its RXS-M-XS output permutation.
+// A counter-based source of 32 random bits for stochastic rounding.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+  const uint32_t s = v * 747796405u + 2891336453u;
+  const uint32_t w = ((s >> ((s >> 28u) + 4u)) ^ s) * 277803737u;
+  return (w >> 22u) ^ w;
+}
+
+// Stochastic rounding of an FP32 value to a format keeping the top 32 - D
+// bits of its encoding: add D random bits to the magnitude bits and cut them
+// off; the result rounds up with probability equal to the discarded fraction.
+// NaN and Inf pass unchanged.  For FP16, values below its normal range lose
+// more than D bits and the conversion rounds the rest to nearest.
+template <int D>
+__device__ __forceinline__ float sround(float v, uint32_t r) {
+  uint32_t b = __float_as_uint(v);
+  if ((b & 0x7F800000u) != 0x7F800000u) {
+    constexpr uint32_t m = (1u << D) - 1u;
+    b = (b + (r & m)) & ~m;
+  }
+  return __uint_as_float(b);
+}
+
 struct half_dev { __half v; };
 struct bf16_dev { __hip_bfloat16 v; };
 
 template <class ST> struct Store;
 template <> struct Store<double> {
   using raw = double;
-  template <class CT> __device__ static CT ld(const raw* p, float) { return (CT)(*p); }
-  template <class CT> __device__ static void st(raw* p, CT v, float) { *p = (double)v; }
+  template <class CT> __device__ static CT ld(const raw* p) { return (CT)(*p); }
+  template <class CT> __device__ static void st(raw* p, CT v) { *p = (double)v; }
 };
 template <> struct Store<float> {
   using raw = float;
-  template <class CT> __device__ static CT ld(const raw* p, float) { return (CT)(*p); }
-  template <class CT> __device__ static void st(raw* p, CT v, float) { *p = (float)v; }
+  template <class CT> __device__ static CT ld(const raw* p) { return (CT)(*p); }
+  template <class CT> __device__ static void st(raw* p, CT v) { *p = (float)v; }
 };
 template <> struct Store<half_dev> {
   using raw = __half;
-  template <class CT> __device__ static CT ld(const raw* p, float ref) {
-    return (CT)(__half2float(*p) + ref);
-  }
-  template <class CT> __device__ static void st(raw* p, CT v, float ref) {
-    *p = __float2half_rn((float)v - ref);
+  template <class CT> __device__ static CT ld(const raw* p) { return (CT)__half2float(*p); }
+  template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2half_rn((float)v); }
+  template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
+    *p = __float2half_rn(sround<13>((float)v, r));
   }
 };
 template <> struct Store<bf16_dev> {
   using raw = __hip_bfloat16;
-  template <class CT> __device__ static CT ld(const raw* p, float ref) {
-    return (CT)(__bfloat162float(*p) + ref);
-  }
-  template <class CT> __device__ static void st(raw* p, CT v, float ref) {
-    *p = __float2bfloat16((float)v - ref);
+  template <class CT> __device__ static CT ld(const raw* p) { return (CT)__bfloat162float(*p); }
+  template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2bfloat16((float)v); }
+  template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
+    *p = __float2bfloat16(sround<16>((float)v, r));
   }
 };
 

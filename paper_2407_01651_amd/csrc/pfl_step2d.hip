@@ -10,6 +10,10 @@
 // Populations live in SoA planes (x fastest), post-collision at their source
 // node, so a node pulls f_i(x) from x - c_i; a population that would cross a
 // wall is read back from the node's own opposite slot (half-way bounce-back).
+// FP32 and 16-bit planes hold deviations f_i - w_i m_ref from the bulk-liquid
+// rest state and the collisions are written in those deviations, so that the
+// bulk, where f_i is close to w_i m_ref, rounds small numbers; FP64 planes
+// hold full populations.
 //
 // Tiles whose pulls stay inside the domain take a fast path: every load and
 // store is a scalar base plus a 32-bit byte offset, one integer add per
@@ -64,11 +68,11 @@ __device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::
   return (typename Store<ST>::raw*)((char*)base + b);
 }
 
-// Pull the pre-collision populations of one set at node (x, y), general
+// Pull the pre-collision population deviations of one set at node (x, y), general
 // addressing: periodic wrap or half-way bounce-back on each axis.
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
-                                             const DevParams& P, const float* ref, int x, int y, CT f[Q]) {
+                                             const DevParams& P, int x, int y, CT f[Q]) {
   using L = Lat<Q>;
   const long long N = P.N;
 #pragma unroll
@@ -81,31 +85,31 @@ __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __re
     else if (sy >= P.ny) { if (P.wall[1]) bounce = true; else sy -= P.ny; }
     const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
     const int plane = bounce ? L::opp[i] : i;
-    f[i] = Store<ST>::template ld<CT>(base + plane * N + idx, ref[plane]);
+    f[i] = Store<ST>::template ld<CT>(base + plane * N + idx);
   }
 }
 
 // Pull at an interior node: source x - c_i lies inside the domain.
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull_fast(const typename Store<ST>::raw* __restrict__ base,
-                                          const DevParams& P, const float* ref, uint32_t nbyte, CT f[Q]) {
+                                          const DevParams& P, uint32_t nbyte, CT f[Q]) {
   using L = Lat<Q>;
   constexpr uint32_t S = sizeof(typename Store<ST>::raw);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t rel = ((uint32_t)i * (uint32_t)P.N - (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx)) * S;
-    f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, rel + nbyte), ref[i]);
+    f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, rel + nbyte));
   }
 }
 
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull(bool fast, const typename Store<ST>::raw* __restrict__ base,
-                                     const DevParams& P, const float* ref, int x, int y, CT f[Q]) {
+                                     const DevParams& P, int x, int y, CT f[Q]) {
   if (fast) {
     const uint32_t nbyte = ((uint32_t)y * (uint32_t)P.nx + (uint32_t)x) * (uint32_t)sizeof(typename Store<ST>::raw);
-    pull_fast<Q, ST, CT>(base, P, ref, nbyte, f);
+    pull_fast<Q, ST, CT>(base, P, nbyte, f);
   } else {
-    pull_general<Q, ST, CT>(base, P, ref, x, y, f);
+    pull_general<Q, ST, CT>(base, P, x, y, f);
   }
 }
 
@@ -240,7 +244,15 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 
   // ---- phase A1: own node populations and moments
   CT fns[NS ? QN : 1], fph[PHI ? QP : 1], fps[PSI ? QS : 1], fc[CC ? QS : 1], fth[TH ? QS : 1];
+  // Moments are rest value + sum of stored values: phi = r_phi + dphi, ...
+  // Deviation storage (FP32, FP16, BF16) has r = (1, -1, C_ref, theta0);
+  // FP64 storage holds full populations, r = 0, and keeps the plain
+  // equilibrium forms below so its rounding follows the definitions.
+  constexpr bool DEV = !std::is_same<ST, double>::value;
+  const CT r_phi = DEV ? CT(1) : CT(0), r_psi = DEV ? CT(-1) : CT(0);
+  const CT r_C = DEV ? K.C_ref : CT(0), r_H = DEV ? K.theta0 : CT(0);
   CT phi = CT(1), psi = CT(-1), C = CT(0), H = CT(0), U = K.U0, jx = CT(0), jy = CT(0);
+  CT dphi = CT(0), dpsi = CT(0), dC = CT(0), dH = CT(0);
   // history and grain id of the own node, loaded early so that their latency
   // overlaps with the pulls
   const bool first = P.first != 0;
@@ -264,33 +276,35 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   }
   if (own) {
     if constexpr (NS) {
-      pull<QN, ST, CT>(fast, fin_ns, P, P.ref_ns, x, y, fns);
+      pull<QN, ST, CT>(fast, fin_ns, P, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) { jx += CT(LN::c[i][0]) * fns[i]; jy += CT(LN::c[i][1]) * fns[i]; }
     }
     if constexpr (PHI) {
-      pull<QP, ST, CT>(fast, fin_phi, P, P.ref_phi, x, y, fph);
-      phi = CT(0);
+      pull<QP, ST, CT>(fast, fin_phi, P, x, y, fph);
 #pragma unroll
-      for (int i = 0; i < QP; ++i) phi += fph[i];
+      for (int i = 0; i < QP; ++i) dphi += fph[i];
+      phi = r_phi + dphi;
     }
     if constexpr (PSI) {
-      pull<QS, ST, CT>(fast, fin_psi, P, P.ref_psi, x, y, fps);
-      psi = CT(0);
+      pull<QS, ST, CT>(fast, fin_psi, P, x, y, fps);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) { psi += fps[i]; s_fps[i][ly + R][lx + R] = fps[i]; }
+      for (int i = 0; i < QS; ++i) { dpsi += fps[i]; s_fps[i][ly + R][lx + R] = fps[i]; }
+      psi = r_psi + dpsi;
     }
     if constexpr (CC) {
-      pull<QS, ST, CT>(fast, fin_c, P, P.ref_c, x, y, fc);
+      pull<QS, ST, CT>(fast, fin_c, P, x, y, fc);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) C += fc[i];
+      for (int i = 0; i < QS; ++i) dC += fc[i];
+      C = r_C + dC;
       const CT h = (psi + CT(1)) * CT(0.5);
       U = (C * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull<QS, ST, CT>(fast, fin_th, P, P.ref_th, x, y, fth);
+      pull<QS, ST, CT>(fast, fin_th, P, x, y, fth);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) H += fth[i];
+      for (int i = 0; i < QS; ++i) dH += fth[i];
+      H = r_H + dH;
     }
     s_phi[ly + R][lx + R] = phi;
     s_psi[ly + R][lx + R] = psi;
@@ -304,31 +318,34 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hjx = CT(0), hjy = CT(0);
     if constexpr (PHI) {
       CT f[QP];
-      pull<QP, ST, CT>(hfast, fin_phi, P, P.ref_phi, gx, gy, f);
-      hphi = CT(0);
+      pull<QP, ST, CT>(hfast, fin_phi, P, gx, gy, f);
+      CT d = CT(0);
 #pragma unroll
-      for (int i = 0; i < QP; ++i) hphi += f[i];
+      for (int i = 0; i < QP; ++i) d += f[i];
+      hphi = r_phi + d;
     }
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull<QS, ST, CT>(hfast, fin_psi, P, P.ref_psi, gx, gy, f);
-        hpsi = CT(0);
+        pull<QS, ST, CT>(hfast, fin_psi, P, gx, gy, f);
+        CT d = CT(0);
 #pragma unroll
-        for (int i = 0; i < QS; ++i) { hpsi += f[i]; s_fps[i][ry][rx] = f[i]; }
+        for (int i = 0; i < QS; ++i) { d += f[i]; s_fps[i][ry][rx] = f[i]; }
+        hpsi = r_psi + d;
       }
       if constexpr (CC) {
         CT f[QS];
-        pull<QS, ST, CT>(hfast, fin_c, P, P.ref_c, gx, gy, f);
-        CT hC = CT(0);
+        pull<QS, ST, CT>(hfast, fin_c, P, gx, gy, f);
+        CT d = CT(0);
 #pragma unroll
-        for (int i = 0; i < QS; ++i) hC += f[i];
+        for (int i = 0; i < QS; ++i) d += f[i];
+        const CT hC = r_C + d;
         const CT h = (hpsi + CT(1)) * CT(0.5);
         hU = (hC * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
       }
       if constexpr (NS) {
         CT f[QN];
-        pull<QN, ST, CT>(hfast, fin_ns, P, P.ref_ns, gx, gy, f);
+        pull<QN, ST, CT>(hfast, fin_ns, P, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) { hjx += CT(LN::c[i][0]) * f[i]; hjy += CT(LN::c[i][1]) * f[i]; }
       }
@@ -508,9 +525,16 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 
   // stores: plane i of a set at byte (o + i) * N * S + idx * S
   const uint32_t nbyte = (uint32_t)idx * S;
-  auto st = [&](int plane, CT v, float ref) {
-    if (P.fast) Store<ST>::st(at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte), v, ref);
-    else Store<ST>::st(fout + (long long)plane * N + idx, v, ref);
+  // 16-bit storage: stochastic rounding keyed on (node, step, plane)
+  constexpr bool LOWP = sizeof(typename Store<ST>::raw) == 2;
+  const uint32_t hnode = LOWP ? pcg_hash((uint32_t)idx ^ pcg_hash(P.step_ctr)) : 0u;
+  auto st = [&](int plane, CT v) {
+    typename Store<ST>::raw* p = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
+                                        : fout + (long long)plane * N + idx;
+    if constexpr (LOWP) {
+      if (P.sr) { Store<ST>::st_sr(p, v, pcg_hash(hnode + (uint32_t)plane)); return; }
+    }
+    Store<ST>::st(p, v);
   };
   auto hst = [&](int plane, CT v) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;
@@ -546,7 +570,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QN; ++i) {
       const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
       const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
-      st(P.o_ns + i, fs, P.ref_ns[i]);
+      st(P.o_ns + i, fs);
     }
   }
 
@@ -564,7 +588,9 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QP; ++i) {
       const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]);
       const CT w = CT(LP::w[i]);
-      feq[i] = w * phi * (CT(1) + (cx * vx + cy * vy) * CT(1.0 / LP::cs2));
+      // equilibrium w phi (1 + c.v/cs2), less w under deviation storage
+      if constexpr (DEV) feq[i] = w * dphi + w * phi * (cx * vx + cy * vy) * CT(1.0 / LP::cs2);
+      else feq[i] = w * phi * (CT(1) + (cx * vx + cy * vy) * CT(1.0 / LP::cs2));
       G[i] = w * (cx * gx_ + cy * gy_) * CT(1.0 / LP::cs2);
       jx_ += cx * (fph[i] - feq[i]); jy_ += cy * (fph[i] - feq[i]);
       gjx += cx * G[i]; gjy += cy * G[i];
@@ -576,7 +602,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT Pf = (cx * jx_ + cy * jy_) * inv_fn;        // projector on the flux moments
       const CT PG = (cx * gjx + cy * gjy) * inv_fn;
       const CT fs = feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG;
-      st(P.o_phi + i, fs, P.ref_phi[i]);
+      st(P.o_phi + i, fs);
     }
     hst(P.h_phiv, phivx);
     hst(P.h_phiv + 1, phivy);
@@ -590,7 +616,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
-      const CT d = fps[i] - CT(LS::w[i]) * psi;
+      const CT d = fps[i] - CT(LS::w[i]) * dpsi;
       jx_ += CT(LS::c[i][0]) * d; jy_ += CT(LS::c[i][1]) * d;
     }
     const CT gNx = -Nx * inv_an, gNy = -Ny * inv_an;    // G_i = -w_i c_i.N / a_s^2
@@ -599,7 +625,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
       const CT w = CT(LS::w[i]);
       const CT G = w * (cx * gNx + cy * gNy);
-      const CT fstar = w * psi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
+      const CT fstar = w * dpsi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
                        CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
       // f_i(x + c_i) before this step; across a wall it is the own f_opp(i)
       const int dx = LS::c[i][0], dy = LS::c[i][1];
@@ -607,7 +633,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
                                     (P.wall[1] && (y + dy < 0 || y + dy >= P.ny)));
       const CT old = across ? fps[LS::opp[i]] : s_fps[i][ry + dy][rx + dx];
       const CT fs = (fstar - (CT(1) - an) * old) * inv_an;
-      st(P.o_psi + i, fs, P.ref_psi[i]);
+      st(P.o_psi + i, fs);
     }
   }
 
@@ -636,10 +662,10 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QS; ++i) {
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
       const CT w = CT(LS::w[i]);
-      const CT feq = w * C + w * (cx * Bx + cy * By) * CT(3);
+      const CT feq = w * dC + w * (cx * Bx + cy * By) * CT(3);
       const CT G = w * (cx * dBx + cy * dBy) * CT(3);
       const CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      st(P.o_c + i, fs, P.ref_c[i]);
+      st(P.o_c + i, fs);
     }
     hst(P.h_B, Bx);
     hst(P.h_B + 1, By);
@@ -651,6 +677,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     CT Hpx = Hvx, Hpy = Hvy;
     if (!first) { Hpx = h_Hv0; Hpy = h_Hv1; }
     const CT s1 = K.s_th;
+    const CT dtheta = dH + h;
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fth[i]; jy_ += CT(LS::c[i][1]) * fth[i]; }
@@ -660,11 +687,12 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QS; ++i) {
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
       const CT w = CT(LS::w[i]);
-      CT geq = w * theta + w * (cx * Hvx + cy * Hvy) * CT(3);
-      if (i == 0) geq = H + (w - CT(1)) * theta;
+      // equilibrium less r_i = w theta0 (dtheta = theta - r_H = dH + h)
+      CT geq = w * dtheta + w * (cx * Hvx + cy * Hvy) * CT(3);
+      if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
       const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
       const CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      st(P.o_th + i, gs, P.ref_th[i]);
+      st(P.o_th + i, gs);
     }
     hst(P.h_Hv, Hvx);
     hst(P.h_Hv + 1, Hvy);

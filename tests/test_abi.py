@@ -82,3 +82,14 @@ def test_error_message_is_thread_local_text():
     rc, _ = _code(w)
     assert rc == -1
     assert "viscosit" in pfl._lib.pfl_last_error().decode()
+
+
+def test_bad_rounding_mode_is_rejected():
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("coupled2d_128")
+    p = pfl.make_params(w, "f16", "nearest")
+    assert p.rounding == 1
+    p.rounding = 7
+    s = pfl.Sizes()
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    assert "rounding" in pfl._lib.pfl_last_error().decode()
