@@ -58,8 +58,8 @@ int validate(const pfl_params* p) {
   if (p->store < PFL_F64 || p->store > PFL_BF16) return fail(PFL_E_INVALID_ARG, "bad storage type");
   if (p->rounding != PFL_ROUND_STOCHASTIC && p->rounding != PFL_ROUND_NEAREST)
     return fail(PFL_E_INVALID_ARG, "bad rounding mode");
-  if (p->dim == 3) return fail(PFL_E_UNSUPPORTED, "3D step not built");
-  if (!step2d_supported((int)f)) return fail(PFL_E_UNSUPPORTED, "field combination not built");
+  if (!(p->dim == 3 ? step3d_supported((int)f) : step2d_supported((int)f)))
+    return fail(PFL_E_UNSUPPORTED, "field combination not built");
   if ((f & PFL_PHI) && (f & PFL_C) && !(f & PFL_THETA))
     return fail(PFL_E_UNSUPPORTED, "isothermal runs with bubbles and solute: F(U) vanishes in gas");
   if (!(p->W0 > 0) || !(p->tau0 > 0) || !(p->PeD > 0))
@@ -339,7 +339,7 @@ int pfl_step(pfl_ctx* c, int nsteps) {
     void* fout = c->cur == 0 ? c->b.pops_b : c->b.pops_a;
     bool ok = true;
     c->d.step_ctr = (uint32_t)c->steps;
-    hipError_t e = launch_step2d(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
+    hipError_t e = launch_step(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
     if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
     if (e != hipSuccess) return hip_fail(e, "step kernel");
     c->cur ^= 1;
@@ -355,7 +355,7 @@ int pfl_get_macros(pfl_ctx* c, void* dev_out) {
   if (!c->inited) return fail(PFL_E_STATE, "get_macros before init");
   void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   bool ok = true;
-  hipError_t e = launch_step2d(c->d, (int)c->p.fields, c->p.store, fin, nullptr, c->b.hist, (double*)dev_out, 1, c->s, ok);
+  hipError_t e = launch_step(c->d, (int)c->p.fields, c->p.store, fin, nullptr, c->b.hist, (double*)dev_out, 1, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
   if (e != hipSuccess) return hip_fail(e, "macros kernel");
   g_err.clear();

@@ -9,6 +9,16 @@ namespace pfl {
 hipError_t launch_step2d(const DevParams& P, int fields, int store, const void* fin, void* fout,
                          void* hist, double* mout, int mode, hipStream_t s, bool& ok);
 bool step2d_supported(int fields);
+hipError_t launch_step3d(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                         void* hist, double* mout, int mode, hipStream_t s, bool& ok);
+bool step3d_supported(int fields);
+
+// The step of the grid's dimension.
+inline hipError_t launch_step(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                              void* hist, double* mout, int mode, hipStream_t s, bool& ok) {
+  return P.dim == 3 ? launch_step3d(P, fields, store, fin, fout, hist, mout, mode, s, ok)
+                    : launch_step2d(P, fields, store, fin, fout, hist, mout, mode, s, ok);
+}
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
 // planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium

@@ -19,54 +19,11 @@
 // store is a scalar base plus a 32-bit byte offset, one integer add per
 // access.  Tiles on the domain edge use the general wrap/bounce addressing.
 #include "pfl_kernels.h"
+#include "pfl_util.h"
 
 namespace pfl {
 
 constexpr int TX = 32, TY = 8, NT = TX * TY;
-
-template <class CT>
-__device__ __forceinline__ CT clamp01(CT v) { return v < CT(0) ? CT(0) : (v > CT(1) ? CT(1) : v); }
-
-// Reciprocal and inverse square root: correctly rounded in FP64 (the parity
-// path), the hardware approximations (1 ulp) in FP32.
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
-// XCDs (workgroup b runs on XCD b mod 8), and each XCD has its own L2.  Give
-// XCD k a contiguous range of logical tiles in row-major order, i.e. a
-// horizontal band of the grid walked row by row, so tiles that share halo
-// rows and columns run on the same XCD at about the same time.
-constexpr int NXCD = 8;
-__device__ __forceinline__ void tile_of_block(int b, int gx, int gy, int& tx, int& ty) {
-  const int T = gx * gy;
-  const int q = T / NXCD, r = T % NXCD;
-  const int k = b % NXCD, j = b / NXCD;
-  const int L = k * q + (k < r ? k : r) + j;
-  ty = L / gx;
-  tx = L % gx;
-}
-
-// Map a (possibly out-of-domain) coordinate to the node whose value it
-// holds: periodic wrap, or mirror across a half-way wall (clamped so that
-// positions no valid node needs stay in range).
-__device__ __forceinline__ int map_coord(int g, int n, int wall) {
-  if (g >= 0 && g < n) return g;
-  if (!wall) { g %= n; if (g < 0) g += n; return g; }
-  g = g < 0 ? -1 - g : 2 * n - 1 - g;
-  return g < 0 ? 0 : (g >= n ? n - 1 : g);
-}
-
-template <class ST>
-__device__ __forceinline__ const typename Store<ST>::raw* at_byte(const typename Store<ST>::raw* base, uint32_t b) {
-  return (const typename Store<ST>::raw*)((const char*)base + b);
-}
-template <class ST>
-__device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::raw* base, uint32_t b) {
-  return (typename Store<ST>::raw*)((char*)base + b);
-}
 
 // Pull the pre-collision population deviations of one set at node (x, y), general
 // addressing: periodic wrap or half-way bounce-back on each axis.
@@ -223,8 +180,9 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
-  int tile_x, tile_y;
-  tile_of_block(blockIdx.x, (P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, tile_x, tile_y);
+  const int gtx = (P.nx + TX - 1) / TX;
+  const int lt = logical_tile(blockIdx.x, gtx * ((P.ny + TY - 1) / TY));
+  const int tile_x = lt % gtx, tile_y = lt / gtx;
   const int bx0 = tile_x * TX, by0 = tile_y * TY;
   const int x = bx0 + lx, y = by0 + ly;
   const bool own = (x < P.nx) && (y < P.ny);
@@ -531,10 +489,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   auto st = [&](int plane, CT v) {
     typename Store<ST>::raw* p = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
                                         : fout + (long long)plane * N + idx;
-    if constexpr (LOWP) {
-      if (P.sr) { Store<ST>::st_sr(p, v, pcg_hash(hnode + (uint32_t)plane)); return; }
-    }
-    Store<ST>::st(p, v);
+    store_pop<ST, CT>(P, p, v, hnode, plane);
   };
   auto hst = [&](int plane, CT v) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;
