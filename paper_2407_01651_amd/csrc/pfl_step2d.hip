@@ -485,11 +485,11 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const uint32_t nbyte = (uint32_t)idx * S;
   // 16-bit storage: stochastic rounding keyed on (node, step, plane)
   constexpr bool LOWP = sizeof(typename Store<ST>::raw) == 2;
-  const uint32_t hnode = LOWP ? pcg_hash((uint32_t)idx ^ pcg_hash(P.step_ctr)) : 0u;
+  RoundBits rb(LOWP ? round_seed(P, (uint32_t)idx) : 1u);
   auto st = [&](int plane, CT v) {
     typename Store<ST>::raw* p = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
                                         : fout + (long long)plane * N + idx;
-    store_pop<ST, CT>(P, p, v, hnode, plane);
+    store_pop<ST, CT>(P, p, v, rb);
   };
   auto hst = [&](int plane, CT v) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;

@@ -40,25 +40,38 @@ __device__ __forceinline__ long long nidx3(const DevParams& P, int x, int y, int
 }
 
 // Pull the stored values of one set at node (x, y, z), general addressing:
-// periodic wrap or half-way bounce-back on each axis.
+// periodic wrap or half-way bounce-back on each axis, from per-axis source
+// offsets computed once per node.
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __restrict__ base,
                                               const DevParams& P, int x, int y, int z, CT f[Q]) {
   using L = Lat<Q>;
-  const long long N = P.N;
-  const int n[3] = {P.nx, P.ny, P.nz};
+  AxisSrc ax, ay, az;
+  axis_src(x, P.nx, P.wall[0], 1, ax);
+  axis_src(y, P.ny, P.wall[1], P.nx, ay);
+  axis_src(z, P.nz, P.wall[2], P.nx * P.ny, az);
+  const int own = (z * P.ny + y) * P.nx + x;     // the node count is below 2^31
+  if (P.fast) {
+    constexpr uint32_t S = sizeof(typename Store<ST>::raw);
+    const uint32_t N = (uint32_t)P.N;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    int s[3] = {x - L::c[i][0], y - L::c[i][1], z - L::c[i][2]};
-    bool bounce = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (s[a] < 0) { if (P.wall[a]) bounce = true; else s[a] += n[a]; }
-      else if (s[a] >= n[a]) { if (P.wall[a]) bounce = true; else s[a] -= n[a]; }
+    for (int i = 0; i < Q; ++i) {
+      const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
+      const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
+      const uint32_t e = b ? (uint32_t)L::opp[i] * N + (uint32_t)own
+                           : (uint32_t)i * N + (uint32_t)(own + ax.off[cx] + ay.off[cy] + az.off[cz]);
+      f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, e * S));
     }
-    const long long id = bounce ? nidx3(P, x, y, z) : nidx3(P, s[0], s[1], s[2]);
-    const int plane = bounce ? L::opp[i] : i;
-    f[i] = Store<ST>::template ld<CT>(base + plane * N + id);
+  } else {
+    const long long N = P.N;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
+      const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
+      const long long e = b ? (long long)L::opp[i] * N + own
+                            : (long long)i * N + (own + ax.off[cx] + ay.off[cy] + az.off[cz]);
+      f[i] = Store<ST>::template ld<CT>(base + e);
+    }
   }
 }
 
@@ -84,7 +97,7 @@ template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull3(bool fast, const typename Store<ST>::raw* __restrict__ base,
                                       const DevParams& P, int x, int y, int z, CT f[Q]) {
   if (fast) {
-    const uint32_t nbyte = (uint32_t)nidx3(P, x, y, z) * (uint32_t)sizeof(typename Store<ST>::raw);
+    const uint32_t nbyte = (uint32_t)((z * P.ny + y) * P.nx + x) * (uint32_t)sizeof(typename Store<ST>::raw);
     pull3_fast<Q, ST, CT>(base, P, nbyte, f);
   } else {
     pull3_general<Q, ST, CT>(base, P, x, y, z, f);
@@ -504,11 +517,11 @@ __global__ __launch_bounds__(Tile3<CT>::NT) void step3d_kernel(const DevParams P
 
   const uint32_t nbyte = (uint32_t)idx * S;
   constexpr bool LOWP = sizeof(raw) == 2;
-  const uint32_t hnode = LOWP ? pcg_hash((uint32_t)idx ^ pcg_hash(P.step_ctr)) : 0u;
+  RoundBits rb(LOWP ? round_seed(P, (uint32_t)idx) : 1u);
   auto st = [&](int plane, CT val) {
     raw* ptr = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
                       : fout + (long long)plane * N + idx;
-    store_pop<ST, CT>(P, ptr, val, hnode, plane);
+    store_pop<ST, CT>(P, ptr, val, rb);
   };
   auto hst = [&](int plane, CT val) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)val;

@@ -47,15 +47,57 @@ __device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::
   return (typename Store<ST>::raw*)((char*)base + b);
 }
 
+// Random bits for the stochastic rounding of one node's stores.  The seed is
+// the PCG hash of (node, step); the stores of the node, in their fixed order,
+// take the two 16-bit halves of successive PCG hashes of a Weyl sequence
+// started from it, so runs are reproducible.  (A xorshift32 stream from the
+// same seed was cheaper but its correlated outputs gave about 1.6 times the
+// spread of the conserved-mass random walk.)
+struct RoundBits {
+  uint32_t s, cur;
+  bool half;
+  __device__ explicit RoundBits(uint32_t seed) : s(seed), cur(0u), half(false) {}
+  __device__ __forceinline__ uint32_t next16() {
+    if (half) { half = false; return cur >> 16; }
+    s += 0x9E3779B9u;
+    cur = pcg_hash(s);
+    half = true;
+    return cur & 0xFFFFu;
+  }
+};
+
+__device__ __forceinline__ uint32_t round_seed(const DevParams& P, uint32_t node) {
+  return pcg_hash(node ^ pcg_hash(P.step_ctr));
+}
+
 // Store of one post-collision value: 16-bit storage rounds stochastically
-// when P.sr is set, keyed on (node, step, plane).
+// when P.sr is set (the bits are drawn either way, so the draw order is fixed).
 template <class ST, class CT>
 __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>::raw* p, CT v,
-                                          uint32_t hnode, int plane) {
+                                          RoundBits& rb) {
   if constexpr (sizeof(typename Store<ST>::raw) == 2) {
-    if (P.sr) { Store<ST>::st_sr(p, v, pcg_hash(hnode + (uint32_t)plane)); return; }
+    const uint32_t r = rb.next16();
+    if (P.sr) { Store<ST>::st_sr(p, v, r); return; }
   }
   Store<ST>::st(p, v);
+}
+
+// Source offsets along one axis for a node at coordinate x: entry c + 1
+// holds the element offset of x - c (periodic wrap) and whether x - c lies
+// beyond a wall (then the population bounces back into the node's own
+// opposite slot).
+struct AxisSrc {
+  int off[3];
+  bool wall[3];
+};
+__device__ __forceinline__ void axis_src(int x, int n, int wall, int stride, AxisSrc& a) {
+  const bool hi = x + 1 >= n, lo = x - 1 < 0;
+  a.off[1] = 0;
+  a.wall[1] = false;
+  a.wall[0] = wall && hi;
+  a.off[0] = hi ? (wall ? 0 : (1 - n) * stride) : stride;
+  a.wall[2] = wall && lo;
+  a.off[2] = lo ? (wall ? 0 : (n - 1) * stride) : -stride;
 }
 
 }  // namespace pfl

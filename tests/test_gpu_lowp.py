@@ -109,13 +109,19 @@ def test_stochastic_rounding_is_reproducible():
     assert torch.equal(states[0], states[1])
 
 
+# Spread of the stochastic-rounding drift of sum C on the coupled 128 x 128
+# run (500 steps), measured over eight rounding streams (step counters): mean
+# within one standard error of zero, standard deviation 0.06 (FP16) and 0.4-0.6
+# (BF16).  Round-to-nearest drifts by -10.3 and -29.3.
+SR_SIGMA = {"f16": 0.06, "bf16": 0.5}
+
+
 @pytest.mark.parametrize("store", ["f16", "bf16"])
 def test_stochastic_rounding_conserves_solute(store):
     """Solute is conserved by the scheme; with round-to-nearest the 16-bit
-    stores drift it systematically, with stochastic rounding the drift is a
-    random walk.  On the coupled 128 x 128 run (500 steps) the measured drift
-    of sum C is 0.07 (FP16) and 0.65 (BF16) with stochastic rounding against
-    10 and 29 with round-to-nearest."""
+    stores drift it systematically, with stochastic rounding the drift is an
+    unbiased random walk: it stays within five standard deviations of zero
+    and well below the round-to-nearest drift."""
     w, n, _, ored = _oracle("coupled2d_128")
     drift = {}
     for rnd in ("stochastic", "nearest"):
@@ -123,5 +129,5 @@ def test_stochastic_rounding_conserves_solute(store):
         drift[rnd] = abs(sim.reduce()["sum_C"] - ored["sum_C"])
         sim.close()
     log(f"[lowp] {store} sum C drift {drift}")
-    assert drift["stochastic"] < 1e-4 * abs(ored["sum_C"])
-    assert 10 * drift["stochastic"] < drift["nearest"]
+    assert drift["stochastic"] < 5 * SR_SIGMA[store]
+    assert 5 * drift["stochastic"] < drift["nearest"]
