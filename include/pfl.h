@@ -118,6 +118,8 @@ typedef struct {
   size_t macros_bytes;      /* PFL_M_COUNT FP64 planes for pfl_get_macros */
   size_t state_bytes;       /* node-form FP64 populations + history (get/set_state) */
   size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce */
+  size_t adj_bytes;         /* FP64 scratch of pfl_step_backward / pfl_init_backward */
+  size_t raw_bytes;         /* raw image of the current state (pfl_save_raw) */
 } pfl_sizes;
 
 typedef struct {
@@ -125,6 +127,7 @@ typedef struct {
   void *hist;               /* hist_bytes */
   void *aux;                /* aux_bytes */
   void *reduce;             /* reduce_bytes */
+  void *adj;                /* adj_bytes, or NULL when no adjoint is taken */
 } pfl_buffers;
 
 /* Global FP64 diagnostics: sum phi, gas volume sum (phi_l - phi), sum C,
@@ -177,6 +180,36 @@ int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count);
 /* Global FP64 reductions; synchronises the stream.  Returns
  * PFL_E_NONFINITE (with *out filled) if the state holds NaN/Inf. */
 int pfl_reduce(pfl_ctx* c, pfl_diag* out);
+
+/* Checkpoints.  save_raw copies the current state (populations in their
+ * storage type, then history) into dev_dst (raw_bytes, caller-owned device
+ * memory) on the context's stream; load_raw makes such an image the current
+ * state with its step count and first-step flag, so that stepping from it
+ * repeats the original steps bit for bit (the stochastic rounding key is the
+ * step count).  Errors: PFL_E_STATE before init. */
+int pfl_save_raw(pfl_ctx* c, void* dev_dst);
+int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first);
+
+/* Adjoint of one time step (2D) at the current state x^n: given
+ * lambda^{n+1} = dL/dx^{n+1} (adj_in), writes lambda^n = (dx^{n+1}/dx^n)^T
+ * lambda^{n+1} (adj_out) and adds lambda^{n+1} . dx^{n+1}/d(eps4, k) to
+ * dparams[0], dparams[1].  x is the node-form state of pfl_get_state
+ * (state_bytes, FP64): pre-collision populations of every set, then the
+ * history planes; the step is differentiated in FP64 at the stored state
+ * whatever the storage type.  adj_in and adj_out are distinct caller-owned
+ * device buffers; dparams is a device FP64 vector [eps4, k, Omega, R_1..R_nbub]
+ * (accumulated).  The state is not changed.  Errors: PFL_E_STATE before init
+ * or without an adj buffer; PFL_E_UNSUPPORTED in 3D or for field
+ * combinations without an adjoint (built: all five sets, psi + C, psi + C +
+ * theta, NS + phi, psi alone). */
+int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double* dparams);
+
+/* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
+ * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling
+ * (theta0 = -Omega when the heat equation is solved, U0 = -Omega otherwise)
+ * and R_b the radius of bubble b.  Uses the seeds and bubbles of the last
+ * pfl_init_fields.  Errors as pfl_step_backward. */
+int pfl_init_backward(pfl_ctx* c, const double* adj0, double* dparams);
 
 /* Steps taken since the last init. */
 int64_t pfl_step_count(const pfl_ctx* c);

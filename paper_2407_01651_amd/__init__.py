@@ -57,11 +57,11 @@ class Bubble(ct.Structure):
 
 class Sizes(ct.Structure):
     _fields_ = [(n, ct.c_size_t) for n in ("pops_bytes", "hist_bytes", "aux_bytes", "macros_bytes",
-                                          "state_bytes", "reduce_bytes")]
+                                          "state_bytes", "reduce_bytes", "adj_bytes", "raw_bytes")]
 
 
 class Buffers(ct.Structure):
-    _fields_ = [(n, ct.c_void_p) for n in ("pops_a", "pops_b", "hist", "aux", "reduce")]
+    _fields_ = [(n, ct.c_void_p) for n in ("pops_a", "pops_b", "hist", "aux", "reduce", "adj")]
 
 
 class Diag(ct.Structure):
@@ -81,6 +81,10 @@ _sig = {
     "pfl_set_state": ([ct.c_void_p, ct.c_void_p, ct.c_int64], ct.c_int),
     "pfl_reduce": ([ct.c_void_p, _P(Diag)], ct.c_int),
     "pfl_step_count": ([ct.c_void_p], ct.c_int64),
+    "pfl_save_raw": ([ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_load_raw": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int], ct.c_int),
+    "pfl_step_backward": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_init_backward": ([ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_destroy": ([ct.c_void_p], ct.c_int),
     "pfl_last_error": ([], ct.c_char_p),
 }
@@ -130,7 +134,7 @@ def query_sizes(p):
 class Sim:
     """One simulation on one GPU; buffers are torch tensors owned here."""
 
-    def __init__(self, w, store=None, device="cuda:0", stream=None, rounding=None):
+    def __init__(self, w, store=None, device="cuda:0", stream=None, rounding=None, adjoint=False):
         self.w = w
         self.device = torch.device(device)
         self.p = make_params(w, store, rounding)
@@ -144,9 +148,11 @@ class Sim:
             return torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
         self.pops_a, self.pops_b = buf(s.pops_bytes), buf(s.pops_bytes)
         self.hist, self.aux, self.red = buf(s.hist_bytes), buf(s.aux_bytes), buf(s.reduce_bytes)
+        self.adj = buf(s.adj_bytes) if adjoint else None
         self.stream = stream or torch.cuda.current_stream(self.device)
         b = Buffers(self.pops_a.data_ptr(), self.pops_b.data_ptr(), self.hist.data_ptr(),
-                    self.aux.data_ptr(), self.red.data_ptr())
+                    self.aux.data_ptr(), self.red.data_ptr(),
+                    self.adj.data_ptr() if adjoint else None)
         ctx = ct.c_void_p()
         _check(_lib.pfl_create(ct.byref(ctx), ct.byref(self.p), ct.byref(b), ct.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
@@ -207,6 +213,29 @@ class Sim:
         st = state.to(self.device, torch.float64).contiguous()
         _check(_lib.pfl_set_state(self.ctx, ct.c_void_p(st.data_ptr()), int(step_count)))
         self._keep = st
+
+    # checkpoints and adjoint ----------------------------------------------------
+    def raw_buffer(self):
+        """A device buffer that holds one raw state image."""
+        return torch.empty(int(self.sizes.raw_bytes), dtype=torch.uint8, device=self.device)
+
+    def save_raw(self, dst):
+        _check(_lib.pfl_save_raw(self.ctx, ct.c_void_p(dst.data_ptr())))
+
+    def load_raw(self, src, step_count, first):
+        _check(_lib.pfl_load_raw(self.ctx, ct.c_void_p(src.data_ptr()), int(step_count), 1 if first else 0))
+
+    def state_planes(self):
+        return int(self.sizes.state_bytes // (8 * self.N))
+
+    def step_backward(self, lam_in, lam_out, dparams):
+        """lambda^n from lambda^{n+1} at the current state; FP64 device tensors of
+        the node-form state shape; dparams accumulates [eps4, k, Omega, R_b...]."""
+        _check(_lib.pfl_step_backward(self.ctx, ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
+                                      ct.c_void_p(dparams.data_ptr())))
+
+    def init_backward(self, lam0, dparams):
+        _check(_lib.pfl_init_backward(self.ctx, ct.c_void_p(lam0.data_ptr()), ct.c_void_p(dparams.data_ptr())))
 
     def reduce(self):
         d = Diag()

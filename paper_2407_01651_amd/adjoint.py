@@ -1,0 +1,139 @@
+"""Gradients of a morphology loss through the fused 2D step.
+
+The parameter vector is p = [eps4, k, Omega, R_1, ..., R_nb]: anisotropy
+strength, partition coefficient, undercooling (theta0 = -Omega when the heat
+equation is solved, U0 = -Omega otherwise) and the initial bubble radii.
+`run_with_gradient` evolves the workload at p for `steps` steps and returns
+the final phi and psi; its backward gives dL/dp for any loss L of them.
+
+Forward: one launch per step, with a raw checkpoint of the state (storage
+type, bit-exact) every K steps.  Backward, segment by segment from the last:
+the segment's states are recomputed from its checkpoint (same stochastic
+rounding keys, so bit-identical), then pfl_step_backward takes the node-form
+adjoint back one step at a time and accumulates dL/d(eps4, k); finally
+pfl_init_backward adds the gradient through the initial profiles.  Memory:
+one raw image per checkpoint plus K raw images for the segment being reversed.
+Every step of the path runs in the library's kernels; this module only
+orders the calls and holds the buffers.
+"""
+from __future__ import annotations
+
+import copy
+
+import torch
+
+from . import Sim
+
+
+def workload_at(w, p):
+    """Copy of workload w with the parameters of p (floats) applied."""
+    p = [float(v) for v in p]
+    w = copy.deepcopy(w)
+    w["eps4"] = p[0]
+    w["k"] = p[1]
+    if "theta" in w["fields"]:
+        w["theta0"] = -p[2]
+    else:
+        w["U0"] = -p[2]
+    for b, r in zip(w["bubbles"], p[3:]):
+        b["r"] = r
+    return w
+
+
+def params_of(w):
+    """p = [eps4, k, Omega, R_1..R_nb] of a workload."""
+    om = -w["theta0"] if "theta" in w["fields"] else -w["U0"]
+    return [w["eps4"], w["k"], om] + [b["r"] for b in w["bubbles"]]
+
+
+class CheckpointedRun:
+    """Forward with checkpoints and the adjoint sweep over it."""
+
+    def __init__(self, w, store="f64", K=100, device="cuda:0"):
+        self.w = w
+        self.K = int(K)
+        self.sim = Sim(w, store=store, device=device, adjoint=True)
+        self.ckpts = []
+        self.steps = 0
+
+    def forward(self, steps):
+        sim = self.sim
+        sim.init_fields()
+        self.ckpts = []
+        self.steps = int(steps)
+        for s0 in range(0, self.steps, self.K):
+            buf = sim.raw_buffer()
+            sim.save_raw(buf)
+            self.ckpts.append(buf)
+            sim.step(min(self.K, self.steps - s0))
+        return sim.macros()
+
+    def lam_from_macros(self, g_phi=None, g_psi=None):
+        """Node-form adjoint of a loss of the final phi and psi: each population
+        of a set carries the derivative with respect to its zeroth moment."""
+        sim = self.sim
+        P = sim.p
+        lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=torch.float64, device=sim.device)
+        q_phi = P.phi_q
+        q_sc = 5 if sim.dim == 2 else 7
+        q_ns = 9 if sim.dim == 2 else 19
+        o = 0
+        f = self.w["fields"]
+        if "ns" in f:
+            o += q_ns
+        if "phi" in f:
+            if g_phi is not None:
+                lam[o:o + q_phi] = g_phi.to(sim.device, torch.float64)
+            o += q_phi
+        if "psi" in f and g_psi is not None:
+            lam[o:o + q_sc] = g_psi.to(sim.device, torch.float64)
+        return lam
+
+    def backward(self, lam):
+        """dL/dp from the node-form adjoint lam of the final state."""
+        sim = self.sim
+        nb = len(self.w["bubbles"])
+        dparams = torch.zeros(3 + nb, dtype=torch.float64, device=sim.device)
+        lam = lam.contiguous().clone()
+        other = torch.empty_like(lam)
+        seg = [sim.raw_buffer() for _ in range(min(self.K, self.steps))]
+        for si in range(len(self.ckpts) - 1, -1, -1):
+            s0 = si * self.K
+            n = min(self.K, self.steps - s0)
+            sim.load_raw(self.ckpts[si], s0, s0 == 0)
+            for j in range(n):
+                sim.save_raw(seg[j])
+                sim.step(1)
+            for j in range(n - 1, -1, -1):
+                sim.load_raw(seg[j], s0 + j, s0 + j == 0)
+                sim.step_backward(lam, other, dparams)
+                lam, other = other, lam
+        sim.init_backward(lam, dparams)
+        return dparams
+
+    def close(self):
+        self.sim.close()
+
+
+class _Run(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, p, w, steps, K, store):
+        run = CheckpointedRun(workload_at(w, p.detach().cpu().tolist()), store=store, K=K,
+                              device=p.device if p.is_cuda else "cuda:0")
+        m = run.forward(steps)
+        ctx.run = run
+        return m["phi"].clone(), m["psi"].clone()
+
+    @staticmethod
+    def backward(ctx, g_phi, g_psi):
+        run = ctx.run
+        lam = run.lam_from_macros(g_phi, g_psi)
+        dp = run.backward(lam)
+        run.close()
+        return dp, None, None, None, None
+
+
+def run_with_gradient(p, w, steps, K=100, store="f64"):
+    """Final (phi, psi) of workload w at parameters p (1-D FP64 tensor
+    [eps4, k, Omega, R_1..R_nb]); differentiable with respect to p."""
+    return _Run.apply(p, w, int(steps), int(K), store)

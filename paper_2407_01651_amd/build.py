@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step3d.hip", "pfl_aux.hip"]
+SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step3d.hip", "pfl_adj2d.hip", "pfl_aux.hip"]
 OUT = os.path.join(HERE, "libpfl.so")
 
 FLAGS = [

@@ -156,6 +156,8 @@ int pfl_query_sizes(const pfl_params* p, pfl_sizes* out) {
   out->macros_bytes = L.macros_bytes;
   out->state_bytes = L.state_bytes;
   out->reduce_bytes = L.reduce_bytes;
+  out->adj_bytes = p->dim == 2 ? (size_t)adj_scratch_planes() * L.N * sizeof(double) : 0;
+  out->raw_bytes = L.pops_bytes + L.hist_bytes;
   g_err.clear();
   return PFL_OK;
 }
@@ -409,6 +411,68 @@ int pfl_reduce(pfl_ctx* c, pfl_diag* out) {
 }
 
 int64_t pfl_step_count(const pfl_ctx* c) { return c ? c->steps : -1; }
+
+int pfl_save_raw(pfl_ctx* c, void* dev_dst) {
+  if (!c || !dev_dst) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "save_raw before init");
+  const void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  hipError_t e = hipMemcpyAsync(dev_dst, pops, c->L.pops_bytes, hipMemcpyDeviceToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char*)dev_dst + c->L.pops_bytes, c->b.hist, c->L.hist_bytes, hipMemcpyDeviceToDevice, c->s);
+  if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first) {
+  if (!c || !dev_src) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "load_raw before init (the grain map comes from init)");
+  if (step_count < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  hipError_t e = hipMemcpyAsync(pops, dev_src, c->L.pops_bytes, hipMemcpyDeviceToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->b.hist, (const char*)dev_src + c->L.pops_bytes, c->L.hist_bytes,
+                       hipMemcpyDeviceToDevice, c->s);
+  if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  c->d.first = first ? 1 : 0;
+  c->steps = step_count;
+  g_err.clear();
+  return PFL_OK;
+}
+
+static int adj_check(pfl_ctx* c) {
+  if (!c) return fail(PFL_E_INVALID_ARG, "null context");
+  if (!c->inited) return fail(PFL_E_STATE, "adjoint before init");
+  if (!c->b.adj) return fail(PFL_E_STATE, "no adjoint scratch buffer (pfl_buffers.adj)");
+  if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
+  if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
+  return PFL_OK;
+}
+
+int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double* dparams) {
+  int rc = adj_check(c);
+  if (rc) return rc;
+  if (!adj_in || !adj_out || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (adj_in == adj_out) return fail(PFL_E_INVALID_ARG, "adj_in and adj_out must differ");
+  const void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  bool ok = true;
+  hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, adj_in, adj_out,
+                                   (double*)c->b.adj, dparams, c->s, ok);
+  if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
+  if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_init_backward(pfl_ctx* c, const double* adj0, double* dparams) {
+  int rc = adj_check(c);
+  if (rc) return rc;
+  if (!adj0 || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
+  hipError_t e = launch_adj_init2d(c->d, (int)c->p.fields, adj0, (double*)c->b.adj, dparams, c->s);
+  if (e != hipSuccess) return hip_fail(e, "initial-state adjoint kernels");
+  g_err.clear();
+  return PFL_OK;
+}
 
 int pfl_destroy(pfl_ctx* c) {
   delete c;

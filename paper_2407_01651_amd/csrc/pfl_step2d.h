@@ -1,0 +1,136 @@
+// 2D step building blocks shared by the forward step and its adjoint: tile
+// shape, pulls (general and 32-bit fast addressing), halo enumeration,
+// isotropic D2Q9 stencils on an LDS tile, and the flow quantities of one
+// tile position.
+#pragma once
+#include "pfl_util.h"
+
+namespace pfl {
+
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+
+// Pull the pre-collision population deviations of one set at node (x, y), general
+// addressing: periodic wrap or half-way bounce-back on each axis.
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
+                                             const DevParams& P, int x, int y, CT f[Q]) {
+  using L = Lat<Q>;
+  const long long N = P.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int sx = x - L::c[i][0], sy = y - L::c[i][1];
+    bool bounce = false;
+    if (sx < 0) { if (P.wall[0]) bounce = true; else sx += P.nx; }
+    else if (sx >= P.nx) { if (P.wall[0]) bounce = true; else sx -= P.nx; }
+    if (sy < 0) { if (P.wall[1]) bounce = true; else sy += P.ny; }
+    else if (sy >= P.ny) { if (P.wall[1]) bounce = true; else sy -= P.ny; }
+    const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
+    const int plane = bounce ? L::opp[i] : i;
+    f[i] = Store<ST>::template ld<CT>(base + plane * N + idx);
+  }
+}
+
+// Pull at an interior node: source x - c_i lies inside the domain.
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull_fast(const typename Store<ST>::raw* __restrict__ base,
+                                          const DevParams& P, uint32_t nbyte, CT f[Q]) {
+  using L = Lat<Q>;
+  constexpr uint32_t S = sizeof(typename Store<ST>::raw);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t rel = ((uint32_t)i * (uint32_t)P.N - (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx)) * S;
+    f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, rel + nbyte));
+  }
+}
+
+template <int Q, class ST, class CT>
+__device__ __forceinline__ void pull(bool fast, const typename Store<ST>::raw* __restrict__ base,
+                                     const DevParams& P, int x, int y, CT f[Q]) {
+  if (fast) {
+    const uint32_t nbyte = ((uint32_t)y * (uint32_t)P.nx + (uint32_t)x) * (uint32_t)sizeof(typename Store<ST>::raw);
+    pull_fast<Q, ST, CT>(base, P, nbyte, f);
+  } else {
+    pull_general<Q, ST, CT>(base, P, x, y, f);
+  }
+}
+
+// Halo position k (0 <= k < RX*RY - TX*TY) of an R-ring tile: the R top
+// rows, the R bottom rows, then the side columns.
+template <int R>
+__device__ __forceinline__ void halo_pos(int k, int& rx, int& ry) {
+  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  if (k < R * RX) { ry = k / RX; rx = k % RX; return; }
+  k -= R * RX;
+  if (k < R * RX) { ry = RY - R + k / RX; rx = k % RX; return; }
+  k -= R * RX;
+  ry = R + k / (2 * R);
+  const int c = k % (2 * R);
+  rx = c < R ? c : TX + c;
+}
+
+// Isotropic D2Q9 gradient and Laplacian from an LDS array.
+template <class CT, int RX>
+__device__ __forceinline__ void grad9(const CT (*s)[RX], int ry, int rx, CT& gx, CT& gy) {
+  const CT e = s[ry][rx + 1], wv = s[ry][rx - 1], n = s[ry + 1][rx], so = s[ry - 1][rx];
+  const CT ne = s[ry + 1][rx + 1], nw = s[ry + 1][rx - 1], sw = s[ry - 1][rx - 1], se = s[ry - 1][rx + 1];
+  gx = CT(3) * (CT(1.0 / 9) * (e - wv) + CT(1.0 / 36) * ((ne - nw) + (se - sw)));
+  gy = CT(3) * (CT(1.0 / 9) * (n - so) + CT(1.0 / 36) * ((ne + nw) - (sw + se)));
+}
+template <class CT, int RX>
+__device__ __forceinline__ CT lap9(const CT (*s)[RX], int ry, int rx) {
+  const CT c = s[ry][rx];
+  const CT ax = (s[ry][rx + 1] - c) + (s[ry][rx - 1] - c) + (s[ry + 1][rx] - c) + (s[ry - 1][rx] - c);
+  const CT dg = (s[ry + 1][rx + 1] - c) + (s[ry + 1][rx - 1] - c) + (s[ry - 1][rx - 1] - c) + (s[ry - 1][rx + 1] - c);
+  return CT(6) * (CT(1.0 / 9) * ax + CT(1.0 / 36) * dg);
+}
+
+// Flow quantities at one LDS position (node or ring 1): chemical potential,
+// surface tension, phi diffusion flux, velocity without the mass-flux force.
+template <class CT>
+struct FlowNode {
+  CT gx, gy, lap, nx, ny, Fsx, Fsy, Dx, Dy, rho, chi, v0x, v0y, sharp;
+};
+
+template <bool NS, bool PHI, class CT, int RX, class JA>
+__device__ __forceinline__ void flow_node(const KP<CT>& K, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
+                                          const JA& s_jx, const JA& s_jy, int ry, int rx, FlowNode<CT>& o) {
+  const CT phi = s_phi[ry][rx];
+  const CT psi = s_psi[ry][rx];
+  if constexpr (PHI) {
+    grad9<CT, RX>(s_phi, ry, rx, o.gx, o.gy);
+    o.lap = lap9<CT, RX>(s_phi, ry, rx);
+  } else {
+    o.gx = o.gy = o.lap = CT(0);
+  }
+  // unit normal, regularised where the gradient vanishes
+  const CT inv = rsq(o.gx * o.gx + o.gy * o.gy + K.dn);
+  o.nx = o.gx * inv;
+  o.ny = o.gy * inv;
+  // phi_l = 1, phi_g = 0, psi_l = -1, beta_phi = 1/4
+  const CT one_m = CT(1) - phi;
+  // double-well factor of the sharpening flux, zero outside [phi_g, phi_l]
+  const CT dw = one_m * phi;
+  o.sharp = K.sharp * (dw > CT(0) ? dw : CT(0));
+  o.Dx = K.M_phi * (o.gx - o.sharp * o.nx);
+  o.Dy = K.M_phi * (o.gy - o.sharp * o.ny);
+  const CT h = (psi + CT(1)) * CT(0.5);
+  o.chi = clamp01(h);
+  o.rho = K.rho_g + K.drho * phi;
+  if constexpr (NS) {
+    const CT f1p = CT(0.5) * one_m * phi * (CT(1) - CT(2) * phi);
+    const CT ps1 = psi + CT(1);
+    const CT f3p = CT(-2) * K.beta_inter * one_m * ps1 * ps1;
+    const CT mu = f1p + f3p - K.Wphi2 * o.lap;
+    o.Fsx = K.k_s * mu * o.gx;
+    o.Fsy = K.k_s * mu * o.gy;
+    // buoyancy relative to the liquid: its hydrostatic head is carried by p
+    const CT Fbx = CT(0), Fby = -(o.rho - K.rho_l) * K.g;
+    const CT s = (CT(1) - o.chi) * rcp(o.rho);
+    o.v0x = s * (s_jx[ry][rx] + CT(0.5) * (o.Fsx + Fbx));
+    o.v0y = s * (s_jy[ry][rx] + CT(0.5) * (o.Fsy + Fby));
+  } else {
+    o.Fsx = o.Fsy = o.v0x = o.v0y = CT(0);
+  }
+}
+
+}  // namespace pfl

@@ -1,0 +1,167 @@
+"""The hand-written adjoint of the 2D step (pfl_step_backward,
+pfl_init_backward) against the reference adjoint of the CPU oracle
+(autograd through the oracle's step, itself pinned against central
+differences), and the checkpointed gradient of a morphology loss against
+the oracle and against central finite differences of the GPU forward.
+
+Bars: one-step adjoint and parameter derivatives 1e-9 normwise relative
+(FP64 on both sides; only summation order differs); full-run gradient 1e-7
+relative against the oracle and 1e-4 relative against central differences
+with step 1e-3 of each parameter (the truncation error of the difference
+quotient is the limit there).
+"""
+import math
+
+import pytest
+import torch
+
+import workloads
+from adjoint_ref import flatten, init_vjp, run_loss, step_vjp
+from oracle import OracleParams, OracleSim
+from parity_util import log
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+CASES = [
+    # name, workload overrides, steps before the differentiated step
+    ("all_walls_20x14", dict(nx=20, ny=14, seed=31), 4),
+    ("all_first_step_19x13", dict(nx=19, ny=13, seed=32), 0),
+    ("all_periodic_34x18", dict(nx=34, ny=18, seed=33, periodic=(True, True, True)), 3),
+    ("all_xwalls_gravity_17x22", dict(nx=17, ny=22, seed=34, periodic=(False, True, True), g=2e-4,
+                                      rho_g=0.01), 3),
+    ("alloy_periodic_35x12", dict(nx=35, ny=12, seed=35, fields=("psi", "c"), periodic=(True, True, True),
+                                  Le=math.inf, U0=-0.55, theta0=0.0, tau0=50.0), 5),
+    ("alloy_theta_18x11", dict(nx=18, ny=11, seed=36, fields=("psi", "c", "theta")), 3),
+    ("nsphi_21x21", dict(nx=21, ny=21, seed=37, fields=("ns", "phi")), 4),
+    ("psi_only_16x16", dict(nx=16, ny=16, seed=38, fields=("psi",), Le=math.inf, theta0=-0.3), 3),
+]
+
+
+def _w(over):
+    over = dict(over)
+    nx, ny, seed = over.pop("nx"), over.pop("ny"), over.pop("seed")
+    fields = over.pop("fields", workloads.FIELDS_ALL)
+    periodic = over.pop("periodic", None)
+    w = workloads.small(nx=nx, ny=ny, seed=seed, fields=fields, periodic=periodic)
+    w.update(over)
+    return w
+
+
+def _relerr(a, b):
+    den = float(b.abs().max())
+    return float((a - b).abs().max()) / (den if den > 0 else 1.0)
+
+
+@pytest.mark.parametrize("name,over,n_pre", CASES, ids=[c[0] for c in CASES])
+def test_step_adjoint_matches_oracle(name, over, n_pre):
+    import paper_2407_01651_amd as pfl
+    w = _w(over)
+    log(f"[adjoint] {name} after {n_pre} steps")
+    osim = OracleSim(OracleParams.from_workload(w))
+    osim.init_fields()
+    shape = flatten(osim.state, w["fields"]).shape
+    g = torch.Generator().manual_seed(101)
+    lam_next = torch.randn(shape, generator=g, dtype=torch.float64)
+    lam_ref, d_eps, d_k = step_vjp(w, n_pre, lam_next)
+    sim = pfl.Sim(w, adjoint=True)
+    sim.init_fields()
+    sim.step(n_pre)
+    lin = lam_next.cuda()
+    lout = torch.empty_like(lin)
+    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
+    sim.step_backward(lin, lout, dp)
+    torch.cuda.synchronize()
+    err = _relerr(lout.cpu(), lam_ref)
+    dpc = dp.cpu()
+    log(f"[adjoint] {name} lambda {err:.2e} d_eps {float(dpc[0]):.6e}/{d_eps:.6e} "
+        f"d_k {float(dpc[1]):.6e}/{d_k:.6e}")
+    # per-plane check names the first plane that disagrees
+    for i in range(shape[0]):
+        e = float((lout[i].cpu() - lam_ref[i]).abs().max()) / max(float(lam_ref.abs().max()), 1e-300)
+        assert e < TOL, (name, "plane", i, e)
+    assert err < TOL
+    scale = max(abs(d_eps), abs(d_k), 1e-300)
+    assert abs(float(dpc[0]) - d_eps) <= TOL * max(abs(d_eps), 1e-3 * scale)
+    assert abs(float(dpc[1]) - d_k) <= TOL * max(abs(d_k), 1e-3 * scale)
+    sim.close()
+
+
+@pytest.mark.parametrize("fields", [workloads.FIELDS_ALL, ("psi", "c")], ids=["all", "alloy"])
+def test_init_adjoint_matches_oracle(fields):
+    import paper_2407_01651_amd as pfl
+    w = _w(dict(nx=30, ny=26, seed=39, fields=fields))
+    if "phi" in fields:
+        w["bubbles"].append(dict(x=5.0, y=20.0, z=0.0, r=3.5))
+    else:
+        w.update(Le=math.inf, U0=-0.4, theta0=0.0)
+    osim = OracleSim(OracleParams.from_workload(w))
+    osim.init_fields()
+    g = torch.Generator().manual_seed(5)
+    lam0 = torch.randn(flatten(osim.state, fields).shape, generator=g, dtype=torch.float64)
+    ref = init_vjp(w, lam0)
+    sim = pfl.Sim(w, adjoint=True)
+    sim.init_fields()
+    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
+    sim.init_backward(lam0.cuda(), dp)
+    got = dp.cpu().tolist()[1:]
+    log(f"[adjoint] init {got} vs {ref}")
+    for a, b in zip(got, ref):
+        assert abs(a - b) <= TOL * max(abs(b), 1e-6 * max(abs(v) for v in ref)), (got, ref)
+    sim.close()
+
+
+def _target(w, steps, p_shift):
+    """Target phi*, psi*: the forward model at perturbed parameters."""
+    from paper_2407_01651_amd.adjoint import CheckpointedRun, params_of, workload_at
+    p = params_of(w)
+    pt = [a + b for a, b in zip(p, p_shift)]
+    run = CheckpointedRun(workload_at(w, pt), K=max(steps, 1))
+    m = run.forward(steps)
+    run.close()
+    return m["phi"].clone(), m["psi"].clone()
+
+
+def _gpu_loss(w, p, steps, phi_t, psi_t):
+    from paper_2407_01651_amd.adjoint import CheckpointedRun, workload_at
+    run = CheckpointedRun(workload_at(w, p), K=max(steps, 1))
+    m = run.forward(steps)
+    run.close()
+    return float(((m["phi"] - phi_t) ** 2).sum() + ((m["psi"] - psi_t) ** 2).sum())
+
+
+def test_checkpointed_gradient_matches_oracle_and_fd():
+    """Loss of phi and psi after 60 steps on a 40 x 36 copy of the adjoint
+    workload, target from perturbed parameters; checkpoints every 16 steps
+    (four segments, the last one partial)."""
+    from paper_2407_01651_amd.adjoint import params_of, run_with_gradient
+    w = workloads.get("adjoint2d_64")
+    w.update(nx=40, ny=36, seeds=[dict(x=20.0, y=14.0, z=0.0, r=4.0, angle=0.3)],
+             bubbles=[dict(x=10.0, y=27.0, z=0.0, r=6.0), dict(x=30.0, y=28.0, z=0.0, r=5.0)])
+    steps = 60
+    phi_t, psi_t = _target(w, steps, [0.01, 0.02, 0.03, 0.5, -0.4])
+    p0 = params_of(w)
+    p = torch.tensor(p0, dtype=torch.float64, device="cuda", requires_grad=True)
+    phi, psi = run_with_gradient(p, w, steps, K=16)
+    L = ((phi - phi_t) ** 2).sum() + ((psi - psi_t) ** 2).sum()
+    L.backward()
+    g = p.grad.cpu().tolist()
+    # oracle reverse-mode reference
+    pt = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in p0]
+    Lo = run_loss(w, pt, steps, phi_t.cpu(), psi_t.cpu())
+    Lo.backward()
+    gref = [float(t.grad) for t in pt]
+    log(f"[adjoint] L gpu {float(L):.10e} oracle {float(Lo):.10e}")
+    log(f"[adjoint] grad gpu {g}")
+    log(f"[adjoint] grad ref {gref}")
+    gmax = max(abs(v) for v in gref)
+    for a, b in zip(g, gref):
+        assert abs(a - b) <= 1e-7 * max(abs(b), 1e-3 * gmax), (g, gref)
+    # central differences of the GPU forward, step 1e-3
+    h = 1e-3
+    for j in range(len(p0)):
+        pp = list(p0); pm = list(p0)
+        pp[j] += h; pm[j] -= h
+        fd = (_gpu_loss(w, pp, steps, phi_t, psi_t) - _gpu_loss(w, pm, steps, phi_t, psi_t)) / (2 * h)
+        log(f"[adjoint] fd {j}: {fd:.8e} adjoint {g[j]:.8e}")
+        assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
