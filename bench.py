@@ -56,6 +56,8 @@ def parse():
                     help="comma list of config:storage pairs timed beside (variants)")
     ap.add_argument("--rounding", default="stochastic", choices=("stochastic", "nearest"),
                     help="rounding into 16-bit storage")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward cost ratio on the 512^2 adjoint workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--calib", action="store_true",
@@ -116,6 +118,59 @@ def time_gpu(w, store, steps, warmup, rounding=None):
                 achieved_gbs=gbs, nonfinite=r["nonfinite"], solid_fraction=r["solid_fraction"])
 
 
+def time_adjoint(name="adjoint2d_512", store="f32", K=100):
+    """Cost of the gradient of a morphology loss relative to the plain forward:
+    (forward with checkpoints every K steps + checkpointed adjoint sweep) /
+    (forward), both over the workload's full step count, HIP events on the
+    stream the library launches on.  The loss target is the forward model at
+    perturbed parameters (computed outside the timed region)."""
+    import torch
+    import workloads
+    import paper_2407_01651_amd as pfl
+    from paper_2407_01651_amd.adjoint import CheckpointedRun, params_of, workload_at
+    w = workloads.get(name)
+    steps = w["steps"]
+    p = params_of(w)
+    tgt = CheckpointedRun(workload_at(w, [a + b for a, b in zip(p, [0.005, 0.01, 0.02] + [0.5] * (len(p) - 3))]),
+                          store=store, K=steps)
+    mt = tgt.forward(steps)
+    phi_t, psi_t = mt["phi"].clone(), mt["psi"].clone()
+    tgt.close()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    sim = pfl.Sim(w, store=store)
+    sim.init_fields()
+    sim.step(50)
+    sim.init_fields()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    sim.step(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t_fwd = a.elapsed_time(b)
+    sim.close()
+    run = CheckpointedRun(w, store=store, K=K)
+    torch.cuda.synchronize()
+    a, b, c = ev(), ev(), ev()
+    a.record(stream)
+    m = run.forward(steps)
+    b.record(stream)
+    lam = run.lam_from_macros(2 * (m["phi"] - phi_t), 2 * (m["psi"] - psi_t))
+    dp = run.backward(lam)
+    c.record(stream)
+    torch.cuda.synchronize()
+    t_ck, t_bwd = a.elapsed_time(b), b.elapsed_time(c)
+    grad = dp.cpu().tolist()
+    run.close()
+    return {"workload": name, "storage": store, "steps": steps, "checkpoint_every": K,
+            "adjoint_compute": "f64", "forward_ms": round(t_fwd, 3),
+            "forward_with_checkpoints_ms": round(t_ck, 3), "backward_ms": round(t_bwd, 3),
+            "ratio": round((t_ck + t_bwd) / t_fwd, 3),
+            "params": ["eps4", "k", "Omega"] + [f"R{i + 1}" for i in range(len(p) - 3)],
+            "grad": [round(v, 8) for v in grad]}
+
+
 def time_cpu(w, steps):
     import torch
     from oracle import OracleParams, OracleSim
@@ -156,10 +211,11 @@ def main():
     for item in [s for s in a.extra.split(",") if s]:
         cfg, st = item.split(":")
         variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding)
+    adj = None if a.no_adjoint else time_adjoint()
     cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
     n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
     out = {
-        "metric": "MLUPS (all fields fused)",
+        "metric": "MLUPS (all fields fused) FP64 vs FP32/FP16-store; adjoint/forward cost ratio",
         "value": round(main_run["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -182,6 +238,7 @@ def main():
                          "achieved_gbs": round(v["achieved_gbs"], 1),
                          "frac": round(v["achieved_gbs"] / PEAK_HBM_GBS, 4),
                          "bytes_per_node": v["bytes_per_node"]} for k, v in variants.items()},
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

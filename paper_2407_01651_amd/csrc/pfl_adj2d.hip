@@ -129,6 +129,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   const raw* fin_th = fin + (long long)(TH ? P.o_th : 0) * N;
   const CT k1 = K.k1;
   const bool first = P.first != 0;
+  // every pull of the tile and its halo stays inside the domain
+  const bool fast = P.fast && bx0 >= R + 1 && by0 >= R + 1 && bx0 + TX + R + 1 <= P.nx &&
+                    by0 + TY + R + 1 <= P.ny;
 
   // ---- forward phase A: own node, full populations (rest values added back)
   CT fns[NS ? QN : 1], fph[PHI ? QP : 1], fps[PSI ? QS : 1], fc[CC ? QS : 1], fth[TH ? QS : 1];
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       if constexpr (TH) { h_Hv0 = hld(P.h_Hv); h_Hv1 = hld(P.h_Hv + 1); }
     }
     if constexpr (NS) {
-      pull_general<QN, ST, CT>(fin_ns, P, x, y, fns);
+      pull<QN, ST, CT>(fast, fin_ns, P, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) {
         fns[i] += P.ref_ns[i];
@@ -155,26 +158,26 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       }
     }
     if constexpr (PHI) {
-      pull_general<QP, ST, CT>(fin_phi, P, x, y, fph);
+      pull<QP, ST, CT>(fast, fin_phi, P, x, y, fph);
       phi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) { fph[i] += P.ref_phi[i]; phi += fph[i]; }
     }
     if constexpr (PSI) {
-      pull_general<QS, ST, CT>(fin_psi, P, x, y, fps);
+      pull<QS, ST, CT>(fast, fin_psi, P, x, y, fps);
       psi = CT(0);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fps[i] += P.ref_psi[i]; psi += fps[i]; }
     }
     if constexpr (CC) {
-      pull_general<QS, ST, CT>(fin_c, P, x, y, fc);
+      pull<QS, ST, CT>(fast, fin_c, P, x, y, fc);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fc[i] += P.ref_c[i]; C += fc[i]; }
       const CT h0 = (psi + CT(1)) * CT(0.5);
       U = (C / (CT(1) - k1 * h0) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull_general<QS, ST, CT>(fin_th, P, x, y, fth);
+      pull<QS, ST, CT>(fast, fin_th, P, x, y, fth);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fth[i] += P.ref_th[i]; H += fth[i]; }
     }
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hjx = CT(0), hjy = CT(0);
     if constexpr (PHI) {
       CT f[QP];
-      pull_general<QP, ST, CT>(fin_phi, P, gx, gy, f);
+      pull<QP, ST, CT>(fast, fin_phi, P, gx, gy, f);
       hphi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) hphi += f[i] + P.ref_phi[i];
@@ -202,14 +205,14 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull_general<QS, ST, CT>(fin_psi, P, gx, gy, f);
+        pull<QS, ST, CT>(fast, fin_psi, P, gx, gy, f);
         hpsi = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) hpsi += f[i] + P.ref_psi[i];
       }
       if constexpr (CC) {
         CT f[QS];
-        pull_general<QS, ST, CT>(fin_c, P, gx, gy, f);
+        pull<QS, ST, CT>(fast, fin_c, P, gx, gy, f);
         CT hC = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) hC += f[i] + P.ref_c[i];
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       }
       if constexpr (NS) {
         CT f[QN];
-        pull_general<QN, ST, CT>(fin_ns, P, gx, gy, f);
+        pull<QN, ST, CT>(fast, fin_ns, P, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) {
           f[i] += P.ref_ns[i];
@@ -875,14 +878,16 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, double
 // ------------------------------------------------------------------- R3
 template <int FIELDS, int QP>
 __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, const double* __restrict__ S_in,
-                                                           double* __restrict__ S, double* __restrict__ lam_out) {
+                                                           double* __restrict__ S, double* __restrict__ lam_out,
+                                                           double* __restrict__ part) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   using LN = Lat<9>;
   using LS = Lat<5>;
   using LP = Lat<QP>;
-  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (n >= P.N) return;
+  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool live = n0 < P.N;
+  const long long n = live ? n0 : P.N - 1;
   const long long N = P.N;
   const int x = (int)(n % P.nx), y = (int)(n / P.nx);
   const KP<CT>& K = P.kd;
@@ -910,7 +915,19 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
     a_psi += a_U * C / (2 * m0 * m0);
     a_k1 += a_U * (C * h / (m0 * m0) - U) / k1;
   }
-  S[PG_K1 * N + n] = a_k1;
+  // per-block partial sums of the parameter gradients (fixed order)
+  {
+    __shared__ double s_e[256], s_k[256];
+    s_e[threadIdx.x] = live ? S_in[PG_EPS * N + n] : 0.0;
+    s_k[threadIdx.x] = live ? a_k1 : 0.0;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s_e[0]; part[2 * blockIdx.x + 1] = s_k[0]; }
+  }
+  if (!live) return;
   auto add = [&](int plane, CT v) { lam_out[(long long)plane * N + n] += v; };
   if constexpr (NS) {
     const CT ajx = S_in[AM_JX * N + n], ajy = S_in[AM_JY * N + n];
@@ -946,23 +963,23 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
   }
 }
 
-// Step parameter gradients: block 0 sums the eps4 plane into dparams[0],
-// block 1 the k1 plane into dparams[1] with the sign of k = 1 - k1; each in a
-// fixed order (deterministic).
-__global__ __launch_bounds__(256) void adj_param_sum_kernel(long long N, const double* __restrict__ planes,
+// Step parameter gradients from the per-block partials of the assembly pass:
+// 256 threads take fixed strided subsets, then a fixed-order tree; thread 0
+// adds the eps4 sum to dparams[0] and minus the k1 sum to dparams[1]
+// (k = 1 - k1).  Deterministic.
+__global__ __launch_bounds__(256) void adj_param_sum_kernel(int nblocks, const double* __restrict__ part,
                                                             double* __restrict__ dparams) {
-  const int b = blockIdx.x;
-  const double* pl = planes + (long long)b * N;
-  double a = 0.0;
-  for (long long n = threadIdx.x; n < N; n += 256) a += pl[n];
-  __shared__ double s[256];
-  s[threadIdx.x] = a;
+  __shared__ double s_e[256], s_k[256];
+  double e = 0.0, k = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) { e += part[2 * b]; k += part[2 * b + 1]; }
+  s_e[threadIdx.x] = e;
+  s_k[threadIdx.x] = k;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) dparams[b] += (b == 0 ? 1.0 : -1.0) * s[0];
+  if (threadIdx.x == 0) { dparams[0] += s_e[0]; dparams[1] -= s_k[0]; }
 }
 
 // ------------------------------------------------------------ initial state
@@ -1074,9 +1091,11 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
     hipLaunchKernelGGL(adj_flow_kernel, dim3(nb), dim3(256), 0, s, P, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP>), dim3(nb), dim3(256), 0, s, P, S, S, lam_out);
+  double* part = S + (long long)A_NPLANES * N;
+  hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP>), dim3(nb), dim3(256), 0, s, P, S, S, lam_out, part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return hipSuccess;
+  hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
+  return hipGetLastError();
 }
 
 template <class ST, class HT>
@@ -1104,7 +1123,9 @@ hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const v
 
 }  // namespace
 
-int adj_scratch_planes() { return A_NPLANES; }
+// FP64 planes of N nodes, plus the per-block partials (2 per 256 nodes, one
+// more plane covers them).
+int adj_scratch_planes() { return A_NPLANES + 1; }
 
 bool adj2d_supported(int fields) {
   switch (fields) {
@@ -1130,11 +1151,7 @@ hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const vo
     case 3: e = adj_dispatch<bf16_dev, float>(P, fields, fin, hist, lam_in, lam_out, scratch, dparams, s, ok); break;
     default: ok = false; return hipSuccess;
   }
-  if (e != hipSuccess || !ok) return e;
-  // dparams[0] += sum a_eps, dparams[1] += -sum a_k1 (k1 = 1 - k)
-  hipLaunchKernelGGL(adj_param_sum_kernel, dim3(2), dim3(256), 0, s, P.N, scratch + (long long)PG_EPS * P.N,
-                     dparams);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_adj_init2d(const DevParams& P, int fields, const double* lam0, double* scratch,

@@ -165,3 +165,27 @@ def test_checkpointed_gradient_matches_oracle_and_fd():
         fd = (_gpu_loss(w, pp, steps, phi_t, psi_t) - _gpu_loss(w, pm, steps, phi_t, psi_t)) / (2 * h)
         log(f"[adjoint] fd {j}: {fd:.8e} adjoint {g[j]:.8e}")
         assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
+
+
+def test_adjoint2d_64_full_run_matches_fd():
+    """The 64 x 64 copy of the adjoint workload, FP64, all 2000 steps with
+    checkpoints every 100: gradient with respect to [eps4, k, Omega, R_1, R_2]
+    against central differences with step 1e-3."""
+    from paper_2407_01651_amd.adjoint import params_of, run_with_gradient
+    w = workloads.get("adjoint2d_64")
+    steps = w["steps"]
+    phi_t, psi_t = _target(w, steps, [0.005, 0.01, 0.02, 0.5, -0.5])
+    p0 = params_of(w)
+    p = torch.tensor(p0, dtype=torch.float64, device="cuda", requires_grad=True)
+    phi, psi = run_with_gradient(p, w, steps, K=100)
+    L = ((phi - phi_t) ** 2).sum() + ((psi - psi_t) ** 2).sum()
+    L.backward()
+    g = p.grad.cpu().tolist()
+    gmax = max(abs(v) for v in g)
+    h = 1e-3
+    for j in range(len(p0)):
+        pp = list(p0); pm = list(p0)
+        pp[j] += h; pm[j] -= h
+        fd = (_gpu_loss(w, pp, steps, phi_t, psi_t) - _gpu_loss(w, pm, steps, phi_t, psi_t)) / (2 * h)
+        log(f"[adjoint64] L {float(L):.8e} param {j}: fd {fd:.8e} adjoint {g[j]:.8e}")
+        assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
