@@ -190,6 +190,13 @@ int pfl_reduce(pfl_ctx* c, pfl_diag* out);
 int pfl_save_raw(pfl_ctx* c, void* dev_dst);
 int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first);
 
+/* One time step from the raw image raw_in into the raw image raw_out
+ * (distinct, raw_bytes each), as the step taken from a state with that step
+ * count and first-step flag; the context's own state is not touched.  The
+ * recompute of a checkpointed segment steps image to image this way instead
+ * of copying states in and out.  Errors as pfl_step. */
+int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first);
+
 /* Adjoint of one time step (2D) at the current state x^n: given
  * lambda^{n+1} = dL/dx^{n+1} (adj_in), writes lambda^n = (dx^{n+1}/dx^n)^T
  * lambda^{n+1} (adj_out) and adds lambda^{n+1} . dx^{n+1}/d(eps4, k) to
@@ -203,6 +210,12 @@ int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first)
  * combinations without an adjoint (built: all five sets, psi + C, psi + C +
  * theta, NS + phi, psi alone). */
 int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double* dparams);
+
+/* pfl_step_backward at the state held in a raw image (pfl_save_raw /
+ * pfl_step_raw layout) with its step count and first-step flag, instead of
+ * the context's current state.  Errors as pfl_step_backward. */
+int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+                          const double* adj_in, double* adj_out, double* dparams);
 
 /* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
  * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling

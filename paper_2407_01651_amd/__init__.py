@@ -84,6 +84,9 @@ _sig = {
     "pfl_save_raw": ([ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_load_raw": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int], ct.c_int),
     "pfl_step_backward": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_step_raw": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int], ct.c_int),
+    "pfl_step_backward_raw": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p,
+                               ct.c_void_p], ct.c_int),
     "pfl_init_backward": ([ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_destroy": ([ct.c_void_p], ct.c_int),
     "pfl_last_error": ([], ct.c_char_p),
@@ -233,6 +236,15 @@ class Sim:
         the node-form state shape; dparams accumulates [eps4, k, Omega, R_b...]."""
         _check(_lib.pfl_step_backward(self.ctx, ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
                                       ct.c_void_p(dparams.data_ptr())))
+
+    def step_raw(self, raw_in, raw_out, step_count, first):
+        _check(_lib.pfl_step_raw(self.ctx, ct.c_void_p(raw_in.data_ptr()), ct.c_void_p(raw_out.data_ptr()),
+                                 int(step_count), 1 if first else 0))
+
+    def step_backward_raw(self, raw, step_count, first, lam_in, lam_out, dparams):
+        _check(_lib.pfl_step_backward_raw(self.ctx, ct.c_void_p(raw.data_ptr()), int(step_count), 1 if first else 0,
+                                          ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
+                                          ct.c_void_p(dparams.data_ptr())))
 
     def init_backward(self, lam0, dparams):
         _check(_lib.pfl_init_backward(self.ctx, ct.c_void_p(lam0.data_ptr()), ct.c_void_p(dparams.data_ptr())))

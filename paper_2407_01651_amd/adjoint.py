@@ -8,11 +8,12 @@ the final phi and psi; its backward gives dL/dp for any loss L of them.
 
 Forward: one launch per step, with a raw checkpoint of the state (storage
 type, bit-exact) every K steps.  Backward, segment by segment from the last:
-the segment's states are recomputed from its checkpoint (same stochastic
-rounding keys, so bit-identical), then pfl_step_backward takes the node-form
-adjoint back one step at a time and accumulates dL/d(eps4, k); finally
-pfl_init_backward adds the gradient through the initial profiles.  Memory:
-one raw image per checkpoint plus K raw images for the segment being reversed.
+the segment's states are recomputed from its checkpoint image to image with
+pfl_step_raw (same stochastic rounding keys, so bit-identical), then
+pfl_step_backward_raw takes the node-form adjoint back one step at a time at
+each image and accumulates dL/d(eps4, k); finally pfl_init_backward adds the
+gradient through the initial profiles.  Memory: one raw image per checkpoint
+plus K - 1 raw images for the segment being reversed.
 Every step of the path runs in the library's kernels; this module only
 orders the calls and holds the buffers.
 """
@@ -96,17 +97,16 @@ class CheckpointedRun:
         dparams = torch.zeros(3 + nb, dtype=torch.float64, device=sim.device)
         lam = lam.contiguous().clone()
         other = torch.empty_like(lam)
-        seg = [sim.raw_buffer() for _ in range(min(self.K, self.steps))]
+        # seg[0] is the checkpoint itself; seg[j] = x^{s0 + j} stepped image to image
+        seg = [None] + [sim.raw_buffer() for _ in range(min(self.K, self.steps) - 1)]
         for si in range(len(self.ckpts) - 1, -1, -1):
             s0 = si * self.K
             n = min(self.K, self.steps - s0)
-            sim.load_raw(self.ckpts[si], s0, s0 == 0)
-            for j in range(n):
-                sim.save_raw(seg[j])
-                sim.step(1)
+            seg[0] = self.ckpts[si]
+            for j in range(n - 1):
+                sim.step_raw(seg[j], seg[j + 1], s0 + j, s0 + j == 0)
             for j in range(n - 1, -1, -1):
-                sim.load_raw(seg[j], s0 + j, s0 + j == 0)
-                sim.step_backward(lam, other, dparams)
+                sim.step_backward_raw(seg[j], s0 + j, s0 + j == 0, lam, other, dparams)
                 lam, other = other, lam
         sim.init_backward(lam, dparams)
         return dparams

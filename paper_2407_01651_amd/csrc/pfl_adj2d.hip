@@ -87,7 +87,7 @@ __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, in
 }
 
 // ------------------------------------------------------------------- R1
-template <int FIELDS, int QP, class ST, class HT>
+template <int FIELDS, int QP, class ST, class HT, class CT>
 __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                                                        const typename Store<ST>::raw* __restrict__ fin,
                                                        const HT* __restrict__ hist,
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   using LS = Lat<5>;
   using LP = Lat<QP>;
   using raw = typename Store<ST>::raw;
-  const KP<CT>& K = P.kd;
+  const KP<CT>& K = kp<CT>(P);
 
   __shared__ CT s_phi[RY][RX];
   __shared__ CT s_psi[RY][RX];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       pull<QN, ST, CT>(fast, fin_ns, P, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) {
-        fns[i] += P.ref_ns[i];
+        fns[i] += CT(P.ref_ns[i]);
         jx += CT(LN::c[i][0]) * fns[i];
         jy += CT(LN::c[i][1]) * fns[i];
       }
@@ -161,25 +161,25 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       pull<QP, ST, CT>(fast, fin_phi, P, x, y, fph);
       phi = CT(0);
 #pragma unroll
-      for (int i = 0; i < QP; ++i) { fph[i] += P.ref_phi[i]; phi += fph[i]; }
+      for (int i = 0; i < QP; ++i) { fph[i] += CT(P.ref_phi[i]); phi += fph[i]; }
     }
     if constexpr (PSI) {
       pull<QS, ST, CT>(fast, fin_psi, P, x, y, fps);
       psi = CT(0);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) { fps[i] += P.ref_psi[i]; psi += fps[i]; }
+      for (int i = 0; i < QS; ++i) { fps[i] += CT(P.ref_psi[i]); psi += fps[i]; }
     }
     if constexpr (CC) {
       pull<QS, ST, CT>(fast, fin_c, P, x, y, fc);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) { fc[i] += P.ref_c[i]; C += fc[i]; }
-      const CT h0 = (psi + CT(1)) * CT(0.5);
+      for (int i = 0; i < QS; ++i) { fc[i] += CT(P.ref_c[i]); C += fc[i]; }
+      const CT h0 = (psi + CT(1)) * CT(CT(0.5));
       U = (C / (CT(1) - k1 * h0) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
       pull<QS, ST, CT>(fast, fin_th, P, x, y, fth);
 #pragma unroll
-      for (int i = 0; i < QS; ++i) { fth[i] += P.ref_th[i]; H += fth[i]; }
+      for (int i = 0; i < QS; ++i) { fth[i] += CT(P.ref_th[i]); H += fth[i]; }
     }
     s_phi[ly + R][lx + R] = phi;
     s_psi[ly + R][lx + R] = psi;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       pull<QP, ST, CT>(fast, fin_phi, P, gx, gy, f);
       hphi = CT(0);
 #pragma unroll
-      for (int i = 0; i < QP; ++i) hphi += f[i] + P.ref_phi[i];
+      for (int i = 0; i < QP; ++i) hphi += f[i] + CT(P.ref_phi[i]);
     }
     if (ring1) {
       if constexpr (PSI) {
@@ -208,15 +208,15 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
         pull<QS, ST, CT>(fast, fin_psi, P, gx, gy, f);
         hpsi = CT(0);
 #pragma unroll
-        for (int i = 0; i < QS; ++i) hpsi += f[i] + P.ref_psi[i];
+        for (int i = 0; i < QS; ++i) hpsi += f[i] + CT(P.ref_psi[i]);
       }
       if constexpr (CC) {
         CT f[QS];
         pull<QS, ST, CT>(fast, fin_c, P, gx, gy, f);
         CT hC = CT(0);
 #pragma unroll
-        for (int i = 0; i < QS; ++i) hC += f[i] + P.ref_c[i];
-        const CT h0 = (hpsi + CT(1)) * CT(0.5);
+        for (int i = 0; i < QS; ++i) hC += f[i] + CT(P.ref_c[i]);
+        const CT h0 = (hpsi + CT(1)) * CT(CT(0.5));
         hU = (hC / (CT(1) - k1 * h0) - CT(1)) * K.inv_k1;
       }
       if constexpr (NS) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
         pull<QN, ST, CT>(fast, fin_ns, P, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) {
-          f[i] += P.ref_ns[i];
+          f[i] += CT(P.ref_ns[i]);
           hjx += CT(LN::c[i][0]) * f[i];
           hjy += CT(LN::c[i][1]) * f[i];
         }
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   S[FW_LAP * N + idx] = fo.lap;
 
   // ---- forward phase C (every intermediate kept)
-  const CT h = (psi + CT(1)) * CT(0.5);
-  const CT qraw = (CT(1) - psi) * CT(0.5);
+  const CT h = (psi + CT(1)) * CT(CT(0.5));
+  const CT qraw = (CT(1) - psi) * CT(CT(0.5));
   const CT q = clamp01(qraw);
   const CT theta = TH ? (H + h) : K.theta0;
   CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
@@ -313,23 +313,23 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   const CT ps1 = psi + CT(1);
   const CT f3psi = CT(2) * K.beta_inter * om * om * ps1;
   const CT s1m = (CT(1) - psi) * ps1;
-  const CT pprime = CT(30.0 / 32.0) * s1m * s1m;
-  const CT f2p = CT(0.5) * (CT(1) - psi) * ps1 * (CT(-2) * psi);
+  const CT pprime = CT(CT(30.0) / CT(32.0)) * s1m * s1m;
+  const CT f2p = CT(CT(0.5)) * (CT(1) - psi) * ps1 * (CT(-2) * psi);
   const CT Qpsi = -(f2p + f3psi + K.lam * pprime * (theta + K.Mcinf * U));
   const CT invF = CT(1) / F;
   const CT T1 = gFx * (an * gpx + Nx) + gFy * (an * gpy + Ny);
   const CT S_psi = K.d_psi * invF * invF * T1 + Qpsi * invF * K.inv_tau0;
   const CT D_psi = K.d_psi * an * invF;
-  const CT rate = CT(1) / (D_psi * CT(3) + CT(0.5));
+  const CT rate = CT(1) / (D_psi * CT(3) + CT(CT(0.5)));
 
   CT vx = CT(0), vy = CT(0), Fx = CT(0), Fy = CT(0), p = CT(0), Fmx = CT(0), Fmy = CT(0);
   CT rvx = CT(0), rvy = CT(0), Fby = CT(0);
   const CT rho = fo.rho;
   const CT grx = K.drho * fo.gx, gry = K.drho * fo.gy;
-  const CT c0 = LN::cs2 / (1.0 - LN::w[0]);
+  const CT c0 = LN::cs2 / (CT(1.0) - CT(LN::w[0]));
   if constexpr (NS) {
     if constexpr (FLOWX) {
-      const CT w1 = CT(1.0 / 9), w2 = CT(1.0 / 36);
+      const CT w1 = CT(CT(1.0) / 9), w2 = CT(CT(1.0) / 36);
       auto Xs = [&](int c, int dy, int dx) { return s_X[c][ry + dy][rx + dx]; };
       const CT ax0 = w1 * (Xs(0, 0, 1) - Xs(0, 0, -1)) + w2 * ((Xs(0, 1, 1) - Xs(0, 1, -1)) + (Xs(0, -1, 1) - Xs(0, -1, -1)));
       const CT ax1 = w1 * (Xs(1, 0, 1) - Xs(1, 0, -1)) + w2 * ((Xs(1, 1, 1) - Xs(1, 1, -1)) + (Xs(1, -1, 1) - Xs(1, -1, -1)));
@@ -339,18 +339,18 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       Fmy = K.drho * CT(3) * (ax1 + ay3);
     }
     Fby = -(rho - K.rho_l) * K.g;
-    rvx = jx + CT(0.5) * (fo.Fsx + Fmx);
-    rvy = jy + CT(0.5) * (fo.Fsy + Fby + Fmy);
+    rvx = jx + CT(CT(0.5)) * (fo.Fsx + Fmx);
+    rvy = jy + CT(CT(0.5)) * (fo.Fsy + Fby + Fmy);
     const CT onechi = CT(1) - fo.chi;
     vx = onechi * rvx / rho;
     vy = onechi * rvy / rho;
     Fx = fo.Fsx + Fmx - CT(2) * fo.chi * rvx;
     Fy = fo.Fsy + Fby + Fmy - CT(2) * fo.chi * rvy;
-    const CT s0 = -LN::w[0] * (vx * vx + vy * vy) * 1.5;
+    const CT s0 = -CT(LN::w[0]) * (vx * vx + vy * vy) * CT(1.5);
     CT sum = CT(0);
 #pragma unroll
     for (int i = 1; i < QN; ++i) sum += fns[i];
-    p = c0 * (sum + 0.5 * (vx * grx + vy * gry) + rho * s0);
+    p = c0 * (sum + CT(0.5) * (vx * grx + vy * gry) + rho * s0);
   }
 
   // ---- reverse
@@ -383,10 +383,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
       const CT ao = lam_in[push_target<QS>(P, P.o_th, x, y, i)];
-      a_jhx += ao * (1 - s1) * cx * 0.5;
-      a_jhy += ao * (1 - s1) * cy * 0.5;
-      a_dx += ao * (1 - 0.5 * s1) * 3 * w * cx;
-      a_dy += ao * (1 - 0.5 * s1) * 3 * w * cy;
+      a_jhx += ao * (1 - s1) * cx * CT(0.5);
+      a_jhy += ao * (1 - s1) * cy * CT(0.5);
+      a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
+      a_dy += ao * (1 - CT(0.5) * s1) * 3 * w * cy;
       if (i == 0) { a_H += ao; a_theta += ao * (w - 1); }
       else { a_theta += ao * w; a_Hvx += ao * 3 * w * cx; a_Hvy += ao * 3 * w * cy; }
     }
@@ -410,11 +410,11 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     const CT Jx = jv * fo.nx, Jy = jv * fo.ny;
     const CT m = 1 - k1 * h;
     const CT invm = 1 / m;
-    const CT dr = K.D * q * C * k1 * invm * invm * 0.5;
+    const CT dr = K.D * q * C * k1 * invm * invm * CT(0.5);
     const CT Bx = C * vx - dr * gpx + k1 * (Jatx + Jx);
     const CT By = C * vy - dr * gpy + k1 * (Jaty + Jy);
     const CT Bpx = first ? Bx : h_B0, Bpy = first ? By : h_B1;
-    const CT s1 = 1 / (K.D * q * invm * 3 + 0.5);
+    const CT s1 = 1 / (K.D * q * invm * 3 + CT(0.5));
     CT jcx = -Bx, jcy = -By;
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jcx += CT(LS::c[i][0]) * fc[i]; jcy += CT(LS::c[i][1]) * fc[i]; }
@@ -428,11 +428,11 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_C += ao * w;
       a_Bx += ao * 3 * w * cx;
       a_By += ao * 3 * w * cy;
-      a_s1 += ao * (-(cx * jcx + cy * jcy) * 0.5 - 0.5 * 3 * w * (cx * dBx + cy * dBy));
-      a_jcx += ao * (1 - s1) * cx * 0.5;
-      a_jcy += ao * (1 - s1) * cy * 0.5;
-      a_dBx += ao * (1 - 0.5 * s1) * 3 * w * cx;
-      a_dBy += ao * (1 - 0.5 * s1) * 3 * w * cy;
+      a_s1 += ao * (-(cx * jcx + cy * jcy) * CT(0.5) - CT(0.5) * 3 * w * (cx * dBx + cy * dBy));
+      a_jcx += ao * (1 - s1) * cx * CT(0.5);
+      a_jcy += ao * (1 - s1) * cy * CT(0.5);
+      a_dBx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
+      a_dBy += ao * (1 - CT(0.5) * s1) * 3 * w * cy;
     }
     a_Bx += a_dBx; a_By += a_dBy;
     if (first) { a_Bx -= a_dBx; a_By -= a_dBy; } else { a_hB0 -= a_dBx; a_hB1 -= a_dBy; }
@@ -449,9 +449,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     a_k1 += a_Bx * (Jatx + Jx) + a_By * (Jaty + Jy);
     const CT a_Jatx = a_Bx * k1, a_Jaty = a_By * k1, a_Jx = a_Bx * k1, a_Jy = a_By * k1;
     // dr = D q C k1 invm^2 / 2
-    a_q += a_dr * 0.5 * K.D * C * k1 * invm * invm;
-    a_C += a_dr * 0.5 * K.D * q * k1 * invm * invm;
-    a_k1 += a_dr * 0.5 * K.D * q * C * invm * invm;
+    a_q += a_dr * CT(0.5) * K.D * C * k1 * invm * invm;
+    a_C += a_dr * CT(0.5) * K.D * q * k1 * invm * invm;
+    a_k1 += a_dr * CT(0.5) * K.D * q * C * invm * invm;
     a_invm += a_dr * K.D * q * C * k1 * invm;
     const CT a_m = -a_invm * invm * invm;
     a_k1 -= a_m * h;
@@ -487,13 +487,13 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
       const CT Gi = w * (cx * gNx + cy * gNy);
-      const CT fstar = w * psi + (1 - rate) * (cx * jax + cy * jay) * 0.5 + w * S_psi +
-                       0.5 * w * (S_psi - Sprev) + (1 - 0.5 * rate) * Gi;
+      const CT fstar = w * psi + (1 - rate) * (cx * jax + cy * jay) * CT(0.5) + w * S_psi +
+                       CT(0.5) * w * (S_psi - Sprev) + (1 - CT(0.5) * rate) * Gi;
       const int dx = LS::c[i][0], dy = LS::c[i][1];
       const bool across = (P.wall[0] && (x + dx < 0 || x + dx >= P.nx)) ||
                           (P.wall[1] && (y + dy < 0 || y + dy >= P.ny));
       const CT old = across ? fps[LS::opp[i]]
-                            : Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx) + P.ref_psi[i];
+                            : Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx) + CT(P.ref_psi[i]);
       const CT ao = lam_in[push_target<QS>(P, P.o_psi, x, y, i)];
       const CT a_fstar = ao * inv_an;
       const CT a_oldi = -ao * (1 - an) * inv_an;
@@ -501,12 +501,12 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_inv_an += ao * (fstar - (1 - an) * old);
       if (across) a_fps[LS::opp[i]] += a_oldi; else a_old[i] += a_oldi;
       a_psi += a_fstar * w;
-      a_rate += a_fstar * (-(cx * jax + cy * jay) * 0.5 - 0.5 * Gi);
-      a_jax += a_fstar * (1 - rate) * cx * 0.5;
-      a_jay += a_fstar * (1 - rate) * cy * 0.5;
-      a_S += a_fstar * 1.5 * w;
-      a_Sprev -= a_fstar * 0.5 * w;
-      const CT a_G = a_fstar * (1 - 0.5 * rate);
+      a_rate += a_fstar * (-(cx * jax + cy * jay) * CT(0.5) - CT(0.5) * Gi);
+      a_jax += a_fstar * (1 - rate) * cx * CT(0.5);
+      a_jay += a_fstar * (1 - rate) * cy * CT(0.5);
+      a_S += a_fstar * CT(1.5) * w;
+      a_Sprev -= a_fstar * CT(0.5) * w;
+      const CT a_G = a_fstar * (1 - CT(0.5) * rate);
       a_gNx += a_G * w * cx; a_gNy += a_G * w * cy;
     }
     a_Nx -= a_gNx * inv_an; a_Ny -= a_gNy * inv_an;
@@ -532,12 +532,12 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QP; ++i) {
       const CT cx = LP::c[i][0], cy = LP::c[i][1], w = LP::w[i];
-      feq[i] = w * phi * (1 + (cx * vx + cy * vy) / LP::cs2);
-      Gv[i] = w * (cx * gx_ + cy * gy_) / LP::cs2;
+      feq[i] = w * phi * (1 + (cx * vx + cy * vy) / CT(LP::cs2));
+      Gv[i] = w * (cx * gx_ + cy * gy_) / CT(LP::cs2);
       jfx += cx * (fph[i] - feq[i]); jfy += cy * (fph[i] - feq[i]);
       gjx += cx * Gv[i]; gjy += cy * Gv[i];
     }
-    const CT ifn = 1.0 / LP::flux_norm;
+    const CT ifn = CT(1.0) / LP::flux_norm;
     CT a_feq[QP], a_G[QP];
     CT a_jfx = 0, a_jfy = 0, a_gjx = 0, a_gjy = 0;
 #pragma unroll
@@ -546,8 +546,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       const CT ao = lam_in[push_target<QP>(P, P.o_phi, x, y, i)];
       a_feq[i] = ao;
       a_jfx += ao * (1 - s1) * cx * ifn; a_jfy += ao * (1 - s1) * cy * ifn;
-      a_G[i] = ao * 0.5;
-      a_gjx += ao * 0.5 * (1 - s1) * cx * ifn; a_gjy += ao * 0.5 * (1 - s1) * cy * ifn;
+      a_G[i] = ao * CT(0.5);
+      a_gjx += ao * CT(0.5) * (1 - s1) * cx * ifn; a_gjy += ao * CT(0.5) * (1 - s1) * cy * ifn;
     }
     CT a_gx_ = 0, a_gy_ = 0;
 #pragma unroll
@@ -556,16 +556,16 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_G[i] += cx * a_gjx + cy * a_gjy;
       a_fph[i] += cx * a_jfx + cy * a_jfy;
       a_feq[i] -= cx * a_jfx + cy * a_jfy;
-      a_gx_ += a_G[i] * w * cx / LP::cs2;
-      a_gy_ += a_G[i] * w * cy / LP::cs2;
-      a_phi += a_feq[i] * w * (1 + (cx * vx + cy * vy) / LP::cs2);
-      a_vx += a_feq[i] * w * phi * cx / LP::cs2;
-      a_vy += a_feq[i] * w * phi * cy / LP::cs2;
+      a_gx_ += a_G[i] * w * cx / CT(LP::cs2);
+      a_gy_ += a_G[i] * w * cy / CT(LP::cs2);
+      a_phi += a_feq[i] * w * (1 + (cx * vx + cy * vy) / CT(LP::cs2));
+      a_vx += a_feq[i] * w * phi * cx / CT(LP::cs2);
+      a_vy += a_feq[i] * w * phi * cy / CT(LP::cs2);
     }
     if (!first) { a_phivx += a_gx_; a_phivy += a_gy_; a_hpv0 -= a_gx_; a_hpv1 -= a_gy_; }
-    a_sharp += (a_gx_ * fo.nx + a_gy_ * fo.ny) * LP::cs2;
-    a_fnx += a_gx_ * LP::cs2 * fo.sharp;
-    a_fny += a_gy_ * LP::cs2 * fo.sharp;
+    a_sharp += (a_gx_ * fo.nx + a_gy_ * fo.ny) * CT(LP::cs2);
+    a_fnx += a_gx_ * CT(LP::cs2) * fo.sharp;
+    a_fny += a_gy_ * CT(LP::cs2) * fo.sharp;
     a_phi += a_phivx * vx + a_phivy * vy;
     a_vx += a_phivx * phi; a_vy += a_phivy * phi;
   }
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   // flow
   if constexpr (NS) {
     const CT nu = (K.mu_g + (K.mu_l - K.mu_g) * phi) / rho;
-    const CT s_nu = 1 / (nu * 3 + 0.5);
+    const CT s_nu = 1 / (nu * 3 + CT(0.5));
     const CT vv = vx * vx + vy * vy;
     const CT vgr = vx * grx + vy * gry;
     const CT vF = vx * Fx + vy * Fy;
@@ -583,10 +583,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     for (int i = 0; i < QN; ++i) {
       const CT cx = LN::c[i][0], cy = LN::c[i][1], w = LN::w[i];
       const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy;
-      feq[i] = w * p * 3 + rho * w * (cv * 3 + cv * cv * 4.5 - vv * 1.5);
+      feq[i] = w * p * 3 + rho * w * (cv * 3 + cv * cv * CT(4.5) - vv * CT(1.5));
       if (i == 0) feq[i] -= p * 3;
       Ft[i] = w * (vgr + cF * 3 + (cv * cF - vF / 3) * 9);
-      const CT fneq = fns[i] - feq[i] + 0.5 * Ft[i];
+      const CT fneq = fns[i] - feq[i] + CT(0.5) * Ft[i];
       m1 += (cx * cx - cy * cy) * fneq;
       m2 += (cx * cy) * fneq;
     }
@@ -596,9 +596,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     for (int i = 0; i < QN; ++i) {
       const CT cx = LN::c[i][0], cy = LN::c[i][1];
       ao_[i] = lam_in[push_target<QN>(P, P.o_ns, x, y, i)];
-      a_r += ao_[i] * 0.25 * ((cx * cx - cy * cy) * m1 + (cx * cy) * m2);
-      a_m1 += ao_[i] * r * 0.25 * (cx * cx - cy * cy);
-      a_m2 += ao_[i] * r * 0.25 * (cx * cy);
+      a_r += ao_[i] * CT(0.25) * ((cx * cx - cy * cy) * m1 + (cx * cy) * m2);
+      a_m1 += ao_[i] * r * CT(0.25) * (cx * cx - cy * cy);
+      a_m2 += ao_[i] * r * CT(0.25) * (cx * cy);
     }
     CT a_vgr = 0, a_vF = 0, a_vv = 0;
 #pragma unroll
@@ -608,15 +608,15 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       const CT a_fneq = (cx * cx - cy * cy) * a_m1 + (cx * cy) * a_m2;
       a_fns[i] += a_fneq;
       const CT a_feq = ao_[i] - a_fneq;
-      const CT a_Ft = 0.5 * a_fneq + 0.5 * ao_[i];
+      const CT a_Ft = CT(0.5) * a_fneq + CT(0.5) * ao_[i];
       a_vgr += a_Ft * w;
       const CT a_cF = a_Ft * w * (3 + 9 * cv);
       CT a_cv = a_Ft * 9 * w * cF;
       a_vF -= 3 * w * a_Ft;
-      a_p += a_feq * (3 * w - (i == 0 ? 3.0 : 0.0));
-      a_rho += a_feq * w * (cv * 3 + cv * cv * 4.5 - vv * 1.5);
+      a_p += a_feq * (3 * w - (i == 0 ? CT(3.0) : CT(0.0)));
+      a_rho += a_feq * w * (cv * 3 + cv * cv * CT(4.5) - vv * CT(1.5));
       a_cv += a_feq * rho * w * (3 + 9 * cv);
-      a_vv -= a_feq * rho * w * 1.5;
+      a_vv -= a_feq * rho * w * CT(1.5);
       a_vx += a_cv * cx; a_vy += a_cv * cy;
       a_Fx += a_cF * cx; a_Fy += a_cF * cy;
     }
@@ -631,10 +631,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     const CT a_sum = a_p * c0;
 #pragma unroll
     for (int i = 1; i < QN; ++i) a_fns[i] += a_sum;
-    a_vx += a_p * c0 * (0.5 * grx - rho * LN::w[0] * 3 * vx);
-    a_vy += a_p * c0 * (0.5 * gry - rho * LN::w[0] * 3 * vy);
-    a_grx += a_p * c0 * 0.5 * vx; a_gry += a_p * c0 * 0.5 * vy;
-    a_rho += a_p * c0 * (-LN::w[0] * (vx * vx + vy * vy) * 1.5);
+    a_vx += a_p * c0 * (CT(0.5) * grx - rho * CT(LN::w[0]) * 3 * vx);
+    a_vy += a_p * c0 * (CT(0.5) * gry - rho * CT(LN::w[0]) * 3 * vy);
+    a_grx += a_p * c0 * CT(0.5) * vx; a_gry += a_p * c0 * CT(0.5) * vy;
+    a_rho += a_p * c0 * (-CT(LN::w[0]) * (vx * vx + vy * vy) * CT(1.5));
     // forces and velocity
     const CT onechi = 1 - fo.chi;
     a_Fsx += a_Fx; a_Fmx += a_Fx; a_chi -= 2 * rvx * a_Fx;
@@ -647,8 +647,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     const CT a_irho = (a_vx * rvx + a_vy * rvy) * onechi;
     a_rho -= a_irho * irho * irho;
     a_chi -= a_onechi;
-    a_jx += a_rvx; a_Fsx += 0.5 * a_rvx; a_Fmx += 0.5 * a_rvx;
-    a_jy += a_rvy; a_Fsy += 0.5 * a_rvy; a_Fby += 0.5 * a_rvy; a_Fmy += 0.5 * a_rvy;
+    a_jx += a_rvx; a_Fsx += CT(0.5) * a_rvx; a_Fmx += CT(0.5) * a_rvx;
+    a_jy += a_rvy; a_Fsy += CT(0.5) * a_rvy; a_Fby += CT(0.5) * a_rvy; a_Fmy += CT(0.5) * a_rvy;
     a_rho -= K.g * a_Fby;
   }
 
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     const CT a_pp = -a_Q * K.lam * (theta + K.Mcinf * U);
     a_theta -= a_Q * K.lam * pprime;
     a_U -= a_Q * K.lam * pprime * K.Mcinf;
-    const CT a_s1m = a_pp * (30.0 / 32.0) * 2 * s1m;
+    const CT a_s1m = a_pp * (CT(30.0) / CT(32.0)) * 2 * s1m;
     a_psi += a_s1m * (-2 * psi);
     const CT a_f3 = -a_Q;
     a_om += a_f3 * 4 * K.beta_inter * om * ps1;
@@ -716,8 +716,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     a_H += a_theta;
     a_h += a_theta;
   }
-  a_psi += 0.5 * a_h;
-  if (qraw > 0 && qraw < 1) a_psi -= 0.5 * a_q;
+  a_psi += CT(0.5) * a_h;
+  if (qraw > 0 && qraw < 1) a_psi -= CT(0.5) * a_q;
   {
     a_gpx += a_ex * invp; a_gpy += a_ey * invp;
     const CT a_invp = a_ex * gpx + a_ey * gpy;
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     a_phi += a_rho * K.drho;
     const CT ps1o = psi + 1;
     const CT omo = 1 - phi;
-    const CT f1p = 0.5 * omo * phi * (1 - 2 * phi);
+    const CT f1p = CT(0.5) * omo * phi * (1 - 2 * phi);
     const CT f3p = -2 * K.beta_inter * omo * ps1o * ps1o;
     const CT mu = f1p + f3p - K.Wphi2 * fo.lap;
     if constexpr (NS) {
@@ -740,10 +740,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_lap -= K.Wphi2 * a_mu;
       a_phi += a_mu * (-2 * K.beta_inter) * (-1) * ps1o * ps1o;
       a_psi += a_mu * (-2 * K.beta_inter) * omo * 2 * ps1o;
-      a_phi += a_mu * 0.5 * (1 - 6 * phi + 6 * phi * phi);
+      a_phi += a_mu * CT(0.5) * (1 - 6 * phi + 6 * phi * phi);
     }
-    const CT ho = (psi + 1) * 0.5;
-    if (ho > 0 && ho < 1) a_psi += 0.5 * a_chi;
+    const CT ho = (psi + 1) * CT(0.5);
+    if (ho > 0 && ho < 1) a_psi += CT(0.5) * a_chi;
     const CT dw = omo * phi;
     if (dw > 0) a_phi += a_sharp * K.sharp * (1 - 2 * phi);
     const CT inv = 1 / sqrt(fo.gx * fo.gx + fo.gy * fo.gy + dn);
@@ -1083,7 +1083,9 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT>), dim3(tiles), dim3(NT), 0, s, P,
+  // the reverse of the node-local phase runs in the forward's compute type
+  using RT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+  hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT>), dim3(tiles), dim3(NT), 0, s, P,
                      (const typename Store<ST>::raw*)fin, (const HT*)hist, lam_in, lam_out, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

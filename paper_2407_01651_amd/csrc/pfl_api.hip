@@ -440,6 +440,24 @@ int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first)
   return PFL_OK;
 }
 
+int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first) {
+  if (!c || !raw_in || !raw_out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "step before init");
+  if (raw_in == raw_out) return fail(PFL_E_INVALID_ARG, "raw_in and raw_out must differ");
+  if (step_count < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  DevParams d = c->d;
+  d.first = first ? 1 : 0;
+  d.step_ctr = (uint32_t)step_count;
+  d.hist_src = (const char*)raw_in + c->L.pops_bytes;
+  bool ok = true;
+  hipError_t e = launch_step(d, (int)c->p.fields, c->p.store, raw_in, raw_out,
+                             (char*)raw_out + c->L.pops_bytes, nullptr, 0, c->s, ok);
+  if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
+  if (e != hipSuccess) return hip_fail(e, "step kernel");
+  g_err.clear();
+  return PFL_OK;
+}
+
 static int adj_check(pfl_ctx* c) {
   if (!c) return fail(PFL_E_INVALID_ARG, "null context");
   if (!c->inited) return fail(PFL_E_STATE, "adjoint before init");
@@ -457,6 +475,26 @@ int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double*
   const void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   bool ok = true;
   hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, adj_in, adj_out,
+                                   (double*)c->b.adj, dparams, c->s, ok);
+  if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
+  if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
+  g_err.clear();
+  return PFL_OK;
+}
+
+int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+                          const double* adj_in, double* adj_out, double* dparams) {
+  int rc = adj_check(c);
+  if (rc) return rc;
+  if (!raw_state || !adj_in || !adj_out || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (adj_in == adj_out) return fail(PFL_E_INVALID_ARG, "adj_in and adj_out must differ");
+  if (step_count < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  DevParams d = c->d;
+  d.first = first ? 1 : 0;
+  d.step_ctr = (uint32_t)step_count;
+  bool ok = true;
+  hipError_t e = launch_adj_step2d(d, (int)c->p.fields, c->p.store, raw_state,
+                                   (const char*)raw_state + c->L.pops_bytes, adj_in, adj_out,
                                    (double*)c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");

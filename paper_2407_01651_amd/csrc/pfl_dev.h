@@ -94,6 +94,7 @@ struct DevParams {
   const double* seeds;         // x, y, z, r, angle per seed
   const double* bubbles;       // x, y, z, r per bubble
   int fast;                    // byte offsets of every buffer fit in 32 bits
+  const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
   uint32_t step_ctr;           // step counter, part of the rounding key
   KP<double> kd;

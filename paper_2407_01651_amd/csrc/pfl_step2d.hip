@@ -27,7 +27,7 @@ template <int FIELDS, int QP, class ST, class HT, class CT>
 __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
                                                     const typename Store<ST>::raw* __restrict__ fin,
                                                     typename Store<ST>::raw* __restrict__ fout,
-                                                    HT* __restrict__ hist, double* __restrict__ mout,
+                                                    HT* hist, double* __restrict__ mout,
                                                     int mode) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
@@ -90,9 +90,10 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const bool first = P.first != 0;
   const uint32_t hbyte = (uint32_t)idx * HS;
   const uint32_t hplane = (uint32_t)N * HS;
+  const HT* hsrc = P.hist_src ? (const HT*)P.hist_src : hist;
   auto hld = [&](int plane) -> CT {
-    if (P.fast) return CT(*(const HT*)((const char*)hist + (uint32_t)plane * hplane + hbyte));
-    return CT(hist[(long long)plane * N + idx]);
+    if (P.fast) return CT(*(const HT*)((const char*)hsrc + (uint32_t)plane * hplane + hbyte));
+    return CT(hsrc[(long long)plane * N + idx]);
   };
   CT h_psi = CT(0), h_S = CT(0), h_pv0 = CT(0), h_pv1 = CT(0), h_B0 = CT(0), h_B1 = CT(0);
   CT h_Hv0 = CT(0), h_Hv1 = CT(0);

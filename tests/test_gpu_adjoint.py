@@ -189,3 +189,52 @@ def test_adjoint2d_64_full_run_matches_fd():
         fd = (_gpu_loss(w, pp, steps, phi_t, psi_t) - _gpu_loss(w, pm, steps, phi_t, psi_t)) / (2 * h)
         log(f"[adjoint64] L {float(L):.8e} param {j}: fd {fd:.8e} adjoint {g[j]:.8e}")
         assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
+
+
+@pytest.mark.parametrize("store", ["f64", "f16"])
+def test_step_raw_reproduces_step_bit_for_bit(store):
+    """Checkpoint recompute: five steps image to image (pfl_step_raw) give the
+    same raw bytes as five pfl_step calls, stochastic rounding included."""
+    import paper_2407_01651_amd as pfl
+    w = _w(dict(nx=45, ny=37, seed=40))
+    sim = pfl.Sim(w, store=store)
+    sim.init_fields()
+    imgs = [sim.raw_buffer() for _ in range(6)]
+    sim.save_raw(imgs[0])
+    for j in range(5):
+        sim.step_raw(imgs[j], imgs[j + 1], j, j == 0)
+    sim.step(5)
+    ref = sim.raw_buffer()
+    sim.save_raw(ref)
+    torch.cuda.synchronize()
+    # compare the payloads (the image pads each region to 256 bytes)
+    N = sim.N
+    elem, helem = (8, 8) if store == "f64" else (2, 4)
+    npop, nhist = 29, 8
+    pb = int(sim.sizes.pops_bytes)
+    assert torch.equal(imgs[5][:npop * N * elem], ref[:npop * N * elem])
+    assert torch.equal(imgs[5][pb:pb + nhist * N * helem], ref[pb:pb + nhist * N * helem])
+    sim.close()
+
+
+def test_fp32_storage_gradient_matches_fp64():
+    """FP32 storage (FP32 forward, FP32 reverse of the node-local phase,
+    FP64 adjoint state and sums) against the FP64 form on the 60-step case."""
+    from paper_2407_01651_amd.adjoint import params_of, run_with_gradient
+    w = workloads.get("adjoint2d_64")
+    w.update(nx=40, ny=36, seeds=[dict(x=20.0, y=14.0, z=0.0, r=4.0, angle=0.3)],
+             bubbles=[dict(x=10.0, y=27.0, z=0.0, r=6.0), dict(x=30.0, y=28.0, z=0.0, r=5.0)])
+    steps = 60
+    phi_t, psi_t = _target(w, steps, [0.01, 0.02, 0.03, 0.5, -0.4])
+    grads = {}
+    for store in ("f64", "f32"):
+        p = torch.tensor(params_of(w), dtype=torch.float64, device="cuda", requires_grad=True)
+        phi, psi = run_with_gradient(p, w, steps, K=16, store=store)
+        (((phi - phi_t) ** 2).sum() + ((psi - psi_t) ** 2).sum()).backward()
+        grads[store] = p.grad.cpu().tolist()
+    log(f"[adjoint] f64 {grads['f64']}")
+    log(f"[adjoint] f32 {grads['f32']}")
+    # measured: 3.7e-5 (eps4), 7.3e-5 (k), 1.0e-4 (Omega), 1.0e-5 and 1.5e-5 (radii)
+    gmax = max(abs(v) for v in grads["f64"])
+    for a, b in zip(grads["f32"], grads["f64"]):
+        assert abs(a - b) <= 5e-4 * max(abs(b), 1e-2 * gmax), (grads["f32"], grads["f64"])
