@@ -23,8 +23,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PROFILE = os.path.join(ROOT, "profiles", "step2d_alloy2d_1024.md")
-KERNEL_SOURCES = ("paper_2407_01651_amd/csrc/pfl_step2d.hip", "paper_2407_01651_amd/csrc/pfl_step2d.h",
-                  "paper_2407_01651_amd/csrc/pfl_util.h", "paper_2407_01651_amd/csrc/pfl_dev.h")
+KERNEL_SOURCES = ("paper_2407_01651_amd/csrc/pfl_step2d.hip", "paper_2407_01651_amd/csrc/pfl_step2d_impl.h",
+                  "paper_2407_01651_amd/csrc/pfl_step2d_lowp.hip", "paper_2407_01651_amd/csrc/pfl_step2d.h",
+                  "paper_2407_01651_amd/csrc/pfl_util.h", "paper_2407_01651_amd/csrc/pfl_dev.h",
+                  "paper_2407_01651_amd/build.py")
 
 
 def measured_traffic(store):

@@ -7,7 +7,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step3d.hip", "pfl_adj2d.hip", "pfl_aux.hip"]
+SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step2d_lowp.hip", "pfl_step3d.hip", "pfl_step3d_lowp.hip",
+       "pfl_adj2d.hip", "pfl_aux.hip"]
+# FP32-compute step instantiations: contraction (FMA) and reassociation are
+# allowed; the FP64 parity form and everything else is built without them.
+LOWP = {"pfl_step2d_lowp.hip", "pfl_step3d_lowp.hip"}
+LOWP_FLAGS = ["-ffp-contract=fast", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math",
+              "-freciprocal-math"]
 OUT = os.path.join(HERE, "libpfl.so")
 
 FLAGS = [
@@ -26,7 +32,10 @@ def build(verbose=False, jobs=None):
     procs = []
     for s in SRC:
         obj = os.path.join(HERE, "csrc", s.replace(".hip", ".o"))
-        cmd = [hipcc, "-c", os.path.join(HERE, "csrc", s), "-o", obj] + [f for f in FLAGS if f != "-shared"] + inc
+        flags = [f for f in FLAGS if f != "-shared"]
+        if s in LOWP:
+            flags = [f for f in flags if f != "-ffp-contract=off"] + LOWP_FLAGS
+        cmd = [hipcc, "-c", os.path.join(HERE, "csrc", s), "-o", obj] + flags + inc
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

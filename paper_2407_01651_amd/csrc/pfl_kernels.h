@@ -9,6 +9,10 @@ namespace pfl {
 hipError_t launch_step2d(const DevParams& P, int fields, int store, const void* fin, void* fout,
                          void* hist, double* mout, int mode, hipStream_t s, bool& ok);
 bool step2d_supported(int fields);
+hipError_t launch_step2d_lowp(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                              void* hist, double* mout, int mode, hipStream_t s, bool& ok);
+hipError_t launch_step3d_lowp(const DevParams& P, int fields, int store, const void* fin, void* fout,
+                              void* hist, double* mout, int mode, hipStream_t s, bool& ok);
 hipError_t launch_step3d(const DevParams& P, int fields, int store, const void* fin, void* fout,
                          void* hist, double* mout, int mode, hipStream_t s, bool& ok);
 bool step3d_supported(int fields);
