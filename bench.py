@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--config", default="alloy2d_1024")
     ap.add_argument("--store", default="f64")
     ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
-    ap.add_argument("--extra", default="coupled2d_2048:f16,coupled2d_2048:bf16,coupled2d_2048:f32",
+    ap.add_argument("--extra", default="coupled2d_2048:f16,coupled2d_2048:bf16,coupled2d_2048:f32,"
+                                       "coupled2d_2048_q9:f16",
                     help="comma list of config:storage pairs timed beside (variants)")
     ap.add_argument("--rounding", default="stochastic", choices=("stochastic", "nearest"),
                     help="rounding into 16-bit storage")
@@ -153,7 +154,7 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     torch.cuda.synchronize()
     t_fwd = a.elapsed_time(b)
     sim.close()
-    run = CheckpointedRun(w, store=store, K=K)
+    run = CheckpointedRun(w, store=store, K=K, steps=steps)
     torch.cuda.synchronize()
     a, b, c = ev(), ev(), ev()
     a.record(stream)
@@ -167,7 +168,8 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     grad = dp.cpu().tolist()
     run.close()
     return {"workload": name, "storage": store, "steps": steps, "checkpoint_every": K,
-            "adjoint_compute": "f64", "forward_ms": round(t_fwd, 3),
+            "reverse_compute": "f32 node-local reverse (the forward's compute type), f64 adjoint state and sums",
+            "forward_ms": round(t_fwd, 3),
             "forward_with_checkpoints_ms": round(t_ck, 3), "backward_ms": round(t_bwd, 3),
             "ratio": round((t_ck + t_bwd) / t_fwd, 3),
             "params": ["eps4", "k", "Omega"] + [f"R{i + 1}" for i in range(len(p) - 3)],

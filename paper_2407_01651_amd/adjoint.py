@@ -50,22 +50,33 @@ def params_of(w):
 class CheckpointedRun:
     """Forward with checkpoints and the adjoint sweep over it."""
 
-    def __init__(self, w, store="f64", K=100, device="cuda:0"):
+    def __init__(self, w, store="f64", K=100, device="cuda:0", steps=None):
         self.w = w
         self.K = int(K)
         self.sim = Sim(w, store=store, device=device, adjoint=True)
         self.ckpts = []
+        self.seg = []
         self.steps = 0
+        if steps is not None:
+            self._reserve(int(steps))
+
+    def _reserve(self, steps):
+        """Device images for the checkpoints and one segment (set-up, so that
+        neither sweep allocates)."""
+        sim = self.sim
+        n_ck = (steps + self.K - 1) // self.K
+        while len(self.ckpts) < n_ck:
+            self.ckpts.append(sim.raw_buffer())
+        while len(self.seg) < min(self.K, steps) - 1:
+            self.seg.append(sim.raw_buffer())
 
     def forward(self, steps):
         sim = self.sim
-        sim.init_fields()
-        self.ckpts = []
         self.steps = int(steps)
-        for s0 in range(0, self.steps, self.K):
-            buf = sim.raw_buffer()
-            sim.save_raw(buf)
-            self.ckpts.append(buf)
+        self._reserve(self.steps)
+        sim.init_fields()
+        for i, s0 in enumerate(range(0, self.steps, self.K)):
+            sim.save_raw(self.ckpts[i])
             sim.step(min(self.K, self.steps - s0))
         return sim.macros()
 
@@ -98,8 +109,9 @@ class CheckpointedRun:
         lam = lam.contiguous().clone()
         other = torch.empty_like(lam)
         # seg[0] is the checkpoint itself; seg[j] = x^{s0 + j} stepped image to image
-        seg = [None] + [sim.raw_buffer() for _ in range(min(self.K, self.steps) - 1)]
-        for si in range(len(self.ckpts) - 1, -1, -1):
+        seg = [None] + self.seg
+        n_ck = (self.steps + self.K - 1) // self.K
+        for si in range(n_ck - 1, -1, -1):
             s0 = si * self.K
             n = min(self.K, self.steps - s0)
             seg[0] = self.ckpts[si]

@@ -30,6 +30,9 @@ CASES = [
     ("alloy_35x21", dict(nx=35, ny=21, seed=6, fields=("psi", "c"), Le=math.inf, U0=-0.55,
                          theta0=0.0, tau0=50.0, periodic=(True, True, True)), 40),
     ("alloy_theta_26x18", dict(nx=26, ny=18, seed=7, fields=("psi", "c", "theta")), 30),
+    # case (B): isothermal at theta_sys = -Mc_inf Omega / (1 - (1-k) Omega), Mc_inf = 1 - (1-k) Omega
+    ("alloy_caseB_31x23", dict(nx=31, ny=23, seed=14, fields=("psi", "c"), Le=math.inf, U0=0.0,
+                               theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, True, True)), 40),
     ("nsphi_33x33", dict(nx=33, ny=33, seed=8, fields=("ns", "phi")), 40),
     ("noflow_29x15", dict(nx=29, ny=15, seed=9, fields=("phi", "psi", "c", "theta")), 30),
     ("psi_only_16x16", dict(nx=16, ny=16, seed=10, fields=("psi",), Le=math.inf, theta0=-0.3), 30),

@@ -248,3 +248,17 @@ def test_centred_seed_d4_symmetry(angle):
     # and the seed grew, fastest along its crystal axes
     h = (psi + 1) / 2
     assert float(h.sum()) > math.pi * 16
+
+
+def test_case_b_system_temperature():
+    """eq-Tsys (Sec. 3.3): Mc_inf = 1 - (1-k) Omega and theta_sys =
+    -Mc_inf Omega / (1 - (1-k) Omega), which reduces to -Omega; the case-B
+    workload carries these values with zero initial supersaturation, so the
+    driving force theta + Mc_inf U starts at -Omega as in the thermal case."""
+    import workloads
+    th, mc = workloads.case_b(0.55, 0.15)
+    assert abs(mc - (1 - 0.85 * 0.55)) < 1e-15 and abs(mc - 0.5325) < 1e-15
+    assert abs(th - (-0.5325 * 0.55 / 0.5325)) < 1e-15 and abs(th + 0.55) < 1e-15
+    w = workloads.get("alloy2d_1024_caseB")
+    assert w["U0"] == 0.0 and abs(w["theta0"] + 0.55) < 1e-15 and abs(w["Mcinf"] - 0.5325) < 1e-15
+    assert "theta" not in w["fields"]

@@ -146,6 +146,24 @@ def alloy2d_1024(seed=1, store="f64"):
     return c
 
 
+def case_b(Omega, k):
+    """System temperature and Mc_inf of the solutal case at a fixed temperature
+    (Sec. 3.3, eq-Tsys): equal solutal and thermal capillary lengths give
+    Mc_inf = 1 - (1 - k) Omega and theta_sys = -Mc_inf Omega / (1 - (1 - k) Omega)."""
+    mc = 1.0 - (1.0 - k) * Omega
+    return -mc * Omega / (1.0 - (1.0 - k) * Omega), mc
+
+
+def alloy2d_1024_caseB(seed=1, store="f64", Omega=0.55):
+    """The alloy workload in the paper's case (B): isothermal solutal growth at
+    the system temperature theta_sys with Mc_inf from eq-Tsys and zero initial
+    supersaturation (C = 1 - (1 - k) h(psi))."""
+    c = alloy2d_1024(seed=seed, store=store)
+    th, mc = case_b(Omega, c["k"])
+    c.update(name="alloy2d_1024_caseB", theta0=th, Mcinf=mc, U0=0.0)
+    return c
+
+
 def coupled2d_2048(seed=3, store="f16"):
     """Coupled 2D dendrites plus rising bubbles, 2048 x 2048, 10000 steps:
     16 seeds (R 4), 24 bubbles (R uniform in [8, 24]), density ratio 100,
@@ -159,6 +177,14 @@ def coupled2d_2048(seed=3, store="f16"):
     c.update(name="coupled2d_2048", nx=2048, ny=2048, eps4=0.02, rho_g=0.01,
              g=1e-6, seeds=seeds, bubbles=bubs, steps=10000,
              store=store, rng_seed=seed)
+    return c
+
+
+def coupled2d_2048_q9(seed=3, store="f16"):
+    """coupled2d_2048 with the bubble phase on D2Q9, the lattice the paper
+    uses for the conservative Allen-Cahn equation (Appendix B)."""
+    c = coupled2d_2048(seed=seed, store=store)
+    c.update(name="coupled2d_2048_q9", phi_q=9)
     return c
 
 
@@ -229,6 +255,8 @@ CONFIGS = {
     "coupled2d_128": coupled2d_128,
     "alloy2d_1024": alloy2d_1024,
     "coupled2d_2048": coupled2d_2048,
+    "coupled2d_2048_q9": coupled2d_2048_q9,
+    "alloy2d_1024_caseB": alloy2d_1024_caseB,
     "adjoint2d_512": adjoint2d_512,
     "adjoint2d_64": adjoint2d_64,
     "coupled3d_256": coupled3d_256,
