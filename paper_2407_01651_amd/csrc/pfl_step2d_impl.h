@@ -380,6 +380,40 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     const CT vv = vx * vx + vy * vy;
     const CT vgr = vx * grx + vy * gry;
     const CT vF = vx * Fx + vy * Fy;
+    if constexpr (sizeof(CT) == 4) {
+      // FP32 compute: the same collision in moment form.  On the 4th-order
+      // isotropic lattice the traceless stress moments of f^eq and of F/2 are
+      // rho T:vv and T:(vF) (symmetrised), and for i > 0
+      // f_i^eq + F_i/2 = w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F)) + 1.5 c.F]
+      // with A = 3p - 1.5 rho v.v + v.grad(rho)/2 - 1.5 v.F; f_0^eq + F_0/2 = w_0 A - 3p.
+      const CT r = CT(1) - s_nu;
+      const CT A = CT(3) * p - CT(1.5) * rho * vv + CT(0.5) * vgr - CT(1.5) * vF;
+      CT s1 = CT(0), s2 = CT(0);
+#pragma unroll
+      for (int i = 1; i < QN; ++i) {
+        const int t1 = LN::c[i][0] * LN::c[i][0] - LN::c[i][1] * LN::c[i][1], t2 = LN::c[i][0] * LN::c[i][1];
+        if (t1 > 0) s1 += fns[i]; else if (t1 < 0) s1 -= fns[i];
+        if (t2 > 0) s2 += fns[i]; else if (t2 < 0) s2 -= fns[i];
+      }
+      const CT m1 = s1 - rho * (vx * vx - vy * vy) + (vx * Fx - vy * Fy);
+      const CT m2 = s2 - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx);
+      const CT q1 = CT(0.25) * r * m1, q2 = CT(0.25) * r * m2;
+      const CT rho3 = CT(3) * rho;
+#pragma unroll
+      for (int i = 0; i < QN; ++i) {
+        const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
+        const CT w = CT(LN::w[i]);
+        CT fs;
+        if (i == 0) {
+          fs = w * A - CT(3) * p;
+        } else {
+          const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy;
+          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF)) + CT(1.5) * cF + A;
+          fs = w * t + ((cx * cx - cy * cy) * q1 + (cx * cy) * q2);
+        }
+        st(P.o_ns + i, fs);
+      }
+    } else {
     CT fneq[QN], fhalf[QN];
     CT m1 = CT(0), m2 = CT(0);   // projections on c_x^2 - c_y^2 and c_x c_y
 #pragma unroll
@@ -402,6 +436,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
       const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
       st(P.o_ns + i, fs);
+    }
     }
   }
 

@@ -542,6 +542,49 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
     const CT vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     const CT vgr = v[0] * gr[0] + v[1] * gr[1] + v[2] * gr[2];
     const CT vF = v[0] * Ft[0] + v[1] * Ft[1] + v[2] * Ft[2];
+    if constexpr (sizeof(CT) == 4) {
+      // FP32 compute: the same collision in moment form (D3Q19 is 4th-order
+      // isotropic, so each traceless stress moment T of f^eq + F/2 is
+      // rho T:vv + T:(vF) symmetrised; for i > 0 f_i^eq + F_i/2 =
+      // w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F)) + 1.5 c.F] with
+      // A = 3p - 1.5 rho v.v + v.grad(rho)/2 - 1.5 v.F, and w_0 A - 3p at rest)
+      const CT r = CT(1) - s_nu;
+      const CT A = CT(3) * p - CT(1.5) * rho * vv + CT(0.5) * vgr - CT(1.5) * vF;
+      CT s9 = CT(0), s11 = CT(0), sxy = CT(0), syz = CT(0), sxz = CT(0);
+#pragma unroll
+      for (int i = 1; i < QN; ++i) {
+        const int cx = LN::c[i][0], cy = LN::c[i][1], cz = LN::c[i][2];
+        s9 += CT(2 * cx * cx - cy * cy - cz * cz) * fns[i];
+        s11 += CT(cy * cy - cz * cz) * fns[i];
+        sxy += CT(cx * cy) * fns[i];
+        syz += CT(cy * cz) * fns[i];
+        sxz += CT(cx * cz) * fns[i];
+      }
+      const CT vx = v[0], vy = v[1], vz = v[2], Fx = Ft[0], Fy = Ft[1], Fz = Ft[2];
+      const CT q9 = (r * CT(1.0 / 36)) * (s9 - rho * (CT(2) * vx * vx - vy * vy - vz * vz) +
+                                          (CT(2) * vx * Fx - vy * Fy - vz * Fz));
+      const CT q11 = (r * CT(1.0 / 12)) * (s11 - rho * (vy * vy - vz * vz) + (vy * Fy - vz * Fz));
+      const CT qxy = (r * CT(0.25)) * (sxy - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx));
+      const CT qyz = (r * CT(0.25)) * (syz - rho * vy * vz + CT(0.5) * (vy * Fz + vz * Fy));
+      const CT qxz = (r * CT(0.25)) * (sxz - rho * vx * vz + CT(0.5) * (vx * Fz + vz * Fx));
+      const CT rho3 = CT(3) * rho;
+#pragma unroll
+      for (int i = 0; i < QN; ++i) {
+        const int cx = LN::c[i][0], cy = LN::c[i][1], cz = LN::c[i][2];
+        const CT w = CT(LN::w[i]);
+        CT fs;
+        if (i == 0) {
+          fs = w * A - CT(3) * p;
+        } else {
+          const CT cv = CT(cx) * vx + CT(cy) * vy + CT(cz) * vz;
+          const CT cF = CT(cx) * Fx + CT(cy) * Fy + CT(cz) * Fz;
+          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF)) + CT(1.5) * cF + A;
+          fs = w * t + (CT(2 * cx * cx - cy * cy - cz * cz) * q9 + CT(cy * cy - cz * cz) * q11 +
+                        CT(cx * cy) * qxy + CT(cy * cz) * qyz + CT(cx * cz) * qxz);
+        }
+        st(P.o_ns + i, fs);
+      }
+    } else {
     CT fhalf[QN];
     CT m9 = CT(0), m11 = CT(0), mxy = CT(0), myz = CT(0), mxz = CT(0);
 #pragma unroll
@@ -573,6 +616,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT ps = (CT(2) * cx * cx - cy * cy - cz * cz) * m9 + (cy * cy - cz * cz) * m11 +
                     (cx * cy) * mxy + (cy * cz) * myz + (cx * cz) * mxz;
       st(P.o_ns + i, fhalf[i] + r * ps);
+    }
     }
   }
 
