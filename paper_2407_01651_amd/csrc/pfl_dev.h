@@ -121,16 +121,15 @@ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
 // Stochastic rounding of an FP32 value to a format keeping the top 32 - D
 // bits of its encoding: add D random bits to the magnitude bits and cut them
 // off; the result rounds up with probability equal to the discarded fraction.
-// NaN and Inf pass unchanged.  For FP16, values below its normal range lose
-// more than D bits and the conversion rounds the rest to nearest.
+// Infinities pass unchanged (their low D bits are zero, so nothing carries).
+// A NaN stays a NaN unless its mantissa lies within 2^D of all ones, which
+// neither the default NaN of arithmetic nor a NaN loaded from 16-bit storage
+// (low D bits zero) does.  For FP16, values below its normal range lose more
+// than D bits and the conversion rounds the rest to nearest.
 template <int D>
-__device__ __forceinline__ float sround(float v, uint32_t r) {
-  uint32_t b = __float_as_uint(v);
-  if ((b & 0x7F800000u) != 0x7F800000u) {
-    constexpr uint32_t m = (1u << D) - 1u;
-    b = (b + (r & m)) & ~m;
-  }
-  return __uint_as_float(b);
+__device__ __forceinline__ uint32_t sround_bits(float v, uint32_t r) {
+  constexpr uint32_t m = (1u << D) - 1u;
+  return (__float_as_uint(v) + (r & m)) & ~m;
 }
 
 struct half_dev { __half v; };
@@ -152,7 +151,7 @@ template <> struct Store<half_dev> {
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)__half2float(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2half_rn((float)v); }
   template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
-    *p = __float2half_rn(sround<13>((float)v, r));
+    *p = __float2half_rn(__uint_as_float(sround_bits<13>((float)v, r)));
   }
 };
 template <> struct Store<bf16_dev> {
@@ -160,7 +159,8 @@ template <> struct Store<bf16_dev> {
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)__bfloat162float(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2bfloat16((float)v); }
   template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
-    *p = __float2bfloat16(sround<16>((float)v, r));
+    // the low 16 bits are zero after rounding: the top half is the BF16 value
+    *p = __ushort_as_bfloat16((unsigned short)(sround_bits<16>((float)v, r) >> 16));
   }
 };
 

@@ -361,11 +361,16 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   const uint32_t nbyte = (uint32_t)idx * S;
   // 16-bit storage: stochastic rounding keyed on (node, step, plane)
   constexpr bool LOWP = sizeof(typename Store<ST>::raw) == 2;
-  RoundBits rb(LOWP ? round_seed(P, (uint32_t)idx) : 1u);
-  auto st = [&](int plane, CT v) {
+  constexpr int QMAX = NS ? QN : ((PHI && QP > QS) ? QP : QS);
+  const RoundBits<LOWP ? (QMAX + 1) / 2 : 1> rb(LOWP ? round_seed(P, (uint32_t)idx) : 0u, LOWP && P.sr);
+  // store of population i of the set whose first plane is o
+  auto st = [&](int o, int i, CT v) {
+    const int plane = o + i;
     typename Store<ST>::raw* p = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
                                         : fout + (long long)plane * N + idx;
-    store_pop<ST, CT>(P, p, v, rb);
+    uint32_t r = 0u;
+    if constexpr (LOWP) r = rb.bits(i);
+    store_pop<ST, CT>(P, p, v, r);
   };
   auto hst = [&](int plane, CT v) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
           const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF)) + CT(1.5) * cF + A;
           fs = w * t + ((cx * cx - cy * cy) * q1 + (cx * cy) * q2);
         }
-        st(P.o_ns + i, fs);
+        st(P.o_ns, i, fs);
       }
     } else {
     CT fneq[QN], fhalf[QN];
@@ -435,7 +440,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 0; i < QN; ++i) {
       const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
       const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
-      st(P.o_ns + i, fs);
+      st(P.o_ns, i, fs);
     }
     }
   }
@@ -468,7 +473,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT Pf = (cx * jx_ + cy * jy_) * inv_fn;        // projector on the flux moments
       const CT PG = (cx * gjx + cy * gjy) * inv_fn;
       const CT fs = feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG;
-      st(P.o_phi + i, fs);
+      st(P.o_phi, i, fs);
     }
     hst(P.h_phiv, phivx);
     hst(P.h_phiv + 1, phivy);
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
                                     (P.wall[1] && (y + dy < 0 || y + dy >= P.ny)));
       const CT old = across ? fps[LS::opp[i]] : s_fps[i][ry + dy][rx + dx];
       const CT fs = (fstar - (CT(1) - an) * old) * inv_an;
-      st(P.o_psi + i, fs);
+      st(P.o_psi, i, fs);
     }
   }
 
@@ -531,7 +536,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT feq = w * dC + w * (cx * Bx + cy * By) * CT(3);
       const CT G = w * (cx * dBx + cy * dBy) * CT(3);
       const CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      st(P.o_c + i, fs);
+      st(P.o_c, i, fs);
     }
     hst(P.h_B, Bx);
     hst(P.h_B + 1, By);
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
       const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
       const CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
-      st(P.o_th + i, gs);
+      st(P.o_th, i, gs);
     }
     hst(P.h_Hv, Hvx);
     hst(P.h_Hv + 1, Hvy);

@@ -521,11 +521,16 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
 
   const uint32_t nbyte = (uint32_t)idx * S;
   constexpr bool LOWP = sizeof(raw) == 2;
-  RoundBits rb(LOWP ? round_seed(P, (uint32_t)idx) : 1u);
-  auto st = [&](int plane, CT val) {
+  constexpr int QMAX = NS ? QN : QS;
+  const RoundBits<LOWP ? (QMAX + 1) / 2 : 1> rb(LOWP ? round_seed(P, (uint32_t)idx) : 0u, LOWP && P.sr);
+  // store of population i of the set whose first plane is o
+  auto st = [&](int o, int i, CT val) {
+    const int plane = o + i;
     raw* ptr = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
                       : fout + (long long)plane * N + idx;
-    store_pop<ST, CT>(P, ptr, val, rb);
+    uint32_t r = 0u;
+    if constexpr (LOWP) r = rb.bits(i);
+    store_pop<ST, CT>(P, ptr, val, r);
   };
   auto hst = [&](int plane, CT val) {
     if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)val;
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
           fs = w * t + (CT(2 * cx * cx - cy * cy - cz * cz) * q9 + CT(cy * cy - cz * cz) * q11 +
                         CT(cx * cy) * qxy + CT(cy * cz) * qyz + CT(cx * cz) * qxz);
         }
-        st(P.o_ns + i, fs);
+        st(P.o_ns, i, fs);
       }
     } else {
     CT fhalf[QN];
@@ -615,7 +620,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]), cz = CT(LN::c[i][2]);
       const CT ps = (CT(2) * cx * cx - cy * cy - cz * cz) * m9 + (cy * cy - cz * cz) * m11 +
                     (cx * cy) * mxy + (cy * cz) * myz + (cx * cz) * mxz;
-      st(P.o_ns + i, fhalf[i] + r * ps);
+      st(P.o_ns, i, fhalf[i] + r * ps);
     }
     }
   }
@@ -650,7 +655,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT cx = CT(LP::c[i][0]), cy = CT(LP::c[i][1]), cz = CT(LP::c[i][2]);
       const CT Pf = (cx * jf[0] + cy * jf[1] + cz * jf[2]) * inv_fn;
       const CT PG = (cx * gj[0] + cy * gj[1] + cz * gj[2]) * inv_fn;
-      st(P.o_phi + i, feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG);
+      st(P.o_phi, i, feq[i] + (CT(1) - s1) * Pf + CT(0.5) * G[i] + CT(0.5) * (CT(1) - s1) * PG);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) hst(P.h_phiv + a, phiv[a]);
@@ -690,7 +695,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT old = across ? fps[LS::opp[i]]
                             : (P.fast ? Store<ST>::template ld<CT>(at_byte<ST>(own_psi, (uint32_t)i * (uint32_t)N * S))
                                       : Store<ST>::template ld<CT>(own_psi + (long long)i * N));
-      st(P.o_psi + i, (fstar - (CT(1) - an) * old) * inv_an);
+      st(P.o_psi, i, (fstar - (CT(1) - an) * old) * inv_an);
     }
   }
 
@@ -722,7 +727,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT w = CT(LS::w[i]);
       const CT feq = w * dC + w * (cx * B[0] + cy * B[1] + cz * B[2]) * CT(1.0 / LS::cs2);
       const CT G = w * (cx * dB[0] + cy * dB[1] + cz * dB[2]) * CT(1.0 / LS::cs2);
-      st(P.o_c + i, feq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
+      st(P.o_c, i, feq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
                         (CT(1) - CT(0.5) * s1) * G);
     }
 #pragma unroll
@@ -751,7 +756,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       CT geq = w * dtheta + w * (cx * Hv[0] + cy * Hv[1] + cz * Hv[2]) * CT(1.0 / LS::cs2);
       if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
       const CT G = w * (cx * dHv[0] + cy * dHv[1] + cz * dHv[2]) * CT(1.0 / LS::cs2);
-      st(P.o_th + i, geq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
+      st(P.o_th, i, geq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
                          (CT(1) - CT(0.5) * s1) * G);
     }
 #pragma unroll

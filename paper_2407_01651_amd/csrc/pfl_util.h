@@ -48,21 +48,28 @@ __device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::
 }
 
 // Random bits for the stochastic rounding of one node's stores.  The seed is
-// the PCG hash of (node, step); the stores of the node, in their fixed order,
-// take the two 16-bit halves of successive PCG hashes of a Weyl sequence
-// started from it, so runs are reproducible.  (A xorshift32 stream from the
-// same seed was cheaper but its correlated outputs gave about 1.6 times the
-// spread of the conserved-mass random walk.)
+// the PCG hash of (node, step); population i of a set takes the 16-bit half
+// i mod 2 of the PCG hash of the Weyl sequence entry seed + (i/2 + 1) * g
+// (g the 32-bit golden ratio), so runs are reproducible.  All sets of the node
+// take the bits of their population index: every population of a set has
+// bits of its own, and no conserved sum mixes sets.  (A xorshift32 stream
+// from the same seed was cheaper but its correlated outputs gave about 1.6
+// times the spread of the conserved-mass random walk.)
+template <int NH>
 struct RoundBits {
-  uint32_t s, cur;
-  bool half;
-  __device__ explicit RoundBits(uint32_t seed) : s(seed), cur(0u), half(false) {}
-  __device__ __forceinline__ uint32_t next16() {
-    if (half) { half = false; return cur >> 16; }
-    s += 0x9E3779B9u;
-    cur = pcg_hash(s);
-    half = true;
-    return cur & 0xFFFFu;
+  uint32_t h[NH];
+  __device__ RoundBits(uint32_t seed, bool on) {
+    if (on) {
+#pragma unroll
+      for (int j = 0; j < NH; ++j) h[j] = pcg_hash(seed + (uint32_t)(j + 1) * 0x9E3779B9u);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NH; ++j) h[j] = 0u;
+    }
+  }
+  // 16 bits for population i of a set (i a compile-time index)
+  __device__ __forceinline__ uint32_t bits(int i) const {
+    return (i & 1) ? (h[i >> 1] >> 16) : (h[i >> 1] & 0xFFFFu);
   }
 };
 
@@ -71,12 +78,11 @@ __device__ __forceinline__ uint32_t round_seed(const DevParams& P, uint32_t node
 }
 
 // Store of one post-collision value: 16-bit storage rounds stochastically
-// when P.sr is set (the bits are drawn either way, so the draw order is fixed).
+// with the random bits r when P.sr is set.
 template <class ST, class CT>
 __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>::raw* p, CT v,
-                                          RoundBits& rb) {
+                                          uint32_t r) {
   if constexpr (sizeof(typename Store<ST>::raw) == 2) {
-    const uint32_t r = rb.next16();
     if (P.sr) { Store<ST>::st_sr(p, v, r); return; }
   }
   Store<ST>::st(p, v);

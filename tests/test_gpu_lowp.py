@@ -98,8 +98,8 @@ def test_reduced_precision_against_oracle(case, form):
 
 
 def test_stochastic_rounding_is_reproducible():
-    """The rounding bits are a hash of (node, step, plane): two runs from the
-    same inputs give bit-identical states."""
+    """The rounding bits are a hash of (node, step, population index): two
+    runs from the same inputs give bit-identical states."""
     w = workloads.small(nx=45, ny=37, seed=3)
     states = []
     for _ in range(2):
@@ -111,9 +111,9 @@ def test_stochastic_rounding_is_reproducible():
 
 # Spread of the stochastic-rounding drift of sum C on the coupled 128 x 128
 # run (500 steps), measured over eight rounding streams (step counters): mean
-# within one standard error of zero, standard deviation 0.06 (FP16) and 0.4-0.6
-# (BF16).  Round-to-nearest drifts by -10.3 and -29.3.
-SR_SIGMA = {"f16": 0.06, "bf16": 0.5}
+# within two standard errors of zero, standard deviation 0.06-0.09 (FP16) and
+# 0.33-0.6 (BF16).  Round-to-nearest drifts by -10.5 and -29.3.
+SR_SIGMA = {"f16": 0.09, "bf16": 0.5}
 
 
 @pytest.mark.parametrize("store", ["f16", "bf16"])
