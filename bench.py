@@ -168,7 +168,7 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     grad = dp.cpu().tolist()
     run.close()
     return {"workload": name, "storage": store, "steps": steps, "checkpoint_every": K,
-            "reverse_compute": "f32 node-local reverse (the forward's compute type), f64 adjoint state and sums",
+            "reverse_compute": "f32 reverse, adjoint state and scratch (the forward's compute type), f64 parameter sums",
             "forward_ms": round(t_fwd, 3),
             "forward_with_checkpoints_ms": round(t_ck, 3), "backward_ms": round(t_bwd, 3),
             "ratio": round((t_ck + t_bwd) / t_fwd, 3),

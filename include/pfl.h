@@ -118,7 +118,7 @@ typedef struct {
   size_t macros_bytes;      /* PFL_M_COUNT FP64 planes for pfl_get_macros */
   size_t state_bytes;       /* node-form FP64 populations + history (get/set_state) */
   size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce */
-  size_t adj_bytes;         /* FP64 scratch of pfl_step_backward / pfl_init_backward */
+  size_t adj_bytes;         /* scratch of pfl_step_backward / pfl_init_backward */
   size_t raw_bytes;         /* raw image of the current state (pfl_save_raw) */
 } pfl_sizes;
 
@@ -200,29 +200,32 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
 /* Adjoint of one time step (2D) at the current state x^n: given
  * lambda^{n+1} = dL/dx^{n+1} (adj_in), writes lambda^n = (dx^{n+1}/dx^n)^T
  * lambda^{n+1} (adj_out) and adds lambda^{n+1} . dx^{n+1}/d(eps4, k) to
- * dparams[0], dparams[1].  x is the node-form state of pfl_get_state
- * (state_bytes, FP64): pre-collision populations of every set, then the
- * history planes; the step is differentiated in FP64 at the stored state
- * whatever the storage type.  adj_in and adj_out are distinct caller-owned
- * device buffers; dparams is a device FP64 vector [eps4, k, Omega, R_1..R_nbub]
- * (accumulated).  The state is not changed.  Errors: PFL_E_STATE before init
- * or without an adj buffer; PFL_E_UNSUPPORTED in 3D or for field
- * combinations without an adjoint (built: all five sets, psi + C, psi + C +
- * theta, NS + phi, psi alone). */
-int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double* dparams);
+ * dparams[0], dparams[1].  x is the node-form state of pfl_get_state:
+ * pre-collision populations of every set, then the history planes, at the
+ * stored values.  The adjoint has the same layout, one element per entry of
+ * x, in the step's compute type: FP64 (double) for FP64 storage, FP32 (float)
+ * for FP32, FP16 and BF16 storage; the step is differentiated in that type.
+ * adj_in and adj_out are distinct caller-owned device buffers of
+ * state_bytes / 8 elements; dparams is a device FP64 vector
+ * [eps4, k, Omega, R_1..R_nbub] (accumulated in FP64).  The state is not
+ * changed.  Errors: PFL_E_STATE before init or without an adj buffer;
+ * PFL_E_UNSUPPORTED in 3D or for field combinations without an adjoint
+ * (built: all five sets, psi + C, psi + C + theta, NS + phi, psi alone). */
+int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dparams);
 
 /* pfl_step_backward at the state held in a raw image (pfl_save_raw /
  * pfl_step_raw layout) with its step count and first-step flag, instead of
  * the context's current state.  Errors as pfl_step_backward. */
 int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
-                          const double* adj_in, double* adj_out, double* dparams);
+                          const void* adj_in, void* adj_out, double* dparams);
 
 /* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
  * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling
  * (theta0 = -Omega when the heat equation is solved, U0 = -Omega otherwise)
- * and R_b the radius of bubble b.  Uses the seeds and bubbles of the last
- * pfl_init_fields.  Errors as pfl_step_backward. */
-int pfl_init_backward(pfl_ctx* c, const double* adj0, double* dparams);
+ * and R_b the radius of bubble b.  adj0 is lambda^0 in the adjoint type of
+ * pfl_step_backward; the sums are FP64.  Uses the seeds and bubbles of the
+ * last pfl_init_fields.  Errors as pfl_step_backward. */
+int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams);
 
 /* Steps taken since the last init. */
 int64_t pfl_step_count(const pfl_ctx* c);

@@ -231,9 +231,22 @@ class Sim:
     def state_planes(self):
         return int(self.sizes.state_bytes // (8 * self.N))
 
+    @property
+    def adj_dtype(self):
+        """Element type of the adjoint state: the step's compute type (FP64
+        for FP64 storage, FP32 otherwise)."""
+        return torch.float64 if self.p.store == 0 else torch.float32
+
+    def _adj(self, *ts):
+        for t in ts:
+            if t.dtype != self.adj_dtype or not t.is_contiguous() or not t.is_cuda:
+                raise TypeError(f"adjoint tensors must be contiguous {self.adj_dtype} device tensors")
+
     def step_backward(self, lam_in, lam_out, dparams):
-        """lambda^n from lambda^{n+1} at the current state; FP64 device tensors of
-        the node-form state shape; dparams accumulates [eps4, k, Omega, R_b...]."""
+        """lambda^n from lambda^{n+1} at the current state; device tensors of
+        the node-form state shape in adj_dtype; dparams (FP64) accumulates
+        [eps4, k, Omega, R_b...]."""
+        self._adj(lam_in, lam_out)
         _check(_lib.pfl_step_backward(self.ctx, ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
                                       ct.c_void_p(dparams.data_ptr())))
 
@@ -242,11 +255,13 @@ class Sim:
                                  int(step_count), 1 if first else 0))
 
     def step_backward_raw(self, raw, step_count, first, lam_in, lam_out, dparams):
+        self._adj(lam_in, lam_out)
         _check(_lib.pfl_step_backward_raw(self.ctx, ct.c_void_p(raw.data_ptr()), int(step_count), 1 if first else 0,
                                           ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
                                           ct.c_void_p(dparams.data_ptr())))
 
     def init_backward(self, lam0, dparams):
+        self._adj(lam0)
         _check(_lib.pfl_init_backward(self.ctx, ct.c_void_p(lam0.data_ptr()), ct.c_void_p(dparams.data_ptr())))
 
     def reduce(self):

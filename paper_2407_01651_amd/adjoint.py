@@ -85,7 +85,7 @@ class CheckpointedRun:
         of a set carries the derivative with respect to its zeroth moment."""
         sim = self.sim
         P = sim.p
-        lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=torch.float64, device=sim.device)
+        lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=sim.adj_dtype, device=sim.device)
         q_phi = P.phi_q
         q_sc = 5 if sim.dim == 2 else 7
         q_ns = 9 if sim.dim == 2 else 19
@@ -95,10 +95,10 @@ class CheckpointedRun:
             o += q_ns
         if "phi" in f:
             if g_phi is not None:
-                lam[o:o + q_phi] = g_phi.to(sim.device, torch.float64)
+                lam[o:o + q_phi] = g_phi.to(sim.device, sim.adj_dtype)
             o += q_phi
         if "psi" in f and g_psi is not None:
-            lam[o:o + q_sc] = g_psi.to(sim.device, torch.float64)
+            lam[o:o + q_sc] = g_psi.to(sim.device, sim.adj_dtype)
         return lam
 
     def backward(self, lam):
@@ -106,7 +106,7 @@ class CheckpointedRun:
         sim = self.sim
         nb = len(self.w["bubbles"])
         dparams = torch.zeros(3 + nb, dtype=torch.float64, device=sim.device)
-        lam = lam.contiguous().clone()
+        lam = lam.to(sim.adj_dtype).contiguous().clone()
         other = torch.empty_like(lam)
         # seg[0] is the checkpoint itself; seg[j] = x^{s0 + j} stepped image to image
         seg = [None] + self.seg

@@ -6,7 +6,9 @@
 // i becomes the node-form population i of x + c_i at the next step (or of the
 // node itself in direction opp(i) across a wall).
 //
-// Three passes per step, all in FP64 whatever the storage type:
+// Three passes per step, in the forward's compute type (FP64 for FP64
+// storage, FP32 otherwise); the adjoint state and the scratch planes are held
+// in that type, the parameter-gradient sums in FP64:
 //  R1 (tile kernel): recompute the forward step of the tile as the forward
 //     kernel does, then reverse the node-local phase (collisions, forces,
 //     anisotropy, kinetics) by hand.  Writes the adjoints of the node's own
@@ -66,14 +68,14 @@ __device__ __forceinline__ long long push_target(const DevParams& P, int base, i
 // offset c, or, when z - c lies beyond a wall, by the mirror node at the
 // offset reflected on that axis (its ghost at that offset mirrors z).
 struct Reader {
-  long long node;
+  uint32_t node;
   int cx, cy;      // offset as seen from the reader
-  double sign;     // (-1)^(walls crossed): the sign of an odd (antisymmetric) ghost
+  int sign;        // (-1)^(walls crossed): the sign of an odd (antisymmetric) ghost
 };
 __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, int cx, int cy) {
   Reader r;
   int rx = x - cx, ry = y - cy;
-  r.cx = cx; r.cy = cy; r.sign = 1.0;
+  r.cx = cx; r.cy = cy; r.sign = 1;
   if (rx < 0 || rx >= P.nx) {
     if (P.wall[0]) { rx = rx < 0 ? -1 - rx : 2 * P.nx - 1 - rx; r.cx = -cx; r.sign = -r.sign; }
     else rx = rx < 0 ? rx + P.nx : rx - P.nx;
@@ -82,8 +84,19 @@ __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, in
     if (P.wall[1]) { ry = ry < 0 ? -1 - ry : 2 * P.ny - 1 - ry; r.cy = -cy; r.sign = -r.sign; }
     else ry = ry < 0 ? ry + P.ny : ry - P.ny;
   }
-  r.node = (long long)ry * P.nx + rx;
+  r.node = (uint32_t)ry * (uint32_t)P.nx + (uint32_t)rx;
   return r;
+}
+
+// Element `node` of a plane, addressed by a 32-bit byte offset from the
+// plane's base (a plane holds fewer than 2^32 bytes).
+template <class T>
+__device__ __forceinline__ const T& at_node(const T* plane, uint32_t node) {
+  return *(const T*)((const char*)plane + node * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T& at_node(T* plane, uint32_t node) {
+  return *(T*)((char*)plane + node * (uint32_t)sizeof(T));
 }
 
 // ------------------------------------------------------------------- R1
@@ -91,9 +104,9 @@ template <int FIELDS, int QP, class ST, class HT, class CT>
 __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                                                        const typename Store<ST>::raw* __restrict__ fin,
                                                        const HT* __restrict__ hist,
-                                                       const double* __restrict__ lam_in,
-                                                       double* __restrict__ lam_out,
-                                                       double* __restrict__ S) {
+                                                       const CT* __restrict__ lam_in,
+                                                       CT* __restrict__ lam_out,
+                                                       CT* __restrict__ S) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   constexpr bool FLOWX = NS && PHI;
@@ -803,123 +816,127 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 // ------------------------------------------------------------------- R2
 // Adjoint of X = D_phi (x) v0 at every node, from the transposed divergence of
 // the mass-flux force adjoints, reversed through the node's flow quantities.
-__global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, double* __restrict__ S) {
+template <class CT>
+__global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __restrict__ S) {
   using LN = Lat<9>;
-  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (n >= P.N) return;
+  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n0 >= P.N) return;
+  const uint32_t n = (uint32_t)n0;
   const long long N = P.N;
-  const int x = (int)(n % P.nx), y = (int)(n / P.nx);
-  const KP<CT>& K = P.kd;
+  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
+  const KP<CT>& K = kp<CT>(P);
+  auto pl = [&](int k) -> CT* { return S + (long long)k * N; };
   // X-bar_ab(z) = sum over readers 3 drho w c'_a Fm-bar_b(reader) (odd ghosts)
-  CT aX0 = 0, aX1 = 0, aX2 = 0, aX3 = 0;
+  CT aX0 = CT(0), aX1 = CT(0), aX2 = CT(0), aX3 = CT(0);
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const Reader r = reader_of(P, x, y, LN::c[i][0], LN::c[i][1]);
-    const CT f = 3 * K.drho * LN::w[i] * r.sign;
-    const CT fmx = S[AS_FMX * N + r.node], fmy = S[AS_FMY * N + r.node];
-    aX0 += f * r.cx * fmx;   // X_xx feeds Fm_x through c_x
-    aX1 += f * r.cx * fmy;   // X_xy feeds Fm_y through c_x
-    aX2 += f * r.cy * fmx;   // X_yx feeds Fm_x through c_y
-    aX3 += f * r.cy * fmy;   // X_yy feeds Fm_y through c_y
+    const CT f = CT(3.0 * LN::w[i]) * K.drho * CT(r.sign);
+    const CT fmx = at_node(pl(AS_FMX), r.node), fmy = at_node(pl(AS_FMY), r.node);
+    aX0 += f * CT(r.cx) * fmx;   // X_xx feeds Fm_x through c_x
+    aX1 += f * CT(r.cx) * fmy;   // X_xy feeds Fm_y through c_x
+    aX2 += f * CT(r.cy) * fmx;   // X_yx feeds Fm_x through c_y
+    aX3 += f * CT(r.cy) * fmy;   // X_yy feeds Fm_y through c_y
   }
-  const CT phi = S[FW_PHI * N + n], psi = S[FW_PSI * N + n];
-  const CT jx = S[FW_JX * N + n], jy = S[FW_JY * N + n];
-  const CT gx = S[FW_GX * N + n], gy = S[FW_GY * N + n], lap = S[FW_LAP * N + n];
+  const CT phi = at_node(pl(FW_PHI), n), psi = at_node(pl(FW_PSI), n);
+  const CT jx = at_node(pl(FW_JX), n), jy = at_node(pl(FW_JY), n);
+  const CT gx = at_node(pl(FW_GX), n), gy = at_node(pl(FW_GY), n), lap = at_node(pl(FW_LAP), n);
   // forward flow quantities at the node
-  const CT inv = 1 / sqrt(gx * gx + gy * gy + K.dn);
+  const CT inv = CT(1) / sqrt(gx * gx + gy * gy + K.dn);
   const CT nx = gx * inv, ny = gy * inv;
-  const CT om = 1 - phi, dw = om * phi;
-  const CT sharp = K.sharp * (dw > 0 ? dw : CT(0));
+  const CT om = CT(1) - phi, dw = om * phi;
+  const CT sharp = K.sharp * (dw > CT(0) ? dw : CT(0));
   const CT Dx = K.M_phi * (gx - sharp * nx), Dy = K.M_phi * (gy - sharp * ny);
-  const CT h = (psi + 1) * 0.5;
+  const CT h = (psi + CT(1)) * CT(0.5);
   const CT chi = clamp01(h);
   const CT rho = K.rho_g + K.drho * phi;
-  const CT ps1 = psi + 1;
-  const CT mu = 0.5 * om * phi * (1 - 2 * phi) - 2 * K.beta_inter * om * ps1 * ps1 - K.Wphi2 * lap;
+  const CT ps1 = psi + CT(1);
+  const CT mu = CT(0.5) * om * phi * (CT(1) - CT(2) * phi) - CT(2) * K.beta_inter * om * ps1 * ps1 - K.Wphi2 * lap;
   const CT Fsx = K.k_s * mu * gx, Fsy = K.k_s * mu * gy;
   const CT Fby = -(rho - K.rho_l) * K.g;
-  const CT s = (1 - chi) / rho;
-  const CT ux = jx + 0.5 * Fsx, uy = jy + 0.5 * (Fsy + Fby);
-  const CT v0x = s * ux, v0y = s * uy;
+  const CT sc = (CT(1) - chi) / rho;
+  const CT ux = jx + CT(0.5) * Fsx, uy = jy + CT(0.5) * (Fsy + Fby);
+  const CT v0x = sc * ux, v0y = sc * uy;
   // X = D (x) v0
   const CT a_Dx = aX0 * v0x + aX1 * v0y, a_Dy = aX2 * v0x + aX3 * v0y;
   const CT a_v0x = aX0 * Dx + aX2 * Dy, a_v0y = aX1 * Dx + aX3 * Dy;
   // v0 = s (j + (Fs + Fb)/2)
   const CT a_s = a_v0x * ux + a_v0y * uy;
-  const CT a_jx = s * a_v0x, a_jy = s * a_v0y;
-  const CT a_Fsx = 0.5 * s * a_v0x, a_Fsy = 0.5 * s * a_v0y, a_Fby = 0.5 * s * a_v0y;
+  const CT a_jx = sc * a_v0x, a_jy = sc * a_v0y;
+  const CT a_Fsx = CT(0.5) * sc * a_v0x, a_Fsy = CT(0.5) * sc * a_v0y, a_Fby = CT(0.5) * sc * a_v0y;
   const CT a_chi = -a_s / rho;
-  CT a_rho = -a_s * (1 - chi) / (rho * rho) - K.g * a_Fby;
+  CT a_rho = -a_s * (CT(1) - chi) / (rho * rho) - K.g * a_Fby;
   const CT a_mu = K.k_s * (a_Fsx * gx + a_Fsy * gy);
   CT a_gx = a_Fsx * K.k_s * mu + K.M_phi * a_Dx;
   CT a_gy = a_Fsy * K.k_s * mu + K.M_phi * a_Dy;
   const CT a_lap = -K.Wphi2 * a_mu;
-  CT a_phi = a_mu * (0.5 * (1 - 6 * phi + 6 * phi * phi) + 2 * K.beta_inter * ps1 * ps1);
-  CT a_psi = a_mu * (-4 * K.beta_inter * om * ps1);
+  CT a_phi = a_mu * (CT(0.5) * (CT(1) - CT(6) * phi + CT(6) * phi * phi) + CT(2) * K.beta_inter * ps1 * ps1);
+  CT a_psi = a_mu * (CT(-4) * K.beta_inter * om * ps1);
   // D = M (g - sharp n)
   const CT a_sharp = -K.M_phi * (a_Dx * nx + a_Dy * ny);
   const CT a_nx = -K.M_phi * sharp * a_Dx, a_ny = -K.M_phi * sharp * a_Dy;
-  if (dw > 0) a_phi += a_sharp * K.sharp * (1 - 2 * phi);
+  if (dw > CT(0)) a_phi += a_sharp * K.sharp * (CT(1) - CT(2) * phi);
   a_gx += a_nx * inv; a_gy += a_ny * inv;
   const CT a_inv = a_nx * gx + a_ny * gy;
   a_gx -= a_inv * gx * inv * inv * inv;
   a_gy -= a_inv * gy * inv * inv * inv;
   a_phi += a_rho * K.drho;
-  if (h > 0 && h < 1) a_psi += 0.5 * a_chi;
-  S[AS_GPHX * N + n] += a_gx;
-  S[AS_GPHY * N + n] += a_gy;
-  S[AS_LAP * N + n] += a_lap;
-  S[AM_PHI * N + n] += a_phi;
-  S[AM_PSI * N + n] += a_psi;
-  S[AM_JX * N + n] += a_jx;
-  S[AM_JY * N + n] += a_jy;
+  if (h > CT(0) && h < CT(1)) a_psi += CT(0.5) * a_chi;
+  at_node(pl(AS_GPHX), n) += a_gx;
+  at_node(pl(AS_GPHY), n) += a_gy;
+  at_node(pl(AS_LAP), n) += a_lap;
+  at_node(pl(AM_PHI), n) += a_phi;
+  at_node(pl(AM_PSI), n) += a_psi;
+  at_node(pl(AM_JX), n) += a_jx;
+  at_node(pl(AM_JY), n) += a_jy;
 }
 
 // ------------------------------------------------------------------- R3
-template <int FIELDS, int QP>
-__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, const double* __restrict__ S_in,
-                                                           double* __restrict__ S, double* __restrict__ lam_out,
-                                                           double* __restrict__ part) {
+template <int FIELDS, int QP, class CT>
+__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, const CT* __restrict__ S_in,
+                                                           CT* __restrict__ lam_out, double* __restrict__ part) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   using LN = Lat<9>;
   using LS = Lat<5>;
-  using LP = Lat<QP>;
   const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
   const bool live = n0 < P.N;
-  const long long n = live ? n0 : P.N - 1;
+  const uint32_t n = (uint32_t)(live ? n0 : P.N - 1);
   const long long N = P.N;
-  const int x = (int)(n % P.nx), y = (int)(n / P.nx);
-  const KP<CT>& K = P.kd;
+  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
+  const KP<CT>& K = kp<CT>(P);
+  auto pl = [&](int k) -> const CT* { return S_in + (long long)k * N; };
   // transposed isotropic stencils (gradient 3 sum w c f, Laplacian 6 sum w (f - f0))
-  CT a_phi = S_in[AM_PHI * N + n] - 6 * (1 - LN::w[0]) * S_in[AS_LAP * N + n];
-  CT a_psi = S_in[AM_PSI * N + n], a_U = S_in[AM_U * N + n];
+  CT a_phi = at_node(pl(AM_PHI), n) - CT(6.0 * (1.0 - LN::w[0])) * at_node(pl(AS_LAP), n);
+  CT a_psi = at_node(pl(AM_PSI), n), a_U = at_node(pl(AM_U), n);
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const Reader r = reader_of(P, x, y, LN::c[i][0], LN::c[i][1]);
-    const CT w = LN::w[i];
-    a_phi += 3 * w * (r.cx * S_in[AS_GPHX * N + r.node] + r.cy * S_in[AS_GPHY * N + r.node]) +
-             6 * w * S_in[AS_LAP * N + r.node];
-    a_psi += 3 * w * (r.cx * S_in[AS_GPSX * N + r.node] + r.cy * S_in[AS_GPSY * N + r.node]);
-    a_U += 3 * w * (r.cx * S_in[AS_GUX * N + r.node] + r.cy * S_in[AS_GUY * N + r.node]);
+    const CT w3 = CT(3.0 * LN::w[i]), w6 = CT(6.0 * LN::w[i]);
+    const CT cx = CT(r.cx), cy = CT(r.cy);
+    if constexpr (PHI)
+      a_phi += w3 * (cx * at_node(pl(AS_GPHX), r.node) + cy * at_node(pl(AS_GPHY), r.node)) +
+               w6 * at_node(pl(AS_LAP), r.node);
+    if constexpr (PSI) a_psi += w3 * (cx * at_node(pl(AS_GPSX), r.node) + cy * at_node(pl(AS_GPSY), r.node));
+    if constexpr (CC) a_U += w3 * (cx * at_node(pl(AS_GUX), r.node) + cy * at_node(pl(AS_GUY), r.node));
   }
-  CT a_C = S_in[AM_C * N + n];
-  CT a_k1 = S_in[PG_K1 * N + n];
+  CT a_C = at_node(pl(AM_C), n);
+  CT a_k1 = at_node(pl(PG_K1), n);
   if constexpr (CC) {
-    const CT psi = S_in[FW_PSI * N + n], C = S_in[FW_C * N + n];
-    const CT h = (psi + 1) * 0.5;
+    const CT psi = at_node(pl(FW_PSI), n), C = at_node(pl(FW_C), n);
+    const CT h = (psi + CT(1)) * CT(0.5);
     const CT k1 = K.k1;
-    const CT m0 = 1 - k1 * h;
-    const CT U = (C / m0 - 1) / k1;
+    const CT m0 = CT(1) - k1 * h;
+    const CT U = (C / m0 - CT(1)) / k1;
     a_C += a_U / (k1 * m0);
-    a_psi += a_U * C / (2 * m0 * m0);
+    a_psi += a_U * C / (CT(2) * m0 * m0);
     a_k1 += a_U * (C * h / (m0 * m0) - U) / k1;
   }
-  // per-block partial sums of the parameter gradients (fixed order)
+  // per-block partial sums of the parameter gradients (FP64, fixed order)
   {
     __shared__ double s_e[256], s_k[256];
-    s_e[threadIdx.x] = live ? S_in[PG_EPS * N + n] : 0.0;
-    s_k[threadIdx.x] = live ? a_k1 : 0.0;
+    s_e[threadIdx.x] = live ? (double)at_node(pl(PG_EPS), n) : 0.0;
+    s_k[threadIdx.x] = live ? (double)a_k1 : 0.0;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
       if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
@@ -928,11 +945,11 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = s_e[0]; part[2 * blockIdx.x + 1] = s_k[0]; }
   }
   if (!live) return;
-  auto add = [&](int plane, CT v) { lam_out[(long long)plane * N + n] += v; };
+  auto add = [&](int plane, CT v) { at_node(lam_out + (long long)plane * N, n) += v; };
   if constexpr (NS) {
-    const CT ajx = S_in[AM_JX * N + n], ajy = S_in[AM_JY * N + n];
+    const CT ajx = at_node(pl(AM_JX), n), ajy = at_node(pl(AM_JY), n);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) add(P.o_ns + i, LN::c[i][0] * ajx + LN::c[i][1] * ajy);
+    for (int i = 0; i < 9; ++i) add(P.o_ns + i, CT(LN::c[i][0]) * ajx + CT(LN::c[i][1]) * ajy);
   }
   if constexpr (PHI) {
 #pragma unroll
@@ -948,7 +965,7 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
       bool ok = true;
       if (sx < 0 || sx >= P.nx) { if (P.wall[0]) ok = false; else sx = sx < 0 ? sx + P.nx : sx - P.nx; }
       if (sy < 0 || sy >= P.ny) { if (P.wall[1]) ok = false; else sy = sy < 0 ? sy + P.ny : sy - P.ny; }
-      if (ok) v += S_in[(long long)(A_OLD0 + i) * N + (long long)sy * P.nx + sx];
+      if (ok) v += at_node(pl(A_OLD0 + i), (uint32_t)sy * (uint32_t)P.nx + (uint32_t)sx);
       add(P.o_psi + i, v);
     }
   }
@@ -957,7 +974,7 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
     for (int i = 0; i < 5; ++i) add(P.o_c + i, a_C);
   }
   if constexpr (TH) {
-    const CT aH = S_in[AM_H * N + n];
+    const CT aH = at_node(pl(AM_H), n);
 #pragma unroll
     for (int i = 0; i < 5; ++i) add(P.o_th + i, aH);
   }
@@ -989,9 +1006,9 @@ __global__ __launch_bounds__(256) void adj_param_sum_kernel(int nblocks, const d
 // (1 - (1-k) h), theta = theta0 (Omega enters as theta0 = -Omega with the heat
 // equation, as U0 = -Omega without it).  Per node the contributions go to
 // planes: [k1, Omega, radius of the nearest bubble] and the bubble id.
-template <int QP>
+template <int QP, class AT>
 __global__ __launch_bounds__(256) void adj_init_kernel(const DevParams P, int fields,
-                                                       const double* __restrict__ lam0,
+                                                       const AT* __restrict__ lam0,
                                                        double* __restrict__ S) {
   using LP = Lat<QP>;
   using LS = Lat<5>;
@@ -1033,15 +1050,15 @@ __global__ __launch_bounds__(256) void adj_init_kernel(const DevParams P, int fi
   double lphi = 0.0, lC = 0.0, lth = 0.0;
   if (fields & F_PHI) {
 #pragma unroll
-    for (int i = 0; i < QP; ++i) lphi += lam0[(long long)(P.o_phi + i) * N + n] * LP::w[i];
+    for (int i = 0; i < QP; ++i) lphi += (double)lam0[(long long)(P.o_phi + i) * N + n] * LP::w[i];
   }
   if (fields & F_C) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lC += lam0[(long long)(P.o_c + i) * N + n] * LS::w[i];
+    for (int i = 0; i < 5; ++i) lC += (double)lam0[(long long)(P.o_c + i) * N + n] * LS::w[i];
   }
   if (fields & F_TH) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lth += lam0[(long long)(P.o_th + i) * N + n] * LS::w[i];
+    for (int i = 0; i < 5; ++i) lth += (double)lam0[(long long)(P.o_th + i) * N + n] * LS::w[i];
   }
   const double cfac = (1.0 + k1 * U0) * (1.0 - k1 * h);
   double gR = (lphi + lC * cfac) * dphi_dR;
@@ -1077,24 +1094,35 @@ __global__ __launch_bounds__(256) void adj_init_sum_kernel(long long N, const do
   }
 }
 
+// Byte offset of the per-block partials in the scratch buffer, after the
+// A_NPLANES planes of the compute type.
+size_t part_offset(long long N, size_t elem) {
+  return ((size_t)A_NPLANES * (size_t)N * elem + 255) & ~(size_t)255;
+}
+
 template <int FIELDS, int QP, class ST, class HT>
-hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const double* lam_in,
-                      double* lam_out, double* S, double* dparams, hipStream_t s) {
+hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const void* lam_in_v,
+                      void* lam_out_v, void* scratch, double* dparams, hipStream_t s) {
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
-  // the reverse of the node-local phase runs in the forward's compute type
+  // the reverse runs in the forward's compute type, which is also the type
+  // of the adjoint state and of the scratch planes
   using RT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+  const RT* lam_in = (const RT*)lam_in_v;
+  RT* lam_out = (RT*)lam_out_v;
+  RT* S = (RT*)scratch;
+  double* part = (double*)((char*)scratch + part_offset(N, sizeof(RT)));
   hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT>), dim3(tiles), dim3(NT), 0, s, P,
                      (const typename Store<ST>::raw*)fin, (const HT*)hist, lam_in, lam_out, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if constexpr ((FIELDS & F_NS) && (FIELDS & F_PHI)) {
-    hipLaunchKernelGGL(adj_flow_kernel, dim3(nb), dim3(256), 0, s, P, S);
+    hipLaunchKernelGGL((adj_flow_kernel<RT>), dim3(nb), dim3(256), 0, s, P, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  double* part = S + (long long)A_NPLANES * N;
-  hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP>), dim3(nb), dim3(256), 0, s, P, S, S, lam_out, part);
+  hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, (const RT*)S, lam_out,
+                     part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
   return hipGetLastError();
@@ -1102,7 +1130,7 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
 
 template <class ST, class HT>
 hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const void* hist,
-                        const double* lam_in, double* lam_out, double* S, double* dparams, hipStream_t s,
+                        const void* lam_in, void* lam_out, void* S, double* dparams, hipStream_t s,
                         bool& ok) {
   ok = true;
   const bool q9 = P.q_phi == 9;
@@ -1125,9 +1153,14 @@ hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const v
 
 }  // namespace
 
-// FP64 planes of N nodes, plus the per-block partials (2 per 256 nodes, one
-// more plane covers them).
-int adj_scratch_planes() { return A_NPLANES + 1; }
+size_t adj_scratch_bytes(long long N, int store) {
+  const size_t elem = store == 0 ? sizeof(double) : sizeof(float);
+  const size_t nb = (size_t)((N + 255) / 256);
+  const size_t bytes = part_offset(N, elem) + 2 * nb * sizeof(double);
+  // the initial-state adjoint uses four FP64 planes of the same buffer
+  const size_t init = 4 * (size_t)N * sizeof(double);
+  return bytes > init ? bytes : init;
+}
 
 bool adj2d_supported(int fields) {
   switch (fields) {
@@ -1143,7 +1176,7 @@ bool adj2d_supported(int fields) {
 }
 
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
-                             const double* lam_in, double* lam_out, double* scratch, double* dparams,
+                             const void* lam_in, void* lam_out, void* scratch, double* dparams,
                              hipStream_t s, bool& ok) {
   hipError_t e;
   switch (store) {
@@ -1156,16 +1189,24 @@ hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const vo
   return e;
 }
 
-hipError_t launch_adj_init2d(const DevParams& P, int fields, const double* lam0, double* scratch,
+hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s) {
   const unsigned nb = (unsigned)((P.N + 255) / 256);
-  if (P.q_phi == 9)
-    hipLaunchKernelGGL((adj_init_kernel<9>), dim3(nb), dim3(256), 0, s, P, fields, lam0, scratch);
-  else
-    hipLaunchKernelGGL((adj_init_kernel<5>), dim3(nb), dim3(256), 0, s, P, fields, lam0, scratch);
+  double* S = (double*)scratch;
+  if (store == 0) {
+    if (P.q_phi == 9)
+      hipLaunchKernelGGL((adj_init_kernel<9, double>), dim3(nb), dim3(256), 0, s, P, fields, (const double*)lam0, S);
+    else
+      hipLaunchKernelGGL((adj_init_kernel<5, double>), dim3(nb), dim3(256), 0, s, P, fields, (const double*)lam0, S);
+  } else {
+    if (P.q_phi == 9)
+      hipLaunchKernelGGL((adj_init_kernel<9, float>), dim3(nb), dim3(256), 0, s, P, fields, (const float*)lam0, S);
+    else
+      hipLaunchKernelGGL((adj_init_kernel<5, float>), dim3(nb), dim3(256), 0, s, P, fields, (const float*)lam0, S);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_init_sum_kernel, dim3(2 + P.nbub), dim3(256), 0, s, P.N, scratch, P.nbub, dparams);
+  hipLaunchKernelGGL(adj_init_sum_kernel, dim3(2 + P.nbub), dim3(256), 0, s, P.N, S, P.nbub, dparams);
   return hipGetLastError();
 }
 

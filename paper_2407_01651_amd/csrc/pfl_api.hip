@@ -156,7 +156,7 @@ int pfl_query_sizes(const pfl_params* p, pfl_sizes* out) {
   out->macros_bytes = L.macros_bytes;
   out->state_bytes = L.state_bytes;
   out->reduce_bytes = L.reduce_bytes;
-  out->adj_bytes = p->dim == 2 ? (size_t)adj_scratch_planes() * L.N * sizeof(double) : 0;
+  out->adj_bytes = p->dim == 2 ? adj_scratch_bytes(L.N, p->store) : 0;
   out->raw_bytes = L.pops_bytes + L.hist_bytes;
   g_err.clear();
   return PFL_OK;
@@ -467,7 +467,7 @@ static int adj_check(pfl_ctx* c) {
   return PFL_OK;
 }
 
-int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double* dparams) {
+int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dparams) {
   int rc = adj_check(c);
   if (rc) return rc;
   if (!adj_in || !adj_out || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
@@ -475,7 +475,7 @@ int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double*
   const void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   bool ok = true;
   hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, adj_in, adj_out,
-                                   (double*)c->b.adj, dparams, c->s, ok);
+                                   c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
   g_err.clear();
@@ -483,7 +483,7 @@ int pfl_step_backward(pfl_ctx* c, const double* adj_in, double* adj_out, double*
 }
 
 int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
-                          const double* adj_in, double* adj_out, double* dparams) {
+                          const void* adj_in, void* adj_out, double* dparams) {
   int rc = adj_check(c);
   if (rc) return rc;
   if (!raw_state || !adj_in || !adj_out || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
@@ -495,18 +495,18 @@ int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count,
   bool ok = true;
   hipError_t e = launch_adj_step2d(d, (int)c->p.fields, c->p.store, raw_state,
                                    (const char*)raw_state + c->L.pops_bytes, adj_in, adj_out,
-                                   (double*)c->b.adj, dparams, c->s, ok);
+                                   c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
   g_err.clear();
   return PFL_OK;
 }
 
-int pfl_init_backward(pfl_ctx* c, const double* adj0, double* dparams) {
+int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams) {
   int rc = adj_check(c);
   if (rc) return rc;
   if (!adj0 || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
-  hipError_t e = launch_adj_init2d(c->d, (int)c->p.fields, adj0, (double*)c->b.adj, dparams, c->s);
+  hipError_t e = launch_adj_init2d(c->d, (int)c->p.fields, c->p.store, adj0, c->b.adj, dparams, c->s);
   if (e != hipSuccess) return hip_fail(e, "initial-state adjoint kernels");
   g_err.clear();
   return PFL_OK;

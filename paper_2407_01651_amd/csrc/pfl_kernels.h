@@ -24,16 +24,16 @@ inline hipError_t launch_step(const DevParams& P, int fields, int store, const v
                     : launch_step2d(P, fields, store, fin, fout, hist, mout, mode, s, ok);
 }
 
-// Adjoint of one 2D step at the state fin/hist (node-form FP64 adjoints
-// lam_in -> lam_out, parameter gradient accumulated into dparams[0..1]) and of
-// the initial state (dparams[1..]).  scratch holds adj_scratch_planes() FP64
-// planes of N nodes.
-int adj_scratch_planes();
+// Adjoint of one 2D step at the state fin/hist (node-form adjoints lam_in ->
+// lam_out in the compute type: FP64 for FP64 storage, FP32 otherwise;
+// parameter gradient accumulated into the FP64 dparams[0..1]) and of the
+// initial state (dparams[1..]).  scratch holds adj_scratch_bytes(N, store).
+size_t adj_scratch_bytes(long long N, int store);
 bool adj2d_supported(int fields);
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
-                             const double* lam_in, double* lam_out, double* scratch, double* dparams,
+                             const void* lam_in, void* lam_out, void* scratch, double* dparams,
                              hipStream_t s, bool& ok);
-hipError_t launch_adj_init2d(const DevParams& P, int fields, const double* lam0, double* scratch,
+hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
