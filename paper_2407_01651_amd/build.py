@@ -8,10 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step2d_lowp.hip", "pfl_step3d.hip", "pfl_step3d_lowp.hip",
-       "pfl_adj2d.hip", "pfl_aux.hip"]
-# FP32-compute step instantiations: contraction (FMA) and reassociation are
-# allowed; the FP64 parity form and everything else is built without them.
-LOWP = {"pfl_step2d_lowp.hip", "pfl_step3d_lowp.hip"}
+       "pfl_adj2d.hip", "pfl_adj2d_lowp.hip", "pfl_aux.hip"]
+# FP32-compute instantiations of the step and its adjoint: contraction (FMA)
+# and reassociation are allowed; the FP64 parity form and everything else is
+# built without them.
+LOWP = {"pfl_step2d_lowp.hip", "pfl_step3d_lowp.hip", "pfl_adj2d_lowp.hip"}
 LOWP_FLAGS = ["-ffp-contract=fast", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math",
               "-freciprocal-math"]
 OUT = os.path.join(HERE, "libpfl.so")

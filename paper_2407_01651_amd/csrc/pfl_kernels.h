@@ -35,6 +35,10 @@ hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const vo
                              hipStream_t s, bool& ok);
 hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s);
+// The FP32-compute part of launch_adj_step2d (stores 1-3).
+hipError_t launch_adj_step2d_lowp(const DevParams& P, int fields, int store, const void* fin, const void* hist,
+                                  const void* lam_in, void* lam_out, void* scratch, double* dparams,
+                                  hipStream_t s, bool& ok);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
 // planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium
