@@ -12,8 +12,10 @@ the segment's states are recomputed from its checkpoint image to image with
 pfl_step_raw (same stochastic rounding keys, so bit-identical), then
 pfl_step_backward_raw takes the node-form adjoint back one step at a time at
 each image and accumulates dL/d(eps4, k); finally pfl_init_backward adds the
-gradient through the initial profiles.  Memory: one raw image per checkpoint
-plus K - 1 raw images for the segment being reversed.
+gradient through the initial profiles.  The recompute of the previous segment
+runs on a second stream (its own forward-only context) while the current
+segment is reversed, into a second set of segment images.  Memory: one raw
+image per checkpoint plus 2 (K - 1) raw images.
 Every step of the path runs in the library's kernels; this module only
 orders the calls and holds the buffers.
 """
@@ -50,12 +52,18 @@ def params_of(w):
 class CheckpointedRun:
     """Forward with checkpoints and the adjoint sweep over it."""
 
-    def __init__(self, w, store="f64", K=100, device="cuda:0", steps=None):
+    def __init__(self, w, store="f64", K=100, device="cuda:0", steps=None, overlap=True):
         self.w = w
         self.K = int(K)
         self.sim = Sim(w, store=store, device=device, adjoint=True)
+        # recompute context on a second stream (default priority)
+        self.overlap = bool(overlap)
+        self.rstream = torch.cuda.Stream(device=self.sim.device) if self.overlap else None
+        self.rsim = Sim(w, store=store, device=device, stream=self.rstream) if self.overlap else self.sim
+        if self.overlap:
+            self.rsim.init_fields()        # grain map and angles for its pfl_step_raw
         self.ckpts = []
-        self.seg = []
+        self.seg = [[], []]
         self.steps = 0
         if steps is not None:
             self._reserve(int(steps))
@@ -67,8 +75,9 @@ class CheckpointedRun:
         n_ck = (steps + self.K - 1) // self.K
         while len(self.ckpts) < n_ck:
             self.ckpts.append(sim.raw_buffer())
-        while len(self.seg) < min(self.K, steps) - 1:
-            self.seg.append(sim.raw_buffer())
+        for st in self.seg[:2 if self.overlap else 1]:
+            while len(st) < min(self.K, steps) - 1:
+                st.append(sim.raw_buffer())
 
     def forward(self, steps):
         sim = self.sim
@@ -101,29 +110,62 @@ class CheckpointedRun:
             lam[o:o + q_sc] = g_psi.to(sim.device, sim.adj_dtype)
         return lam
 
+    def _images(self, si):
+        """Images of segment si: its checkpoint, then x^{s0 + j} for j >= 1."""
+        return [self.ckpts[si]] + self.seg[si % 2 if self.overlap else 0]
+
+    def _recompute(self, si):
+        s0 = si * self.K
+        n = min(self.K, self.steps - s0)
+        img = self._images(si)
+        for j in range(n - 1):
+            self.rsim.step_raw(img[j], img[j + 1], s0 + j, s0 + j == 0)
+
     def backward(self, lam):
         """dL/dp from the node-form adjoint lam of the final state."""
         sim = self.sim
+        main = sim.stream
         nb = len(self.w["bubbles"])
         dparams = torch.zeros(3 + nb, dtype=torch.float64, device=sim.device)
         lam = lam.to(sim.adj_dtype).contiguous().clone()
         other = torch.empty_like(lam)
-        # seg[0] is the checkpoint itself; seg[j] = x^{s0 + j} stepped image to image
-        seg = [None] + self.seg
         n_ck = (self.steps + self.K - 1) // self.K
+        if self.overlap:
+            # recompute of segment si - 1 (stream 2) runs beside the reverse of
+            # segment si (main stream); a set of images is reused once the
+            # reverse that read it has finished
+            start = torch.cuda.Event()
+            start.record(main)
+            self.rstream.wait_event(start)
+            ready = [torch.cuda.Event() for _ in range(n_ck)]
+            freed = [torch.cuda.Event(), torch.cuda.Event()]
+            self._recompute(n_ck - 1)
+            ready[n_ck - 1].record(self.rstream)
         for si in range(n_ck - 1, -1, -1):
             s0 = si * self.K
             n = min(self.K, self.steps - s0)
-            seg[0] = self.ckpts[si]
-            for j in range(n - 1):
-                sim.step_raw(seg[j], seg[j + 1], s0 + j, s0 + j == 0)
+            if self.overlap:
+                if si > 0:
+                    if si + 1 < n_ck:
+                        self.rstream.wait_event(freed[(si - 1) % 2])
+                    self._recompute(si - 1)
+                    ready[si - 1].record(self.rstream)
+                main.wait_event(ready[si])
+            else:
+                self._recompute(si)
+            img = self._images(si)
             for j in range(n - 1, -1, -1):
-                sim.step_backward_raw(seg[j], s0 + j, s0 + j == 0, lam, other, dparams)
+                sim.step_backward_raw(img[j], s0 + j, s0 + j == 0, lam, other, dparams)
                 lam, other = other, lam
+            if self.overlap:
+                freed[si % 2].record(main)
         sim.init_backward(lam, dparams)
         return dparams
 
     def close(self):
+        if self.overlap:
+            torch.cuda.synchronize(self.sim.device)
+            self.rsim.close()
         self.sim.close()
 
 
