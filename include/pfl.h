@@ -120,6 +120,7 @@ typedef struct {
   size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce */
   size_t adj_bytes;         /* scratch of pfl_step_backward / pfl_init_backward */
   size_t raw_bytes;         /* raw image of the current state (pfl_save_raw) */
+  size_t tape_bytes;        /* one step tape (pfl_step_raw_taped); 0 in 3D */
 } pfl_sizes;
 
 typedef struct {
@@ -218,6 +219,23 @@ int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dpa
  * the context's current state.  Errors as pfl_step_backward. */
 int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
                           const void* adj_in, void* adj_out, double* dparams);
+
+/* pfl_step_raw that also writes the step's tape (2D): the results of the
+ * step's finite-difference stencils at every node, in the step's compute type
+ * (FP64 for FP64 storage, FP32 otherwise), nine planes of N nodes: grad phi
+ * (x, y), Laplacian of phi, grad psi (x, y), grad U (x, y) and the mass-flux
+ * force (x, y) (zero where a set is not evolved).  tape is caller-owned device
+ * memory of tape_bytes.  The state written is the same as pfl_step_raw's.
+ * Errors as pfl_step_raw; PFL_E_UNSUPPORTED in 3D. */
+int pfl_step_raw_taped(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first,
+                       void* tape);
+
+/* pfl_step_backward_raw with the step's stencil results taken from the tape
+ * that pfl_step_raw_taped wrote for the same step from the same image, instead
+ * of recomputing them (the reverse then does no halo work).  Errors as
+ * pfl_step_backward. */
+int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+                            const void* tape, const void* adj_in, void* adj_out, double* dparams);
 
 /* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
  * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling

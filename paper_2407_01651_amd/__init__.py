@@ -57,7 +57,8 @@ class Bubble(ct.Structure):
 
 class Sizes(ct.Structure):
     _fields_ = [(n, ct.c_size_t) for n in ("pops_bytes", "hist_bytes", "aux_bytes", "macros_bytes",
-                                          "state_bytes", "reduce_bytes", "adj_bytes", "raw_bytes")]
+                                          "state_bytes", "reduce_bytes", "adj_bytes", "raw_bytes",
+                                          "tape_bytes")]
 
 
 class Buffers(ct.Structure):
@@ -87,6 +88,9 @@ _sig = {
     "pfl_step_raw": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int], ct.c_int),
     "pfl_step_backward_raw": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p,
                                ct.c_void_p], ct.c_int),
+    "pfl_step_raw_taped": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p], ct.c_int),
+    "pfl_step_backward_taped": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                 ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_init_backward": ([ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_destroy": ([ct.c_void_p], ct.c_int),
     "pfl_last_error": ([], ct.c_char_p),
@@ -221,6 +225,21 @@ class Sim:
     def raw_buffer(self):
         """A device buffer that holds one raw state image."""
         return torch.empty(int(self.sizes.raw_bytes), dtype=torch.uint8, device=self.device)
+
+    def tape_buffer(self):
+        """A device buffer that holds one step tape (2D)."""
+        return torch.empty(max(int(self.sizes.tape_bytes), 256), dtype=torch.uint8, device=self.device)
+
+    def step_raw_taped(self, raw_in, raw_out, step_count, first, tape):
+        _check(_lib.pfl_step_raw_taped(self.ctx, ct.c_void_p(raw_in.data_ptr()), ct.c_void_p(raw_out.data_ptr()),
+                                       int(step_count), 1 if first else 0, ct.c_void_p(tape.data_ptr())))
+
+    def step_backward_taped(self, raw, step_count, first, tape, lam_in, lam_out, dparams):
+        self._adj(lam_in, lam_out)
+        _check(_lib.pfl_step_backward_taped(self.ctx, ct.c_void_p(raw.data_ptr()), int(step_count),
+                                            1 if first else 0, ct.c_void_p(tape.data_ptr()),
+                                            ct.c_void_p(lam_in.data_ptr()), ct.c_void_p(lam_out.data_ptr()),
+                                            ct.c_void_p(dparams.data_ptr())))
 
     def save_raw(self, dst):
         _check(_lib.pfl_save_raw(self.ctx, ct.c_void_p(dst.data_ptr())))

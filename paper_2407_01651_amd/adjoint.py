@@ -9,13 +9,15 @@ the final phi and psi; its backward gives dL/dp for any loss L of them.
 Forward: one launch per step, with a raw checkpoint of the state (storage
 type, bit-exact) every K steps.  Backward, segment by segment from the last:
 the segment's states are recomputed from its checkpoint image to image with
-pfl_step_raw (same stochastic rounding keys, so bit-identical), then
-pfl_step_backward_raw takes the node-form adjoint back one step at a time at
-each image and accumulates dL/d(eps4, k); finally pfl_init_backward adds the
-gradient through the initial profiles.  The recompute of the previous segment
-runs on a second stream (its own forward-only context) while the current
-segment is reversed, into a second set of segment images.  Memory: one raw
-image per checkpoint plus 2 (K - 1) raw images.
+pfl_step_raw_taped (same stochastic rounding keys, so bit-identical), which
+also keeps each step's stencil results (its tape), then
+pfl_step_backward_taped takes the node-form adjoint back one step at a time at
+each image, with that step's tape, and accumulates dL/d(eps4, k); finally
+pfl_init_backward adds the gradient through the initial profiles.  The
+recompute of the previous segment runs on a second stream (its own
+forward-only context) while the current segment is reversed, into a second
+set of segment images and tapes.  Memory: one raw image per checkpoint plus
+2 (K - 1) raw images and 2 K tapes (nine planes of N values each).
 Every step of the path runs in the library's kernels; this module only
 orders the calls and holds the buffers.
 """
@@ -52,7 +54,7 @@ def params_of(w):
 class CheckpointedRun:
     """Forward with checkpoints and the adjoint sweep over it."""
 
-    def __init__(self, w, store="f64", K=100, device="cuda:0", steps=None, overlap=True):
+    def __init__(self, w, store="f64", K=100, device="cuda:0", steps=None, overlap=True, taped=True):
         self.w = w
         self.K = int(K)
         self.sim = Sim(w, store=store, device=device, adjoint=True)
@@ -62,8 +64,11 @@ class CheckpointedRun:
         self.rsim = Sim(w, store=store, device=device, stream=self.rstream) if self.overlap else self.sim
         if self.overlap:
             self.rsim.init_fields()        # grain map and angles for its pfl_step_raw
+        self.taped = bool(taped)
         self.ckpts = []
         self.seg = [[], []]
+        self.tapes = [[], []]
+        self.sink = None
         self.steps = 0
         if steps is not None:
             self._reserve(int(steps))
@@ -75,9 +80,16 @@ class CheckpointedRun:
         n_ck = (steps + self.K - 1) // self.K
         while len(self.ckpts) < n_ck:
             self.ckpts.append(sim.raw_buffer())
-        for st in self.seg[:2 if self.overlap else 1]:
+        nsets = 2 if self.overlap else 1
+        for st in self.seg[:nsets]:
             while len(st) < min(self.K, steps) - 1:
                 st.append(sim.raw_buffer())
+        if self.taped:
+            for tp in self.tapes[:nsets]:
+                while len(tp) < min(self.K, steps):
+                    tp.append(sim.tape_buffer())
+            if self.sink is None:
+                self.sink = sim.raw_buffer()
 
     def forward(self, steps):
         sim = self.sim
@@ -114,12 +126,22 @@ class CheckpointedRun:
         """Images of segment si: its checkpoint, then x^{s0 + j} for j >= 1."""
         return [self.ckpts[si]] + self.seg[si % 2 if self.overlap else 0]
 
+    def _tapes(self, si):
+        return self.tapes[si % 2 if self.overlap else 0]
+
     def _recompute(self, si):
         s0 = si * self.K
         n = min(self.K, self.steps - s0)
         img = self._images(si)
-        for j in range(n - 1):
-            self.rsim.step_raw(img[j], img[j + 1], s0 + j, s0 + j == 0)
+        if self.taped:
+            # every step of the segment, the last one only for its tape
+            tp = self._tapes(si)
+            for j in range(n):
+                out = img[j + 1] if j + 1 < n else self.sink
+                self.rsim.step_raw_taped(img[j], out, s0 + j, s0 + j == 0, tp[j])
+        else:
+            for j in range(n - 1):
+                self.rsim.step_raw(img[j], img[j + 1], s0 + j, s0 + j == 0)
 
     def backward(self, lam):
         """dL/dp from the node-form adjoint lam of the final state."""
@@ -154,8 +176,12 @@ class CheckpointedRun:
             else:
                 self._recompute(si)
             img = self._images(si)
+            tp = self._tapes(si) if self.taped else None
             for j in range(n - 1, -1, -1):
-                sim.step_backward_raw(img[j], s0 + j, s0 + j == 0, lam, other, dparams)
+                if self.taped:
+                    sim.step_backward_taped(img[j], s0 + j, s0 + j == 0, tp[j], lam, other, dparams)
+                else:
+                    sim.step_backward_raw(img[j], s0 + j, s0 + j == 0, lam, other, dparams)
                 lam, other = other, lam
             if self.overlap:
                 freed[si % 2].record(main)

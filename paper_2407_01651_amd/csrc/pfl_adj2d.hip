@@ -128,15 +128,15 @@ bool adj2d_supported(int fields) {
 }
 
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
-                             const void* lam_in, void* lam_out, void* scratch, double* dparams,
-                             hipStream_t s, bool& ok) {
+                             const void* tape, const void* lam_in, void* lam_out, void* scratch,
+                             double* dparams, hipStream_t s, bool& ok) {
   hipError_t e;
   switch (store) {
-    case 0: e = adj_dispatch<double, double>(P, fields, fin, hist, lam_in, lam_out, scratch, dparams, s, ok); break;
+    case 0: e = adj_dispatch<double, double>(P, fields, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, ok); break;
     case 1:
     case 2:
     case 3:
-      return launch_adj_step2d_lowp(P, fields, store, fin, hist, lam_in, lam_out, scratch, dparams, s, ok);
+      return launch_adj_step2d_lowp(P, fields, store, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, ok);
     default: ok = false; return hipSuccess;
   }
   return e;

@@ -119,10 +119,14 @@ __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, in
 
 
 // ------------------------------------------------------------------- R1
-template <int FIELDS, int QP, class ST, class HT, class CT>
+// TAPED: the step's stencil results (grad and Laplacian of phi, grad psi,
+// grad U, mass-flux force) are read from the tape the forward step wrote, so
+// the tile's halo and its LDS stencils are not redone.
+template <int FIELDS, int QP, class ST, class HT, class CT, bool TAPED>
 __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                                                        const typename Store<ST>::raw* __restrict__ fin,
                                                        const HT* __restrict__ hist,
+                                                       const CT* __restrict__ tape,
                                                        const CT* __restrict__ lam_in,
                                                        CT* __restrict__ lam_out,
                                                        CT* __restrict__ S) {
@@ -213,11 +217,14 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fth[i] += CT(P.ref_th[i]); H += fth[i]; }
     }
-    s_phi[ly + R][lx + R] = phi;
-    s_psi[ly + R][lx + R] = psi;
-    s_U[ly + R][lx + R] = U;
-    if constexpr (NS) { s_jx[ly + R][lx + R] = jx; s_jy[ly + R][lx + R] = jy; }
+    if constexpr (!TAPED) {
+      s_phi[ly + R][lx + R] = phi;
+      s_psi[ly + R][lx + R] = psi;
+      s_U[ly + R][lx + R] = U;
+      if constexpr (NS) { s_jx[ly + R][lx + R] = jx; s_jy[ly + R][lx + R] = jy; }
+    }
   }
+  if constexpr (!TAPED) {
   for (int k = tid; k < RX * RY; k += NT) {
     const int rx = k % RX, ry = k / RX;
     const int tx = rx - R, ty = ry - R;
@@ -268,10 +275,11 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     if constexpr (NS) { s_jx[ry][rx] = hjx; s_jy[ry][rx] = hjy; }
   }
   __syncthreads();
+  }
 
   // ---- forward phase B
   FlowNode<CT> fo;
-  if constexpr (FLOWX) {
+  if constexpr (FLOWX && !TAPED) {
     constexpr int AX = TX + 2, AY = TY + 2;
     for (int k = tid; k < AX * AY; k += NT) {
       const int rx = k % AX + R - 1, ry = k / AX + R - 1;
@@ -300,7 +308,11 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   }
   if (!own) return;
   const int ry = ly + R, rx = lx + R;
-  flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, ry, rx, fo);
+  auto tp = [&](int k) -> CT { return tape[(long long)k * N + idx]; };
+  if constexpr (TAPED)
+    flow_node_from<NS, CT>(K, phi, psi, jx, jy, tp(0), tp(1), tp(2), fo);
+  else
+    flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, ry, rx, fo);
 
   // forward values needed by the later passes
   S[FW_PHI * N + idx] = phi;
@@ -318,8 +330,12 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   const CT q = clamp01(qraw);
   const CT theta = TH ? (H + h) : K.theta0;
   CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
-  if constexpr (PSI) grad9<CT, RX>(s_psi, ry, rx, gpx, gpy);
-  if constexpr (CC) grad9<CT, RX>(s_U, ry, rx, gUx, gUy);
+  if constexpr (TAPED) {
+    gpx = tp(3); gpy = tp(4); gUx = tp(5); gUy = tp(6);
+  } else {
+    if constexpr (PSI) grad9<CT, RX>(s_psi, ry, rx, gpx, gpy);
+    if constexpr (CC) grad9<CT, RX>(s_U, ry, rx, gUx, gUy);
+  }
   const CT dn = K.dn;
   const CT invp = CT(1) / sqrt(gpx * gpx + gpy * gpy + dn);
   const CT ex = gpx * invp, ey = gpy * invp;
@@ -360,7 +376,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   const CT grx = K.drho * fo.gx, gry = K.drho * fo.gy;
   const CT c0 = LN::cs2 / (CT(1.0) - CT(LN::w[0]));
   if constexpr (NS) {
-    if constexpr (FLOWX) {
+    if constexpr (TAPED) {
+      Fmx = tp(7);
+      Fmy = tp(8);
+    } else if constexpr (FLOWX) {
       const CT w1 = CT(CT(1.0) / 9), w2 = CT(CT(1.0) / 36);
       auto Xs = [&](int c, int dy, int dx) { return s_X[c][ry + dy][rx + dx]; };
       const CT ax0 = w1 * (Xs(0, 0, 1) - Xs(0, 0, -1)) + w2 * ((Xs(0, 1, 1) - Xs(0, 1, -1)) + (Xs(0, -1, 1) - Xs(0, -1, -1)));
@@ -1025,8 +1044,8 @@ inline size_t part_offset(long long N, size_t elem) {
 }
 
 template <int FIELDS, int QP, class ST, class HT>
-hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const void* lam_in_v,
-                      void* lam_out_v, void* scratch, double* dparams, hipStream_t s) {
+hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const void* tape_v,
+                      const void* lam_in_v, void* lam_out_v, void* scratch, double* dparams, hipStream_t s) {
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
@@ -1037,8 +1056,13 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
   RT* lam_out = (RT*)lam_out_v;
   RT* S = (RT*)scratch;
   double* part = (double*)((char*)scratch + part_offset(N, sizeof(RT)));
-  hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT>), dim3(tiles), dim3(NT), 0, s, P,
-                     (const typename Store<ST>::raw*)fin, (const HT*)hist, lam_in, lam_out, S);
+  const RT* tape = (const RT*)tape_v;
+  if (tape)
+    hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true>), dim3(tiles), dim3(NT), 0, s, P,
+                       (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
+  else
+    hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false>), dim3(tiles), dim3(NT), 0, s, P,
+                       (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if constexpr ((FIELDS & F_NS) && (FIELDS & F_PHI)) {
@@ -1053,15 +1077,15 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
 }
 
 template <class ST, class HT>
-hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const void* hist,
+hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const void* hist, const void* tape,
                         const void* lam_in, void* lam_out, void* S, double* dparams, hipStream_t s,
                         bool& ok) {
   ok = true;
   const bool q9 = P.q_phi == 9;
 #define PFL_ADJ(F)                                                                               \
   case F:                                                                                        \
-    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, lam_in, lam_out, S, dparams, s)           \
-              : adj_step_t<F, 5, ST, HT>(P, fin, hist, lam_in, lam_out, S, dparams, s);
+    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s)     \
+              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s);
   switch (fields) {
     PFL_ADJ(F_NS | F_PHI | F_PSI | F_C | F_TH)
     PFL_ADJ(F_PSI | F_C)

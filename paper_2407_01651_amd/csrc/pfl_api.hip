@@ -158,6 +158,7 @@ int pfl_query_sizes(const pfl_params* p, pfl_sizes* out) {
   out->reduce_bytes = L.reduce_bytes;
   out->adj_bytes = p->dim == 2 ? adj_scratch_bytes(L.N, p->store) : 0;
   out->raw_bytes = L.pops_bytes + L.hist_bytes;
+  out->tape_bytes = p->dim == 2 ? (size_t)TAPE_PLANES * L.N * (p->store == 0 ? sizeof(double) : sizeof(float)) : 0;
   g_err.clear();
   return PFL_OK;
 }
@@ -440,7 +441,7 @@ int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first)
   return PFL_OK;
 }
 
-int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first) {
+static int step_image(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first, void* tape) {
   if (!c || !raw_in || !raw_out) return fail(PFL_E_INVALID_ARG, "null argument");
   if (!c->inited) return fail(PFL_E_STATE, "step before init");
   if (raw_in == raw_out) return fail(PFL_E_INVALID_ARG, "raw_in and raw_out must differ");
@@ -449,6 +450,7 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
   d.first = first ? 1 : 0;
   d.step_ctr = (uint32_t)step_count;
   d.hist_src = (const char*)raw_in + c->L.pops_bytes;
+  d.tape = tape;
   bool ok = true;
   hipError_t e = launch_step(d, (int)c->p.fields, c->p.store, raw_in, raw_out,
                              (char*)raw_out + c->L.pops_bytes, nullptr, 0, c->s, ok);
@@ -456,6 +458,17 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
   if (e != hipSuccess) return hip_fail(e, "step kernel");
   g_err.clear();
   return PFL_OK;
+}
+
+int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first) {
+  return step_image(c, raw_in, raw_out, step_count, first, nullptr);
+}
+
+int pfl_step_raw_taped(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first,
+                       void* tape) {
+  if (!c || !tape) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the step tape is built for 2D");
+  return step_image(c, raw_in, raw_out, step_count, first, tape);
 }
 
 static int adj_check(pfl_ctx* c) {
@@ -474,7 +487,7 @@ int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dpa
   if (adj_in == adj_out) return fail(PFL_E_INVALID_ARG, "adj_in and adj_out must differ");
   const void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   bool ok = true;
-  hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, adj_in, adj_out,
+  hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, nullptr, adj_in, adj_out,
                                    c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
@@ -482,7 +495,7 @@ int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dpa
   return PFL_OK;
 }
 
-int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+static int backward_image(pfl_ctx* c, const void* raw_state, int64_t step_count, int first, const void* tape,
                           const void* adj_in, void* adj_out, double* dparams) {
   int rc = adj_check(c);
   if (rc) return rc;
@@ -494,12 +507,23 @@ int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count,
   d.step_ctr = (uint32_t)step_count;
   bool ok = true;
   hipError_t e = launch_adj_step2d(d, (int)c->p.fields, c->p.store, raw_state,
-                                   (const char*)raw_state + c->L.pops_bytes, adj_in, adj_out,
+                                   (const char*)raw_state + c->L.pops_bytes, tape, adj_in, adj_out,
                                    c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
   g_err.clear();
   return PFL_OK;
+}
+
+int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+                          const void* adj_in, void* adj_out, double* dparams) {
+  return backward_image(c, raw_state, step_count, first, nullptr, adj_in, adj_out, dparams);
+}
+
+int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
+                            const void* tape, const void* adj_in, void* adj_out, double* dparams) {
+  if (!tape) return fail(PFL_E_INVALID_ARG, "null tape");
+  return backward_image(c, raw_state, step_count, first, tape, adj_in, adj_out, dparams);
 }
 
 int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams) {

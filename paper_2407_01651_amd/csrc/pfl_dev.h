@@ -71,6 +71,10 @@ struct KP {
   CT C_ref;                     // bulk solute 1 + (1-k) U0 of the deviation storage
 };
 
+// Planes of a 2D step tape (compute type, N nodes each): grad phi (x, y),
+// Laplacian of phi, grad psi (x, y), grad U (x, y), mass-flux force (x, y).
+constexpr int TAPE_PLANES = 9;
+
 // Everything a kernel needs, passed by value (well under the 4 KB limit).
 struct DevParams {
   int nx, ny, nz, dim;
@@ -97,6 +101,7 @@ struct DevParams {
   const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
   uint32_t step_ctr;           // step counter, part of the rounding key
+  void* tape;                  // 2D: stencil results written here when set (TAPE_PLANES planes)
   KP<double> kd;
   KP<float> kf;
   // rest equilibria r_i of the deviation storage (per set, per direction)

@@ -28,17 +28,19 @@ inline hipError_t launch_step(const DevParams& P, int fields, int store, const v
 // lam_out in the compute type: FP64 for FP64 storage, FP32 otherwise;
 // parameter gradient accumulated into the FP64 dparams[0..1]) and of the
 // initial state (dparams[1..]).  scratch holds adj_scratch_bytes(N, store).
+// tape: the step's TAPE_PLANES stencil planes written by the forward step
+// (P.tape), or null to redo the stencils.
 size_t adj_scratch_bytes(long long N, int store);
 bool adj2d_supported(int fields);
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
-                             const void* lam_in, void* lam_out, void* scratch, double* dparams,
-                             hipStream_t s, bool& ok);
+                             const void* tape, const void* lam_in, void* lam_out, void* scratch,
+                             double* dparams, hipStream_t s, bool& ok);
 hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s);
 // The FP32-compute part of launch_adj_step2d (stores 1-3).
 hipError_t launch_adj_step2d_lowp(const DevParams& P, int fields, int store, const void* fin, const void* hist,
-                                  const void* lam_in, void* lam_out, void* scratch, double* dparams,
-                                  hipStream_t s, bool& ok);
+                                  const void* tape, const void* lam_in, void* lam_out, void* scratch,
+                                  double* dparams, hipStream_t s, bool& ok);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
 // planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium

@@ -91,17 +91,13 @@ struct FlowNode {
   CT gx, gy, lap, nx, ny, Fsx, Fsy, Dx, Dy, rho, chi, v0x, v0y, sharp;
 };
 
-template <bool NS, bool PHI, class CT, int RX, class JA>
-__device__ __forceinline__ void flow_node(const KP<CT>& K, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
-                                          const JA& s_jx, const JA& s_jy, int ry, int rx, FlowNode<CT>& o) {
-  const CT phi = s_phi[ry][rx];
-  const CT psi = s_psi[ry][rx];
-  if constexpr (PHI) {
-    grad9<CT, RX>(s_phi, ry, rx, o.gx, o.gy);
-    o.lap = lap9<CT, RX>(s_phi, ry, rx);
-  } else {
-    o.gx = o.gy = o.lap = CT(0);
-  }
+// The flow quantities from the node's phi, psi, momentum and the phi stencils.
+template <bool NS, class CT>
+__device__ __forceinline__ void flow_node_from(const KP<CT>& K, CT phi, CT psi, CT jx, CT jy, CT gx, CT gy, CT lap,
+                                               FlowNode<CT>& o) {
+  o.gx = gx;
+  o.gy = gy;
+  o.lap = lap;
   // unit normal, regularised where the gradient vanishes
   const CT inv = rsq(o.gx * o.gx + o.gy * o.gy + K.dn);
   o.nx = o.gx * inv;
@@ -126,11 +122,27 @@ __device__ __forceinline__ void flow_node(const KP<CT>& K, const CT (*s_phi)[RX]
     // buoyancy relative to the liquid: its hydrostatic head is carried by p
     const CT Fbx = CT(0), Fby = -(o.rho - K.rho_l) * K.g;
     const CT s = (CT(1) - o.chi) * rcp(o.rho);
-    o.v0x = s * (s_jx[ry][rx] + CT(0.5) * (o.Fsx + Fbx));
-    o.v0y = s * (s_jy[ry][rx] + CT(0.5) * (o.Fsy + Fby));
+    o.v0x = s * (jx + CT(0.5) * (o.Fsx + Fbx));
+    o.v0y = s * (jy + CT(0.5) * (o.Fsy + Fby));
   } else {
     o.Fsx = o.Fsy = o.v0x = o.v0y = CT(0);
   }
+}
+
+template <bool NS, bool PHI, class CT, int RX, class JA>
+__device__ __forceinline__ void flow_node(const KP<CT>& K, const CT (*s_phi)[RX], const CT (*s_psi)[RX],
+                                          const JA& s_jx, const JA& s_jy, int ry, int rx, FlowNode<CT>& o) {
+  CT gx = CT(0), gy = CT(0), lap = CT(0);
+  if constexpr (PHI) {
+    grad9<CT, RX>(s_phi, ry, rx, gx, gy);
+    lap = lap9<CT, RX>(s_phi, ry, rx);
+  }
+  CT jx = CT(0), jy = CT(0);
+  if constexpr (NS) {
+    jx = s_jx[ry][rx];
+    jy = s_jy[ry][rx];
+  }
+  flow_node_from<NS, CT>(K, s_phi[ry][rx], s_psi[ry][rx], jx, jy, gx, gy, lap, o);
 }
 
 }  // namespace pfl

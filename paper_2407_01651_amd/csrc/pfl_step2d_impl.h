@@ -311,8 +311,8 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   CT vx = CT(0), vy = CT(0), Fx = CT(0), Fy = CT(0), p = CT(0);
   const CT rho = fo.rho;
   const CT grx = K.drho * fo.gx, gry = K.drho * fo.gy;
+  CT Fmx = CT(0), Fmy = CT(0);
   if constexpr (NS) {
-    CT Fmx = CT(0), Fmy = CT(0);
     if constexpr (FLOWX) {
       // (div X)_b = 3 sum_i w_i sum_a c_ia X_ab(x + c_i), X = D (x) v0
       const CT w1 = CT(1.0 / 9), w2 = CT(1.0 / 36);
@@ -341,6 +341,14 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     for (int i = 1; i < QN; ++i) sum += (double)fns[i];
     p = CT(LN::cs2 / (1.0 - LN::w[0]) *
            (sum + 0.5 * ((double)vx * grx + (double)vy * gry) + (double)rho * s0));
+  }
+
+  // the step's stencil results, for an adjoint sweep that does not redo them
+  if (P.tape) {
+    CT* t = (CT*)P.tape;
+    const CT tv[TAPE_PLANES] = {fo.gx, fo.gy, fo.lap, gpx, gpy, gUx, gUy, Fmx, Fmy};
+#pragma unroll
+    for (int k = 0; k < TAPE_PLANES; ++k) t[(long long)k * N + idx] = tv[k];
   }
 
   if (mode == 1) {

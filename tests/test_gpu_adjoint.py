@@ -142,6 +142,55 @@ def test_fp32_step_adjoint_matches_oracle_at_its_state(name, over, n_pre):
     sim.close()
 
 
+TAPE_CASES = [c for c in CASES if c[0] in ("all_walls_20x14", "all_periodic_34x18", "all_first_step_19x13",
+                                           "alloy_theta_18x11", "psi_only_16x16")]
+
+
+@pytest.mark.parametrize("store,tol", [("f64", 1e-12), ("f32", 1e-4)], ids=["f64", "f32"])
+@pytest.mark.parametrize("name,over,n_pre", TAPE_CASES, ids=[c[0] for c in TAPE_CASES])
+def test_taped_step_and_backward(name, over, n_pre, store, tol):
+    """pfl_step_raw_taped writes the same state as pfl_step_raw, and the
+    adjoint that reads the step's stencil results from its tape
+    (pfl_step_backward_taped) agrees with the one that recomputes them
+    (pfl_step_backward_raw): to rounding in FP64 (bar 1e-12), and within the
+    FP32 bar in FP32 (the forward forms its stencils from stored deviations,
+    the recompute from full values)."""
+    import paper_2407_01651_amd as pfl
+    w = _w(over)
+    sim = pfl.Sim(w, store=store, adjoint=True)
+    sim.init_fields()
+    sim.step(n_pre)
+    first = n_pre == 0
+    img, o1, o2 = sim.raw_buffer(), sim.raw_buffer(), sim.raw_buffer()
+    tape = sim.tape_buffer()
+    sim.save_raw(img)
+    sim.step_raw(img, o1, n_pre, first)
+    sim.step_raw_taped(img, o2, n_pre, first, tape)
+    states = []
+    for o in (o1, o2):
+        sim.load_raw(o, n_pre + 1, False)
+        states.append(sim.get_state().cpu())
+    assert torch.equal(states[0], states[1]), name
+    g = torch.Generator().manual_seed(103)
+    lam = torch.randn(states[0].shape, generator=g, dtype=torch.float64).to("cuda", sim.adj_dtype)
+    outs, dps = [], []
+    for taped in (False, True):
+        out = torch.empty_like(lam)
+        dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
+        if taped:
+            sim.step_backward_taped(img, n_pre, first, tape, lam, out, dp)
+        else:
+            sim.step_backward_raw(img, n_pre, first, lam, out, dp)
+        outs.append(out.double().cpu())
+        dps.append(dp.cpu())
+    err = _relerr(outs[1], outs[0])
+    log(f"[adjoint] taped {name} {store} lambda {err:.2e} dparams {dps[1][:2].tolist()} / {dps[0][:2].tolist()}")
+    assert err < tol, (name, store, err)
+    scale = float(dps[0][:2].abs().max()) + 1e-300
+    assert float((dps[1][:2] - dps[0][:2]).abs().max()) <= 10 * tol * scale
+    sim.close()
+
+
 @pytest.mark.parametrize("fields", [workloads.FIELDS_ALL, ("psi", "c")], ids=["all", "alloy"])
 def test_init_adjoint_matches_oracle(fields):
     import paper_2407_01651_amd as pfl
