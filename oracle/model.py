@@ -20,7 +20,9 @@ Paper:
   * the unified LB evolution equation (Sec. 3) and the explicit AAC and heat
     models with their equilibria, sources, auxiliary terms and relaxation
     relations (Appendix B); Lambda = M^-1 S M;
-  * half-way bounce-back walls (Sec. 3).
+  * half-way bounce-back walls (Sec. 3);
+  * symmetry planes treated with the symmetric scheme for the distribution
+    functions (Sec. 3, boundary paragraph).
 Readings (the paper defers the CAC, solute and NS schemes and the
 fluid-solid force to other works):
   * NS: pressure-based incompressible scheme, p recovered from the moving
@@ -47,6 +49,12 @@ fluid-solid force to other works):
     far fields), equal to the paper's expressions where |g|^2 >> delta_n2.
   * F(U) = 1/Le + Mc_inf max(1 + (1-k) U, 0); q clamped to [0, 1].
   * Stencil ghosts at walls mirror scalars and negate D_phi (x) v0.
+  * Symmetry planes lie half-way between nodes, as the walls do.  A
+    population leaving across the plane comes back as its mirror image: the
+    source is the mirror node and the velocity's normal component is
+    reversed (specular reflection).  Stencil ghosts are mirror images:
+    scalars even, and each component of D_phi (x) v0 takes one factor -1
+    per index along the plane's normal.
   * The double-well factor (phi_l - phi)(phi - phi_g) of the sharpening flux
     and the factor (phi_l - phi) of the vacuum flux are clamped at 0 outside
     [phi_g, phi_l].
@@ -131,6 +139,7 @@ class OracleParams:
     delta_n2: float
     seeds: list = field(default_factory=list)
     bubbles: list = field(default_factory=list)
+    symmetric: tuple = (False, False, False)   # non-periodic axes: True = symmetry planes
 
     @classmethod
     def from_workload(cls, w):
@@ -144,7 +153,8 @@ class OracleParams:
                    sigma=w["sigma"], M_phi=w["M_phi"], xi=w["xi"],
                    beta_inter=w["beta_inter"], g=w["g"], delta_n2=w["delta_n2"],
                    seeds=[dict(s) for s in w["seeds"]],
-                   bubbles=[dict(b) for b in w["bubbles"]])
+                   bubbles=[dict(b) for b in w["bubbles"]],
+                   symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]))
 
     # --- derived constants -------------------------------------------------
     @property
@@ -231,8 +241,14 @@ class OracleSim:
         return d2
 
     # ------------------------------------------------------------ stencil access
+    def sym(self, a):
+        return (not self.p.periodic[a]) and bool(self.p.symmetric[a])
+
     def nb(self, f, e, anti=False):
-        """Field value at x + e; walls mirror (anti: and negate) ghost nodes."""
+        """Field value at x + e; walls and symmetry planes mirror ghost nodes.
+        anti: f is the tensor D_phi (x) v0 (leading two axes its components),
+        negated at wall ghosts and given the parity of its components at
+        symmetry-plane ghosts."""
         out = f
         for a, ea in enumerate(e):
             ea = int(ea)
@@ -249,10 +265,19 @@ class OracleSim:
                 idx = torch.where(idx >= n, 2 * n - 1 - idx, idx)
                 out = torch.index_select(out, dim, idx)
                 if anti:
-                    s = torch.where(ghost, -1.0, 1.0).to(DT)
+                    g = torch.where(ghost, -1.0, 1.0).to(DT)
                     shp = [1] * f.dim()
                     shp[dim] = n
-                    out = out * s.view(shp)
+                    g = g.view(shp)
+                    if self.sym(a):
+                        # component (i, j) is odd when exactly one of i, j is a
+                        out = out.clone()
+                        for i in range(self.d):
+                            for j in range(self.d):
+                                if (i == a) != (j == a):
+                                    out[i, j] = out[i, j] * g[0, 0]
+                    else:
+                        out = out * g
         return out
 
     def grad(self, f):
@@ -286,26 +311,60 @@ class OracleSim:
         return out / L.cs2
 
     # ---------------------------------------------------------------- streaming
+    @staticmethod
+    def reflect(L, i, a):
+        """Index of c_i with its component along axis a reversed."""
+        c = [int(v) for v in L.c[i]]
+        c[a] = -c[a]
+        for j in range(L.Q):
+            if [int(v) for v in L.c[j]] == c:
+                return j
+        raise ValueError("velocity set not closed under reflection")
+
     def stream(self, fs, L):
-        """out_i(y) = fs_i(y - c_i); across a wall, out_i(y) = fs_opp(i)(y)."""
+        """out_i(y) = fs_i(y - c_i).  Across a wall, out_i(y) = fs_opp(i)(y);
+        across a symmetry plane on axis a (and no wall), the source is the
+        mirror node and the population the one with c_a reversed."""
         out = torch.empty_like(fs)
         for i in range(L.Q):
-            src = fs[i]
-            mask = torch.zeros(self.grid, dtype=torch.bool)
+            wall = torch.zeros(self.grid, dtype=torch.bool)
+            crossed = []                          # symmetry planes crossed: (axis, mask)
             for a in range(self.d):
                 ca = int(L.c[i, a])
-                if ca == 0:
+                if ca == 0 or self.p.periodic[a]:
                     continue
                 dim = self.d - 1 - a
-                src = torch.roll(src, shifts=ca, dims=dim)
-                if not self.p.periodic[a]:
-                    n = self.grid[dim]
-                    idx = torch.arange(n)
-                    edge = (idx == 0) if ca > 0 else (idx == n - 1)
-                    shp = [1] * self.d
-                    shp[dim] = n
-                    mask = mask | edge.view(shp).expand(self.grid)
-            out[i] = torch.where(mask, fs[L.opp[i]], src)
+                n = self.grid[dim]
+                idx = torch.arange(n)
+                edge = (idx == 0) if ca > 0 else (idx == n - 1)
+                shp = [1] * self.d
+                shp[dim] = n
+                m = edge.view(shp).expand(self.grid)
+                if self.sym(a):
+                    crossed.append((a, m))
+                else:
+                    wall = wall | m
+            # every combination of crossed symmetry planes: reflect c on those
+            # axes, take the source with the other components streamed
+            res = torch.zeros(self.grid, dtype=DT)
+            done = torch.zeros(self.grid, dtype=torch.bool)
+            for k in range(1 << len(crossed)):
+                sel = [crossed[b] for b in range(len(crossed)) if k >> b & 1]
+                m = torch.ones(self.grid, dtype=torch.bool)
+                for b in range(len(crossed)):
+                    m = m & (crossed[b][1] if k >> b & 1 else ~crossed[b][1])
+                j = i
+                for a, _ in sel:
+                    j = self.reflect(L, j, a)
+                src = fs[j]
+                for a in range(self.d):
+                    ca = int(L.c[i, a])
+                    if ca == 0 or any(a == sa for sa, _ in sel):
+                        continue                  # mirrored axis: the source keeps y_a
+                    src = torch.roll(src, shifts=ca, dims=self.d - 1 - a)
+                res = torch.where(m & ~done, src, res)
+                done = done | m
+            out[i] = torch.where(wall, fs[L.opp[i]], res)
         return out
 
     # ------------------------------------------------------------- collision
