@@ -95,7 +95,9 @@ typedef struct {
   uint32_t struct_size;     /* sizeof(pfl_params) */
   int dim;                  /* 2 or 3 */
   int nx, ny, nz;           /* nz = 1 in 2D */
-  int wall[3];              /* per axis: 0 periodic, 1 half-way bounce-back walls */
+  int wall[3];              /* per axis: 0 periodic, 1 half-way bounce-back walls, 2 symmetry
+                               planes (half-way; a population crossing one comes back as its
+                               mirror image, stencil ghosts are mirror images; Sec. 3) */
   uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
   int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
   int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */
@@ -210,7 +212,7 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
  * state_bytes / 8 elements; dparams is a device FP64 vector
  * [eps4, k, Omega, R_1..R_nbub] (accumulated in FP64).  The state is not
  * changed.  Errors: PFL_E_STATE before init or without an adj buffer;
- * PFL_E_UNSUPPORTED in 3D or for field combinations without an adjoint
+ * PFL_E_UNSUPPORTED in 3D, with symmetry planes, or for field combinations without an adjoint
  * (built: all five sets, psi + C, psi + C + theta, NS + phi, psi alone). */
 int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dparams);
 

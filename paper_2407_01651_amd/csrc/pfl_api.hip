@@ -49,7 +49,7 @@ int validate(const pfl_params* p) {
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31))
     return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
   for (int a = 0; a < 3; ++a)
-    if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PFL_E_INVALID_ARG, "wall flags must be 0 or 1");
+    if (p->wall[a] < 0 || p->wall[a] > 2) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0, 1 or 2");
   const uint32_t f = p->fields;
   if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
   if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");
@@ -183,7 +183,10 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   DevParams& d = c->d;
   std::memset(&d, 0, sizeof(d));
   d.nx = p->nx; d.ny = p->ny; d.nz = p->nz; d.dim = p->dim;
-  for (int a = 0; a < 3; ++a) d.wall[a] = p->wall[a];
+  for (int a = 0; a < 3; ++a) {
+    d.wall[a] = p->wall[a] != 0;
+    d.sym[a] = p->wall[a] == 2;
+  }
   d.N = L.N;
   d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;
   d.q_ns = L.q_ns; d.q_phi = L.q_phi; d.q_sc = L.q_sc;
@@ -477,6 +480,8 @@ static int adj_check(pfl_ctx* c) {
   if (!c->b.adj) return fail(PFL_E_STATE, "no adjoint scratch buffer (pfl_buffers.adj)");
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
+  for (int a = 0; a < 3; ++a)
+    if (c->p.wall[a] == 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for periodic axes and walls");
   return PFL_OK;
 }
 

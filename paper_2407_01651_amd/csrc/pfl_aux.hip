@@ -9,21 +9,26 @@ namespace {
 constexpr int BT = 256;
 
 // Node-form slot of population i at node (x, y, z) in pull storage: the
-// value is held at its source node x - c_i, or, when that source lies
-// beyond a wall, in the node's own opposite slot.
+// value is held at its source node x - c_i; when that source lies beyond a
+// wall, in the node's own opposite slot; beyond a symmetry plane, at the
+// mirror of the source as the population with that component reversed.
 template <int Q>
 __device__ __forceinline__ long long slot(const DevParams& P, int x, int y, int z, int i) {
   using L = Lat<Q>;
   int s[3] = {x - L::c[i][0], y - L::c[i][1], z - L::c[i][2]};
   const int n[3] = {P.nx, P.ny, P.nz};
-  bool bounce = false;
+  bool bounce = false, fl[3] = {false, false, false};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (s[a] < 0) { if (P.wall[a]) bounce = true; else s[a] += n[a]; }
-    else if (s[a] >= n[a]) { if (P.wall[a]) bounce = true; else s[a] -= n[a]; }
+    if (s[a] < 0 || s[a] >= n[a]) {
+      if (!P.wall[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+      else if (P.sym[a]) { s[a] = s[a] < 0 ? -1 - s[a] : 2 * n[a] - 1 - s[a]; fl[a] = true; }
+      else bounce = true;
+    }
   }
   if (bounce) return (long long)L::opp[i] * P.N + ((long long)z * P.ny + y) * P.nx + x;
-  return (long long)i * P.N + ((long long)s[2] * P.ny + s[1]) * P.nx + s[0];
+  const int j = lat_reflected<Q>(i, fl[0], fl[1], fl[2]);
+  return (long long)j * P.N + ((long long)s[2] * P.ny + s[1]) * P.nx + s[0];
 }
 
 // plane index (within a set) of a slot
@@ -35,8 +40,9 @@ __device__ void scatter_set(const DevParams& P, typename Store<ST>::raw* base, c
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const long long sl = slot<Q>(P, x, y, z, i);
-    // population i of this node lands in plane i, or opp(i) across a wall:
-    // either way it is a population of direction plane_of(sl) at its slot
+    // population i of this node lands in plane i, opp(i) across a wall or
+    // its reflection across a symmetry plane: a population of direction
+    // plane_of(sl) at its slot
     Store<ST>::st(base + sl, f[i] - ref[i]);
   }
 }

@@ -23,6 +23,8 @@ template <> struct Lat<5> {
   static constexpr int Q = 5, D = 2;
   static constexpr int c[5][3] = {{0,0,0},{1,0,0},{0,1,0},{-1,0,0},{0,-1,0}};
   static constexpr int opp[5] = {0, 3, 4, 1, 2};
+  // refl[a][i]: c_i with its component on axis a reversed (specular reflection)
+  static constexpr int refl[3][5] = {{0,3,2,1,4}, {0,1,4,3,2}, {0,1,2,3,4}};
   static constexpr double w[5] = {1.0/3, 1.0/6, 1.0/6, 1.0/6, 1.0/6};
   static constexpr double cs2 = 1.0/3;
   static constexpr double flux_norm = 2.0;   // sum_i c_ia^2
@@ -33,6 +35,8 @@ template <> struct Lat<9> {
   static constexpr int c[9][3] = {{0,0,0},{1,0,0},{0,1,0},{-1,0,0},{0,-1,0},
                                   {1,1,0},{-1,1,0},{-1,-1,0},{1,-1,0}};
   static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  // refl[a][i]: c_i with its component on axis a reversed (specular reflection)
+  static constexpr int refl[3][9] = {{0,3,2,1,4,6,5,8,7}, {0,1,4,3,2,8,7,6,5}, {0,1,2,3,4,5,6,7,8}};
   static constexpr double w[9] = {4.0/9, 1.0/9, 1.0/9, 1.0/9, 1.0/9,
                                   1.0/36, 1.0/36, 1.0/36, 1.0/36};
   static constexpr double cs2 = 1.0/3;
@@ -43,6 +47,8 @@ template <> struct Lat<7> {
   static constexpr int Q = 7, D = 3;
   static constexpr int c[7][3] = {{0,0,0},{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1}};
   static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
+  // refl[a][i]: c_i with its component on axis a reversed (specular reflection)
+  static constexpr int refl[3][7] = {{0,2,1,3,4,5,6}, {0,1,2,4,3,5,6}, {0,1,2,3,4,6,5}};
   static constexpr double w[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
   static constexpr double cs2 = 0.25;
   static constexpr double flux_norm = 2.0;
@@ -55,12 +61,42 @@ template <> struct Lat<19> {
                                    {1,0,1},{-1,0,-1},{1,0,-1},{-1,0,1},
                                    {0,1,1},{0,-1,-1},{0,1,-1},{0,-1,1}};
   static constexpr int opp[19] = {0,2,1,4,3,6,5,8,7,10,9,12,11,14,13,16,15,18,17};
+  // refl[a][i]: c_i with its component on axis a reversed (specular reflection)
+  static constexpr int refl[3][19] = {{0,2,1,3,4,5,6,10,9,8,7,14,13,12,11,15,16,17,18},
+                                    {0,1,2,4,3,5,6,9,10,7,8,11,12,13,14,18,17,16,15},
+                                    {0,1,2,3,4,6,5,7,8,9,10,13,14,11,12,17,18,15,16}};
   static constexpr double w[19] = {1.0/3, 1.0/18, 1.0/18, 1.0/18, 1.0/18, 1.0/18, 1.0/18,
                                    1.0/36, 1.0/36, 1.0/36, 1.0/36, 1.0/36, 1.0/36,
                                    1.0/36, 1.0/36, 1.0/36, 1.0/36, 1.0/36, 1.0/36};
   static constexpr double cs2 = 1.0/3;
   static constexpr double flux_norm = 10.0;
 };
+
+// The reflection tables reverse exactly one component of each velocity.
+template <int Q>
+constexpr bool refl_consistent() {
+  using L = Lat<Q>;
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < Q; ++i)
+      for (int b = 0; b < 3; ++b)
+        if (L::c[L::refl[a][i]][b] != (a == b ? -L::c[i][b] : L::c[i][b])) return false;
+  return true;
+}
+static_assert(refl_consistent<5>() && refl_consistent<9>() && refl_consistent<7>() && refl_consistent<19>(),
+              "reflection tables");
+
+// Index of c_i with the components on the flagged axes reversed.  i is a
+// compile-time index in the unrolled callers, so every table entry below is
+// a constant and only the selects remain.
+template <int Q>
+__device__ __forceinline__ int lat_reflected(int i, bool fx, bool fy, bool fz) {
+  using L = Lat<Q>;
+  const int a1 = L::refl[0][i];
+  const int b0 = L::refl[1][i], b1 = L::refl[1][a1];
+  const int jxy = fy ? (fx ? b1 : b0) : (fx ? a1 : i);
+  const int jz = fy ? (fx ? L::refl[2][b1] : L::refl[2][b0]) : (fx ? L::refl[2][a1] : L::refl[2][i]);
+  return fz ? jz : jxy;
+}
 
 // ------------------------------------------------------------- parameters
 // Constants of the step in the compute precision, reciprocals precomputed.
@@ -78,7 +114,8 @@ constexpr int TAPE_PLANES = 9;
 // Everything a kernel needs, passed by value (well under the 4 KB limit).
 struct DevParams {
   int nx, ny, nz, dim;
-  int wall[3];
+  int wall[3];                 // non-periodic axis: a wall or a symmetry plane
+  int sym[3];                  // the axis's boundaries are symmetry planes
   long long N;                 // nodes
   // population plane offsets (-1 = set inactive)
   int o_ns, o_phi, o_psi, o_c, o_th;

@@ -10,7 +10,9 @@ namespace pfl {
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 
 // Pull the pre-collision population deviations of one set at node (x, y), general
-// addressing: periodic wrap or half-way bounce-back on each axis.
+// addressing: periodic wrap, half-way bounce-back at a wall (the node's own
+// opposite population), or specular reflection at a symmetry plane (the
+// mirror node's population with the normal component reversed) on each axis.
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
                                              const DevParams& P, int x, int y, CT f[Q]) {
@@ -19,13 +21,19 @@ __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __re
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int sx = x - L::c[i][0], sy = y - L::c[i][1];
-    bool bounce = false;
-    if (sx < 0) { if (P.wall[0]) bounce = true; else sx += P.nx; }
-    else if (sx >= P.nx) { if (P.wall[0]) bounce = true; else sx -= P.nx; }
-    if (sy < 0) { if (P.wall[1]) bounce = true; else sy += P.ny; }
-    else if (sy >= P.ny) { if (P.wall[1]) bounce = true; else sy -= P.ny; }
+    bool bounce = false, fx = false, fy = false;
+    if (sx < 0 || sx >= P.nx) {
+      if (!P.wall[0]) sx = sx < 0 ? sx + P.nx : sx - P.nx;
+      else if (P.sym[0]) { sx = sx < 0 ? -1 - sx : 2 * P.nx - 1 - sx; fx = true; }
+      else bounce = true;
+    }
+    if (sy < 0 || sy >= P.ny) {
+      if (!P.wall[1]) sy = sy < 0 ? sy + P.ny : sy - P.ny;
+      else if (P.sym[1]) { sy = sy < 0 ? -1 - sy : 2 * P.ny - 1 - sy; fy = true; }
+      else bounce = true;
+    }
     const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
-    const int plane = bounce ? L::opp[i] : i;
+    const int plane = bounce ? L::opp[i] : lat_reflected<Q>(i, fx, fy, false);
     f[i] = Store<ST>::template ld<CT>(base + plane * N + idx);
   }
 }

@@ -225,24 +225,26 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const int gx0 = bx0 + tx, gy0 = by0 + ty;
       const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
       if (inner && gx0 < P.nx && gy0 < P.ny) continue;
-      // ghosts across a wall take minus the value at their mirror node
+      // ghosts across a wall take minus the value at their mirror node;
+      // across a symmetry plane the mirror image: the off-diagonal
+      // components (one index along the normal) change sign
       int mx = rx, my = ry;
-      CT sgn = CT(1);
+      CT sgn = CT(1), sod = CT(1);
       bool skip = false;
       if (P.wall[0] && (gx0 < 0 || gx0 >= P.nx)) {
         if (gx0 == -1) mx = rx + 1; else if (gx0 == P.nx) mx = rx - 1; else skip = true;
-        sgn = -sgn;
+        if (P.sym[0]) sod = -sod; else sgn = -sgn;
       }
       if (P.wall[1] && (gy0 < 0 || gy0 >= P.ny)) {
         if (gy0 == -1) my = ry + 1; else if (gy0 == P.ny) my = ry - 1; else skip = true;
-        sgn = -sgn;
+        if (P.sym[1]) sod = -sod; else sgn = -sgn;
       }
       CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
       if (!skip) {
         FlowNode<CT> h;
         flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, my, mx, h);
-        X0 = sgn * h.Dx * h.v0x; X1 = sgn * h.Dx * h.v0y;
-        X2 = sgn * h.Dy * h.v0x; X3 = sgn * h.Dy * h.v0y;
+        X0 = sgn * h.Dx * h.v0x; X1 = sgn * sod * h.Dx * h.v0y;
+        X2 = sgn * sod * h.Dy * h.v0x; X3 = sgn * h.Dy * h.v0y;
       }
       s_X[0][ry][rx] = X0; s_X[1][ry][rx] = X1; s_X[2][ry][rx] = X2; s_X[3][ry][rx] = X3;
     }

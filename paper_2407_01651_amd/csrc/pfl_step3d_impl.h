@@ -41,16 +41,17 @@ __device__ __forceinline__ long long nidx3(const DevParams& P, int x, int y, int
 }
 
 // Pull the stored values of one set at node (x, y, z), general addressing:
-// periodic wrap or half-way bounce-back on each axis, from per-axis source
-// offsets computed once per node.
+// periodic wrap, half-way bounce-back at a wall or specular reflection at a
+// symmetry plane on each axis, from per-axis source offsets computed once
+// per node.
 template <int Q, class ST, class CT>
 __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __restrict__ base,
                                               const DevParams& P, int x, int y, int z, CT f[Q]) {
   using L = Lat<Q>;
   AxisSrc ax, ay, az;
-  axis_src(x, P.nx, P.wall[0], 1, ax);
-  axis_src(y, P.ny, P.wall[1], P.nx, ay);
-  axis_src(z, P.nz, P.wall[2], P.nx * P.ny, az);
+  axis_src(x, P.nx, P.wall[0], P.sym[0], 1, ax);
+  axis_src(y, P.ny, P.wall[1], P.sym[1], P.nx, ay);
+  axis_src(z, P.nz, P.wall[2], P.sym[2], P.nx * P.ny, az);
   const int own = (z * P.ny + y) * P.nx + x;     // the node count is below 2^31
   if (P.fast) {
     constexpr uint32_t S = sizeof(typename Store<ST>::raw);
@@ -59,8 +60,9 @@ __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __r
     for (int i = 0; i < Q; ++i) {
       const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
       const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
+      const int j = lat_reflected<Q>(i, ax.flip[cx], ay.flip[cy], az.flip[cz]);
       const uint32_t e = b ? (uint32_t)L::opp[i] * N + (uint32_t)own
-                           : (uint32_t)i * N + (uint32_t)(own + ax.off[cx] + ay.off[cy] + az.off[cz]);
+                           : (uint32_t)j * N + (uint32_t)(own + ax.off[cx] + ay.off[cy] + az.off[cz]);
       f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, e * S));
     }
   } else {
@@ -69,8 +71,9 @@ __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __r
     for (int i = 0; i < Q; ++i) {
       const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
       const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
+      const int j = lat_reflected<Q>(i, ax.flip[cx], ay.flip[cy], az.flip[cz]);
       const long long e = b ? (long long)L::opp[i] * N + own
-                            : (long long)i * N + (own + ax.off[cx] + ay.off[cy] + az.off[cz]);
+                            : (long long)j * N + (own + ax.off[cx] + ay.off[cy] + az.off[cz]);
       f[i] = Store<ST>::template ld<CT>(base + e);
     }
   }
@@ -385,16 +388,18 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY && tz >= 0 && tz < TZ;
       if (inner && g[0] < P.nx && g[1] < P.ny && g[2] < P.nz) continue;
       // ghosts across a wall: D (x) v0 is odd across the wall; D takes minus
-      // the value at the mirror node once per wall crossed, v0 the value
+      // the value at the mirror node once per wall crossed, v0 the value.
+      // Across a symmetry plane the ghost is the mirror image: the normal
+      // components of D and v0 change sign.
       int m[3] = {rx, ry, rz};
       const int n[3] = {P.nx, P.ny, P.nz};
-      CT sgn = CT(1);
+      CT sgn = CT(1), sc[3] = {CT(1), CT(1), CT(1)};
       bool skip = false;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         if (P.wall[a] && (g[a] < 0 || g[a] >= n[a])) {
           if (g[a] == -1) m[a] += 1; else if (g[a] == n[a]) m[a] -= 1; else skip = true;
-          sgn = -sgn;
+          if (P.sym[a]) sc[a] = -sc[a]; else sgn = -sgn;
         }
       }
       CT D[3] = {CT(0), CT(0), CT(0)}, v0[3] = {CT(0), CT(0), CT(0)};
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
         FlowNode3<CT> hn;
         flow_node3<NS, PHI, R, CT>(K, s_phi, s_psi, s_j, m[2], m[1], m[0], hn);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) { D[a] = sgn * hn.D[a]; v0[a] = hn.v0[a]; }
+        for (int a = 0; a < 3; ++a) { D[a] = sgn * sc[a] * hn.D[a]; v0[a] = sc[a] * hn.v0[a]; }
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) { s_D[a * B1::N + k] = D[a]; s_v0[a * B1::N + k] = v0[a]; }

@@ -89,20 +89,26 @@ __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>
 }
 
 // Source offsets along one axis for a node at coordinate x: entry c + 1
-// holds the element offset of x - c (periodic wrap) and whether x - c lies
+// holds the element offset of x - c (periodic wrap), whether x - c lies
 // beyond a wall (then the population bounces back into the node's own
-// opposite slot).
+// opposite slot), and whether it lies beyond a symmetry plane (then the
+// source is the mirror node, x itself, and the population the one with this
+// component reversed).
 struct AxisSrc {
   int off[3];
   bool wall[3];
+  bool flip[3];
 };
-__device__ __forceinline__ void axis_src(int x, int n, int wall, int stride, AxisSrc& a) {
+__device__ __forceinline__ void axis_src(int x, int n, int wall, int sym, int stride, AxisSrc& a) {
   const bool hi = x + 1 >= n, lo = x - 1 < 0;
   a.off[1] = 0;
   a.wall[1] = false;
-  a.wall[0] = wall && hi;
+  a.flip[1] = false;
+  a.wall[0] = wall && !sym && hi;
+  a.flip[0] = wall && sym && hi;
   a.off[0] = hi ? (wall ? 0 : (1 - n) * stride) : stride;
-  a.wall[2] = wall && lo;
+  a.wall[2] = wall && !sym && lo;
+  a.flip[2] = wall && sym && lo;
   a.off[2] = lo ? (wall ? 0 : (n - 1) * stride) : -stride;
 }
 

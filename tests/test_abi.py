@@ -93,3 +93,18 @@ def test_bad_rounding_mode_is_rejected():
     s = pfl.Sizes()
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
     assert "rounding" in pfl._lib.pfl_last_error().decode()
+
+
+def test_boundary_flags():
+    """wall[a]: 0 periodic, 1 wall, 2 symmetry plane; anything else is rejected."""
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("coupled2d_128")
+    w["symmetric"] = (True, True, False)
+    w["periodic"] = (False, False, True)
+    p = pfl.make_params(w, "f64", "nearest")
+    assert list(p.wall) == [2, 2, 0]
+    s = pfl.Sizes()
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.wall[0] = 3
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    assert "boundary" in pfl._lib.pfl_last_error().decode()

@@ -39,6 +39,20 @@ CASES = [
     ("phi_only_18x14", dict(nx=18, ny=14, seed=11, fields=("phi",)), 30),
     ("ns_psi_theta_22x12", dict(nx=22, ny=12, seed=12, fields=("ns", "psi", "theta")), 30),
     ("psi_theta_21x13", dict(nx=21, ny=13, seed=13, fields=("psi", "theta")), 30),
+    # symmetry planes (Sec. 3): specular reflection, mirror ghosts
+    ("all_xsym_ywalls_30x20", dict(nx=30, ny=20, seed=15, periodic=(False, False, True),
+                                   symmetric=(True, False, False), g=2e-4, rho_g=0.01), 30),
+    ("all_xysym_26x22", dict(nx=26, ny=22, seed=16, periodic=(False, False, True),
+                             symmetric=(True, True, False)), 30),
+    ("all_xwalls_ysym_23x19", dict(nx=23, ny=19, seed=17, periodic=(False, False, True),
+                                   symmetric=(False, True, False)), 30),
+    ("all_phiq9_xysym_24x18", dict(nx=24, ny=18, seed=18, phi_q=9, periodic=(False, False, True),
+                                   symmetric=(True, True, False)), 30),
+    ("all_xsym_fasttiles_72x30", dict(nx=72, ny=30, seed=19, periodic=(False, True, True),
+                                      symmetric=(True, False, False)), 20),
+    ("alloy_xysym_33x27", dict(nx=33, ny=27, seed=20, fields=("psi", "c"), Le=math.inf, U0=-0.55,
+                               theta0=0.0, tau0=50.0, periodic=(False, False, True),
+                               symmetric=(True, True, False)), 40),
 ]
 
 

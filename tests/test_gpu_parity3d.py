@@ -33,6 +33,13 @@ CASES = [
                                    periodic=(True, True, False)), 30),
     ("psi_only_14x14x6", dict(nx=14, ny=14, nz=6, seed=28, fields=("psi",), Le=math.inf, theta0=-0.3), 25),
     ("phi_only_15x11x5", dict(nx=15, ny=11, nz=5, seed=29, fields=("phi",)), 25),
+    # symmetry planes (Sec. 3): specular reflection, mirror ghosts
+    ("all_xsym_16x12x8", dict(nx=16, ny=12, nz=8, seed=30, periodic=(False, False, True),
+                              symmetric=(True, False, False), g=2e-4, rho_g=0.01), 20),
+    ("all_xzsym_ywalls_14x12x10", dict(nx=14, ny=12, nz=10, seed=31, periodic=(False, False, False),
+                                       symmetric=(True, False, True)), 20),
+    ("all_xyzsym_40x14x12", dict(nx=40, ny=14, nz=12, seed=32, periodic=(False, False, False),
+                                 symmetric=(True, True, True)), 15),
 ]
 
 
