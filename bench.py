@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--store", default="f64")
     ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
     ap.add_argument("--extra", default="coupled2d_2048:f16,coupled2d_2048:bf16,coupled2d_2048:f32,"
-                                       "coupled2d_2048_q9:f16",
+                                       "coupled2d_2048_q9:f16,coupled3d_256:f16",
                     help="comma list of config:storage pairs timed beside (variants)")
     ap.add_argument("--rounding", default="stochastic", choices=("stochastic", "nearest"),
                     help="rounding into 16-bit storage")
@@ -132,7 +132,7 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     import torch
     import workloads
     import paper_2407_01651_amd as pfl
-    from paper_2407_01651_amd.adjoint import CheckpointedRun, params_of, workload_at
+    from paper_2407_01651_amd.adjoint import CheckpointedRun, ResidentRun, params_of, workload_at
     w = workloads.get(name)
     steps = w["steps"]
     p = params_of(w)
@@ -172,11 +172,33 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     t_ck, t_bwd = a.elapsed_time(b), b.elapsed_time(c)
     grad = dp.cpu().tolist()
     run.close()
+    del run
+    torch.cuda.empty_cache()
+    # every state and tape resident in HBM (no recompute), same timing protocol
+    res = ResidentRun(w, store=store, steps=steps)
+    m = res.forward(steps)
+    res.backward(res.lam_from_macros(2 * (m["phi"] - phi_t), 2 * (m["psi"] - psi_t)))
+    torch.cuda.synchronize()
+    a, b, c = ev(), ev(), ev()
+    a.record(stream)
+    m = res.forward(steps)
+    b.record(stream)
+    res.backward(res.lam_from_macros(2 * (m["phi"] - phi_t), 2 * (m["psi"] - psi_t)))
+    c.record(stream)
+    torch.cuda.synchronize()
+    r_fwd, r_bwd = a.elapsed_time(b), b.elapsed_time(c)
+    r_gb = (len(res.imgs) * res.imgs[0].numel() + len(res.tapes) * res.tapes[0].numel()) / 1e9
+    res.close()
+    del res
+    torch.cuda.empty_cache()
     return {"workload": name, "storage": store, "steps": steps, "checkpoint_every": K,
             "reverse_compute": "f32 reverse, adjoint state and scratch (the forward's compute type), f64 parameter sums",
             "forward_ms": round(t_fwd, 3),
             "forward_with_checkpoints_ms": round(t_ck, 3), "backward_ms": round(t_bwd, 3),
             "ratio": round((t_ck + t_bwd) / t_fwd, 3),
+            "resident": {"note": "every state and tape kept in HBM, no recompute",
+                         "hbm_gb": round(r_gb, 1), "forward_taped_ms": round(r_fwd, 3),
+                         "backward_ms": round(r_bwd, 3), "ratio": round((r_fwd + r_bwd) / t_fwd, 3)},
             "params": ["eps4", "k", "Omega"] + [f"R{i + 1}" for i in range(len(p) - 3)],
             "grad": [round(v, 8) for v in grad]}
 

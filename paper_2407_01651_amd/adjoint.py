@@ -195,6 +195,56 @@ class CheckpointedRun:
         self.sim.close()
 
 
+class ResidentRun:
+    """Forward and adjoint sweep with every state and tape kept in HBM (no
+    recompute): the forward steps image to image with pfl_step_raw_taped,
+    the reverse reads image and tape of each step.  Memory: steps + 1 raw
+    images and steps tapes (96 GB for the 512^2 FP32 workload's 2000 steps,
+    within one GPU's 288 GB)."""
+
+    def __init__(self, w, store="f64", device="cuda:0", steps=0):
+        self.w = w
+        self.sim = Sim(w, store=store, device=device, adjoint=True)
+        self.imgs, self.tapes = [], []
+        self.steps = 0
+        self._reserve(int(steps))
+
+    def _reserve(self, steps):
+        sim = self.sim
+        while len(self.imgs) < steps + 1:
+            self.imgs.append(sim.raw_buffer())
+        while len(self.tapes) < steps:
+            self.tapes.append(sim.tape_buffer())
+
+    lam_from_macros = CheckpointedRun.lam_from_macros
+
+    def forward(self, steps):
+        sim = self.sim
+        self.steps = int(steps)
+        self._reserve(self.steps)
+        sim.init_fields()
+        sim.save_raw(self.imgs[0])
+        for j in range(self.steps):
+            sim.step_raw_taped(self.imgs[j], self.imgs[j + 1], j, j == 0, self.tapes[j])
+        sim.load_raw(self.imgs[self.steps], self.steps, self.steps == 0)
+        return sim.macros()
+
+    def backward(self, lam):
+        sim = self.sim
+        dparams = torch.zeros(3 + len(self.w["bubbles"]), dtype=torch.float64, device=sim.device)
+        lam = lam.to(sim.adj_dtype).contiguous().clone()
+        other = torch.empty_like(lam)
+        for j in range(self.steps - 1, -1, -1):
+            sim.step_backward_taped(self.imgs[j], j, j == 0, self.tapes[j], lam, other, dparams)
+            lam, other = other, lam
+        sim.init_backward(lam, dparams)
+        return dparams
+
+    def close(self):
+        self.imgs, self.tapes = [], []
+        self.sim.close()
+
+
 class _Run(torch.autograd.Function):
     @staticmethod
     def forward(ctx, p, w, steps, K, store):
