@@ -139,7 +139,9 @@ class OracleParams:
     delta_n2: float
     seeds: list = field(default_factory=list)
     bubbles: list = field(default_factory=list)
-    symmetric: tuple = (False, False, False)   # non-periodic axes: True = symmetry planes
+    # non-periodic axes: True = symmetry planes on both sides, "lo" / "hi" = on
+    # the low (coordinate -1/2) or high (n - 1/2) side only, a wall on the other
+    symmetric: tuple = (False, False, False)
 
     @classmethod
     def from_workload(cls, w):
@@ -241,8 +243,16 @@ class OracleSim:
         return d2
 
     # ------------------------------------------------------------ stencil access
-    def sym(self, a):
-        return (not self.p.periodic[a]) and bool(self.p.symmetric[a])
+    def sym(self, a, lo):
+        """Whether the low (lo) or high boundary of axis a is a symmetry plane."""
+        if self.p.periodic[a]:
+            return False
+        v = self.p.symmetric[a]
+        if v == "lo":
+            return lo
+        if v == "hi":
+            return not lo
+        return bool(v)
 
     def nb(self, f, e, anti=False):
         """Field value at x + e; walls and symmetry planes mirror ghost nodes.
@@ -265,19 +275,20 @@ class OracleSim:
                 idx = torch.where(idx >= n, 2 * n - 1 - idx, idx)
                 out = torch.index_select(out, dim, idx)
                 if anti:
-                    g = torch.where(ghost, -1.0, 1.0).to(DT)
-                    shp = [1] * f.dim()
-                    shp[dim] = n
-                    g = g.view(shp)
-                    if self.sym(a):
-                        # component (i, j) is odd when exactly one of i, j is a
-                        out = out.clone()
-                        for i in range(self.d):
-                            for j in range(self.d):
-                                if (i == a) != (j == a):
-                                    out[i, j] = out[i, j] * g[0, 0]
-                    else:
-                        out = out * g
+                    # walls: every component odd; symmetry planes: component
+                    # (i, j) odd when exactly one of i, j is a
+                    raw = torch.arange(n) + ea
+                    lo_g, hi_g = raw < 0, raw >= n
+                    sym_g = (lo_g & self.sym(a, True)) | (hi_g & self.sym(a, False))
+                    wall_g = ghost & ~sym_g
+                    shp = [n if k == dim - 2 else 1 for k in range(f.dim() - 2)]
+                    s_all = torch.where(wall_g, -1.0, 1.0).to(DT).view(shp)
+                    s_off = torch.where(sym_g, -1.0, 1.0).to(DT).view(shp)
+                    out = out.clone()
+                    for i in range(self.d):
+                        for j in range(self.d):
+                            sg = s_all * s_off if (i == a) != (j == a) else s_all
+                            out[i, j] = out[i, j] * sg
         return out
 
     def grad(self, f):
@@ -340,7 +351,7 @@ class OracleSim:
                 shp = [1] * self.d
                 shp[dim] = n
                 m = edge.view(shp).expand(self.grid)
-                if self.sym(a):
+                if self.sym(a, ca > 0):
                     crossed.append((a, m))
                 else:
                     wall = wall | m
