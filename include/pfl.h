@@ -96,8 +96,11 @@ typedef struct {
   int dim;                  /* 2 or 3 */
   int nx, ny, nz;           /* nz = 1 in 2D */
   int wall[3];              /* per axis: 0 periodic, 1 half-way bounce-back walls, 2 symmetry
-                               planes (half-way; a population crossing one comes back as its
-                               mirror image, stencil ghosts are mirror images; Sec. 3) */
+                               planes on both sides, 3 a symmetry plane on the low side (at
+                               coordinate -1/2) and a wall on the high side, 4 the reverse.
+                               Symmetry planes lie half-way; a population crossing one comes
+                               back as its mirror image, stencil ghosts are mirror images
+                               (Sec. 3). */
   uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
   int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
   int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */

@@ -118,8 +118,10 @@ def make_params(w, store=None, rounding=None):
     p.dim = w["dim"]
     p.nx, p.ny, p.nz = w["nx"], w["ny"], (w["nz"] if w["dim"] == 3 else 1)
     for a in range(3):
+        # symmetric[a]: True (both sides), "lo", "hi" or False
         sym = w.get("symmetric", (False, False, False))
-        p.wall[a] = 0 if (a >= w["dim"] or w["periodic"][a]) else (2 if sym[a] else 1)
+        code = {"lo": 3, "hi": 4}.get(sym[a], 2) if sym[a] else 1
+        p.wall[a] = 0 if (a >= w["dim"] or w["periodic"][a]) else code
     bits = 0
     for f in w["fields"]:
         bits |= FIELD_BITS[f]

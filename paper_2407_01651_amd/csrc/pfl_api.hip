@@ -49,7 +49,7 @@ int validate(const pfl_params* p) {
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31))
     return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
   for (int a = 0; a < 3; ++a)
-    if (p->wall[a] < 0 || p->wall[a] > 2) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0, 1 or 2");
+    if (p->wall[a] < 0 || p->wall[a] > 4) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 4");
   const uint32_t f = p->fields;
   if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
   if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");
@@ -185,7 +185,8 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   d.nx = p->nx; d.ny = p->ny; d.nz = p->nz; d.dim = p->dim;
   for (int a = 0; a < 3; ++a) {
     d.wall[a] = p->wall[a] != 0;
-    d.sym[a] = p->wall[a] == 2;
+    d.sym_lo[a] = p->wall[a] == 2 || p->wall[a] == 3;
+    d.sym_hi[a] = p->wall[a] == 2 || p->wall[a] == 4;
   }
   d.N = L.N;
   d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;
@@ -481,7 +482,7 @@ static int adj_check(pfl_ctx* c) {
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   for (int a = 0; a < 3; ++a)
-    if (c->p.wall[a] == 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for periodic axes and walls");
+    if (c->p.wall[a] >= 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for periodic axes and walls");
   return PFL_OK;
 }
 

@@ -22,7 +22,7 @@ __device__ __forceinline__ long long slot(const DevParams& P, int x, int y, int 
   for (int a = 0; a < 3; ++a) {
     if (s[a] < 0 || s[a] >= n[a]) {
       if (!P.wall[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-      else if (P.sym[a]) { s[a] = s[a] < 0 ? -1 - s[a] : 2 * n[a] - 1 - s[a]; fl[a] = true; }
+      else if (s[a] < 0 ? P.sym_lo[a] : P.sym_hi[a]) { s[a] = s[a] < 0 ? -1 - s[a] : 2 * n[a] - 1 - s[a]; fl[a] = true; }
       else bounce = true;
     }
   }

@@ -115,7 +115,7 @@ constexpr int TAPE_PLANES = 9;
 struct DevParams {
   int nx, ny, nz, dim;
   int wall[3];                 // non-periodic axis: a wall or a symmetry plane
-  int sym[3];                  // the axis's boundaries are symmetry planes
+  int sym_lo[3], sym_hi[3];    // the axis's low / high boundary is a symmetry plane
   long long N;                 // nodes
   // population plane offsets (-1 = set inactive)
   int o_ns, o_phi, o_psi, o_c, o_th;

@@ -24,12 +24,12 @@ __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __re
     bool bounce = false, fx = false, fy = false;
     if (sx < 0 || sx >= P.nx) {
       if (!P.wall[0]) sx = sx < 0 ? sx + P.nx : sx - P.nx;
-      else if (P.sym[0]) { sx = sx < 0 ? -1 - sx : 2 * P.nx - 1 - sx; fx = true; }
+      else if (sx < 0 ? P.sym_lo[0] : P.sym_hi[0]) { sx = sx < 0 ? -1 - sx : 2 * P.nx - 1 - sx; fx = true; }
       else bounce = true;
     }
     if (sy < 0 || sy >= P.ny) {
       if (!P.wall[1]) sy = sy < 0 ? sy + P.ny : sy - P.ny;
-      else if (P.sym[1]) { sy = sy < 0 ? -1 - sy : 2 * P.ny - 1 - sy; fy = true; }
+      else if (sy < 0 ? P.sym_lo[1] : P.sym_hi[1]) { sy = sy < 0 ? -1 - sy : 2 * P.ny - 1 - sy; fy = true; }
       else bounce = true;
     }
     const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;

@@ -233,11 +233,11 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       bool skip = false;
       if (P.wall[0] && (gx0 < 0 || gx0 >= P.nx)) {
         if (gx0 == -1) mx = rx + 1; else if (gx0 == P.nx) mx = rx - 1; else skip = true;
-        if (P.sym[0]) sod = -sod; else sgn = -sgn;
+        if (gx0 < 0 ? P.sym_lo[0] : P.sym_hi[0]) sod = -sod; else sgn = -sgn;
       }
       if (P.wall[1] && (gy0 < 0 || gy0 >= P.ny)) {
         if (gy0 == -1) my = ry + 1; else if (gy0 == P.ny) my = ry - 1; else skip = true;
-        if (P.sym[1]) sod = -sod; else sgn = -sgn;
+        if (gy0 < 0 ? P.sym_lo[1] : P.sym_hi[1]) sod = -sod; else sgn = -sgn;
       }
       CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
       if (!skip) {

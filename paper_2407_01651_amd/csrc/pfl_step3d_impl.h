@@ -49,9 +49,9 @@ __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __r
                                               const DevParams& P, int x, int y, int z, CT f[Q]) {
   using L = Lat<Q>;
   AxisSrc ax, ay, az;
-  axis_src(x, P.nx, P.wall[0], P.sym[0], 1, ax);
-  axis_src(y, P.ny, P.wall[1], P.sym[1], P.nx, ay);
-  axis_src(z, P.nz, P.wall[2], P.sym[2], P.nx * P.ny, az);
+  axis_src(x, P.nx, P.wall[0], P.sym_lo[0], P.sym_hi[0], 1, ax);
+  axis_src(y, P.ny, P.wall[1], P.sym_lo[1], P.sym_hi[1], P.nx, ay);
+  axis_src(z, P.nz, P.wall[2], P.sym_lo[2], P.sym_hi[2], P.nx * P.ny, az);
   const int own = (z * P.ny + y) * P.nx + x;     // the node count is below 2^31
   if (P.fast) {
     constexpr uint32_t S = sizeof(typename Store<ST>::raw);
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       for (int a = 0; a < 3; ++a) {
         if (P.wall[a] && (g[a] < 0 || g[a] >= n[a])) {
           if (g[a] == -1) m[a] += 1; else if (g[a] == n[a]) m[a] -= 1; else skip = true;
-          if (P.sym[a]) sc[a] = -sc[a]; else sgn = -sgn;
+          if (g[a] < 0 ? P.sym_lo[a] : P.sym_hi[a]) sc[a] = -sc[a]; else sgn = -sgn;
         }
       }
       CT D[3] = {CT(0), CT(0), CT(0)}, v0[3] = {CT(0), CT(0), CT(0)};

@@ -93,22 +93,22 @@ __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>
 // beyond a wall (then the population bounces back into the node's own
 // opposite slot), and whether it lies beyond a symmetry plane (then the
 // source is the mirror node, x itself, and the population the one with this
-// component reversed).
+// component reversed).  sym_lo / sym_hi: the low / high boundary is a plane.
 struct AxisSrc {
   int off[3];
   bool wall[3];
   bool flip[3];
 };
-__device__ __forceinline__ void axis_src(int x, int n, int wall, int sym, int stride, AxisSrc& a) {
+__device__ __forceinline__ void axis_src(int x, int n, int wall, int sym_lo, int sym_hi, int stride, AxisSrc& a) {
   const bool hi = x + 1 >= n, lo = x - 1 < 0;
   a.off[1] = 0;
   a.wall[1] = false;
   a.flip[1] = false;
-  a.wall[0] = wall && !sym && hi;
-  a.flip[0] = wall && sym && hi;
+  a.wall[0] = wall && !sym_hi && hi;
+  a.flip[0] = wall && sym_hi && hi;
   a.off[0] = hi ? (wall ? 0 : (1 - n) * stride) : stride;
-  a.wall[2] = wall && !sym && lo;
-  a.flip[2] = wall && sym && lo;
+  a.wall[2] = wall && !sym_lo && lo;
+  a.flip[2] = wall && sym_lo && lo;
   a.off[2] = lo ? (wall ? 0 : (n - 1) * stride) : -stride;
 }
 

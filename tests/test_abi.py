@@ -96,7 +96,8 @@ def test_bad_rounding_mode_is_rejected():
 
 
 def test_boundary_flags():
-    """wall[a]: 0 periodic, 1 wall, 2 symmetry plane; anything else is rejected."""
+    """wall[a]: 0 periodic, 1 walls, 2 symmetry planes, 3 / 4 a symmetry plane
+    on the low / high side only; anything else is rejected."""
     import paper_2407_01651_amd as pfl
     w = workloads.get("coupled2d_128")
     w["symmetric"] = (True, True, False)
@@ -105,6 +106,10 @@ def test_boundary_flags():
     assert list(p.wall) == [2, 2, 0]
     s = pfl.Sizes()
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
-    p.wall[0] = 3
+    w["symmetric"] = ("lo", "hi", False)
+    p = pfl.make_params(w, "f64", "nearest")
+    assert list(p.wall) == [3, 4, 0]
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.wall[0] = 5
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
     assert "boundary" in pfl._lib.pfl_last_error().decode()

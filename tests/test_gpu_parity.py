@@ -53,6 +53,11 @@ CASES = [
     ("alloy_xysym_33x27", dict(nx=33, ny=27, seed=20, fields=("psi", "c"), Le=math.inf, U0=-0.55,
                                theta0=0.0, tau0=50.0, periodic=(False, False, True),
                                symmetric=(True, True, False)), 40),
+    # one-sided planes: symmetry on one side of an axis, a wall on the other
+    ("all_xlo_yhi_29x23", dict(nx=29, ny=23, seed=21, periodic=(False, False, True),
+                               symmetric=("lo", "hi", False)), 30),
+    ("psi_theta_corner_40x34", dict(nx=40, ny=34, seed=22, fields=("psi", "theta"), periodic=(False, False, True),
+                                    symmetric=("lo", "lo", False)), 40),
 ]
 
 

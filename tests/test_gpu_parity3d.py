@@ -40,6 +40,8 @@ CASES = [
                                        symmetric=(True, False, True)), 20),
     ("all_xyzsym_40x14x12", dict(nx=40, ny=14, nz=12, seed=32, periodic=(False, False, False),
                                  symmetric=(True, True, True)), 15),
+    ("all_corner_xylo_zhi_16x12x9", dict(nx=16, ny=12, nz=9, seed=33, periodic=(False, False, False),
+                                         symmetric=("lo", "lo", "hi")), 15),
 ]
 
 
