@@ -185,8 +185,8 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   d.nx = p->nx; d.ny = p->ny; d.nz = p->nz; d.dim = p->dim;
   for (int a = 0; a < 3; ++a) {
     d.wall[a] = p->wall[a] != 0;
-    d.sym_lo[a] = p->wall[a] == 2 || p->wall[a] == 3;
-    d.sym_hi[a] = p->wall[a] == 2 || p->wall[a] == 4;
+    if (p->wall[a] == 2 || p->wall[a] == 3) d.sym |= 1 << a;
+    if (p->wall[a] == 2 || p->wall[a] == 4) d.sym |= 1 << (3 + a);
   }
   d.N = L.N;
   d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;

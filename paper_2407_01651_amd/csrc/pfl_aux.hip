@@ -17,12 +17,13 @@ __device__ __forceinline__ long long slot(const DevParams& P, int x, int y, int 
   using L = Lat<Q>;
   int s[3] = {x - L::c[i][0], y - L::c[i][1], z - L::c[i][2]};
   const int n[3] = {P.nx, P.ny, P.nz};
-  bool bounce = false, fl[3] = {false, false, false};
+  bool bounce = false;
+  int fl[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (s[a] < 0 || s[a] >= n[a]) {
       if (!P.wall[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-      else if (s[a] < 0 ? P.sym_lo[a] : P.sym_hi[a]) { s[a] = s[a] < 0 ? -1 - s[a] : 2 * n[a] - 1 - s[a]; fl[a] = true; }
+      else if (sym_side(P, a, s[a] < 0)) { s[a] = s[a] < 0 ? -1 - s[a] : 2 * n[a] - 1 - s[a]; fl[a] = 1; }
       else bounce = true;
     }
   }

@@ -85,17 +85,39 @@ constexpr bool refl_consistent() {
 static_assert(refl_consistent<5>() && refl_consistent<9>() && refl_consistent<7>() && refl_consistent<19>(),
               "reflection tables");
 
-// Index of c_i with the components on the flagged axes reversed.  i is a
-// compile-time index in the unrolled callers, so every table entry below is
-// a constant and only the selects remain.
+// Index of c_i with the components on the flagged axes reversed, from a
+// table in constant memory (read on the edge tiles only; a select over
+// constants would hold every candidate in scalar registers).
 template <int Q>
-__device__ __forceinline__ int lat_reflected(int i, bool fx, bool fy, bool fz) {
-  using L = Lat<Q>;
-  const int a1 = L::refl[0][i];
-  const int b0 = L::refl[1][i], b1 = L::refl[1][a1];
-  const int jxy = fy ? (fx ? b1 : b0) : (fx ? a1 : i);
-  const int jz = fy ? (fx ? L::refl[2][b1] : L::refl[2][b0]) : (fx ? L::refl[2][a1] : L::refl[2][i]);
-  return fz ? jz : jxy;
+struct ReflTab {
+  signed char r[Q][8];
+};
+template <int Q>
+constexpr ReflTab<Q> make_refl_tab() {
+  ReflTab<Q> t{};
+  for (int i = 0; i < Q; ++i)
+    for (int m = 0; m < 8; ++m) {
+      int j = i;
+      for (int a = 0; a < 3; ++a)
+        if ((m >> a) & 1) j = Lat<Q>::refl[a][j];
+      t.r[i][m] = (signed char)j;
+    }
+  return t;
+}
+static __constant__ const ReflTab<5> kRefl5 = make_refl_tab<5>();
+static __constant__ const ReflTab<9> kRefl9 = make_refl_tab<9>();
+static __constant__ const ReflTab<7> kRefl7 = make_refl_tab<7>();
+static __constant__ const ReflTab<19> kRefl19 = make_refl_tab<19>();
+template <int Q> __device__ __forceinline__ const ReflTab<Q>& refl_tab();
+template <> __device__ __forceinline__ const ReflTab<5>& refl_tab<5>() { return kRefl5; }
+template <> __device__ __forceinline__ const ReflTab<9>& refl_tab<9>() { return kRefl9; }
+template <> __device__ __forceinline__ const ReflTab<7>& refl_tab<7>() { return kRefl7; }
+template <> __device__ __forceinline__ const ReflTab<19>& refl_tab<19>() { return kRefl19; }
+
+template <int Q>
+__device__ __forceinline__ int lat_reflected(int i, int fx, int fy, int fz) {
+  const int m = fx | (fy << 1) | (fz << 2);
+  return m ? (int)refl_tab<Q>().r[i][m] : i;
 }
 
 // ------------------------------------------------------------- parameters
@@ -115,7 +137,7 @@ constexpr int TAPE_PLANES = 9;
 struct DevParams {
   int nx, ny, nz, dim;
   int wall[3];                 // non-periodic axis: a wall or a symmetry plane
-  int sym_lo[3], sym_hi[3];    // the axis's low / high boundary is a symmetry plane
+  int sym;                     // symmetry planes: bit a = low side of axis a, bit 3 + a = high side
   long long N;                 // nodes
   // population plane offsets (-1 = set inactive)
   int o_ns, o_phi, o_psi, o_c, o_th;
@@ -144,6 +166,11 @@ struct DevParams {
   // rest equilibria r_i of the deviation storage (per set, per direction)
   double ref_ns[19], ref_phi[19], ref_psi[7], ref_c[7], ref_th[7];
 };
+
+// Whether the low (lo) or high boundary of axis a is a symmetry plane.
+__device__ __forceinline__ bool sym_side(const DevParams& P, int a, bool lo) {
+  return (P.sym >> (lo ? a : 3 + a)) & 1;
+}
 
 // --------------------------------------------------------- storage types
 // FP32, FP16 and BF16 storage hold deviations f_i - r_i from the rest

@@ -13,28 +13,25 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 // addressing: periodic wrap, half-way bounce-back at a wall (the node's own
 // opposite population), or specular reflection at a symmetry plane (the
 // mirror node's population with the normal component reversed) on each axis.
-template <int Q, class ST, class CT>
+// SYM: the grid has symmetry planes (a separate instantiation, so that grids
+// without them carry none of the reflection code).
+template <int Q, class ST, class CT, bool SYM = false>
 __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
                                              const DevParams& P, int x, int y, CT f[Q]) {
   using L = Lat<Q>;
   const long long N = P.N;
+  AxisSrc ax, ay;
+  axis_src(x, P.nx, P.wall[0], SYM && sym_side(P, 0, true), SYM && sym_side(P, 0, false), 1, ax);
+  axis_src(y, P.ny, P.wall[1], SYM && sym_side(P, 1, true), SYM && sym_side(P, 1, false), P.nx, ay);
+  const int m = SYM ? sym_touch(P, x, y, 0) : 0;
+  const long long own = (long long)y * P.nx + x;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    int sx = x - L::c[i][0], sy = y - L::c[i][1];
-    bool bounce = false, fx = false, fy = false;
-    if (sx < 0 || sx >= P.nx) {
-      if (!P.wall[0]) sx = sx < 0 ? sx + P.nx : sx - P.nx;
-      else if (sx < 0 ? P.sym_lo[0] : P.sym_hi[0]) { sx = sx < 0 ? -1 - sx : 2 * P.nx - 1 - sx; fx = true; }
-      else bounce = true;
-    }
-    if (sy < 0 || sy >= P.ny) {
-      if (!P.wall[1]) sy = sy < 0 ? sy + P.ny : sy - P.ny;
-      else if (sy < 0 ? P.sym_lo[1] : P.sym_hi[1]) { sy = sy < 0 ? -1 - sy : 2 * P.ny - 1 - sy; fy = true; }
-      else bounce = true;
-    }
-    const long long idx = bounce ? (long long)y * P.nx + x : (long long)sy * P.nx + sx;
-    const int plane = bounce ? L::opp[i] : lat_reflected<Q>(i, fx, fy, false);
-    f[i] = Store<ST>::template ld<CT>(base + plane * N + idx);
+    const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1;
+    const bool b = ax.wall[cx] || ay.wall[cy];
+    const int j = SYM ? pulled_population<Q>(i, m) : i;
+    const long long e = b ? (long long)L::opp[i] * N + own : (long long)j * N + own + ax.off[cx] + ay.off[cy];
+    f[i] = Store<ST>::template ld<CT>(base + e);
   }
 }
 
@@ -51,14 +48,14 @@ __device__ __forceinline__ void pull_fast(const typename Store<ST>::raw* __restr
   }
 }
 
-template <int Q, class ST, class CT>
+template <int Q, class ST, class CT, bool SYM = false>
 __device__ __forceinline__ void pull(bool fast, const typename Store<ST>::raw* __restrict__ base,
                                      const DevParams& P, int x, int y, CT f[Q]) {
   if (fast) {
     const uint32_t nbyte = ((uint32_t)y * (uint32_t)P.nx + (uint32_t)x) * (uint32_t)sizeof(typename Store<ST>::raw);
     pull_fast<Q, ST, CT>(base, P, nbyte, f);
   } else {
-    pull_general<Q, ST, CT>(base, P, x, y, f);
+    pull_general<Q, ST, CT, SYM>(base, P, x, y, f);
   }
 }
 

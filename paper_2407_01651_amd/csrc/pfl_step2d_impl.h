@@ -24,7 +24,7 @@
 
 namespace pfl {
 
-template <int FIELDS, int QP, class ST, class HT, class CT>
+template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM>
 __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
                                                     const typename Store<ST>::raw* __restrict__ fin,
                                                     typename Store<ST>::raw* __restrict__ fout,
@@ -110,24 +110,24 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   }
   if (own) {
     if constexpr (NS) {
-      pull<QN, ST, CT>(fast, fin_ns, P, x, y, fns);
+      pull<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) { jx += CT(LN::c[i][0]) * fns[i]; jy += CT(LN::c[i][1]) * fns[i]; }
     }
     if constexpr (PHI) {
-      pull<QP, ST, CT>(fast, fin_phi, P, x, y, fph);
+      pull<QP, ST, CT, SYM>(fast, fin_phi, P, x, y, fph);
 #pragma unroll
       for (int i = 0; i < QP; ++i) dphi += fph[i];
       phi = r_phi + dphi;
     }
     if constexpr (PSI) {
-      pull<QS, ST, CT>(fast, fin_psi, P, x, y, fps);
+      pull<QS, ST, CT, SYM>(fast, fin_psi, P, x, y, fps);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { dpsi += fps[i]; s_fps[i][ly + R][lx + R] = fps[i]; }
       psi = r_psi + dpsi;
     }
     if constexpr (CC) {
-      pull<QS, ST, CT>(fast, fin_c, P, x, y, fc);
+      pull<QS, ST, CT, SYM>(fast, fin_c, P, x, y, fc);
 #pragma unroll
       for (int i = 0; i < QS; ++i) dC += fc[i];
       C = r_C + dC;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       U = (C * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull<QS, ST, CT>(fast, fin_th, P, x, y, fth);
+      pull<QS, ST, CT, SYM>(fast, fin_th, P, x, y, fth);
 #pragma unroll
       for (int i = 0; i < QS; ++i) dH += fth[i];
       H = r_H + dH;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hjx = CT(0), hjy = CT(0);
     if constexpr (PHI) {
       CT f[QP];
-      pull<QP, ST, CT>(hfast, fin_phi, P, gx, gy, f);
+      pull<QP, ST, CT, SYM>(hfast, fin_phi, P, gx, gy, f);
       CT d = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) d += f[i];
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull<QS, ST, CT>(hfast, fin_psi, P, gx, gy, f);
+        pull<QS, ST, CT, SYM>(hfast, fin_psi, P, gx, gy, f);
         CT d = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) { d += f[i]; s_fps[i][ry][rx] = f[i]; }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       }
       if constexpr (CC) {
         CT f[QS];
-        pull<QS, ST, CT>(hfast, fin_c, P, gx, gy, f);
+        pull<QS, ST, CT, SYM>(hfast, fin_c, P, gx, gy, f);
         CT d = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) d += f[i];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       }
       if constexpr (NS) {
         CT f[QN];
-        pull<QN, ST, CT>(hfast, fin_ns, P, gx, gy, f);
+        pull<QN, ST, CT, SYM>(hfast, fin_ns, P, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) { hjx += CT(LN::c[i][0]) * f[i]; hjy += CT(LN::c[i][1]) * f[i]; }
       }
@@ -233,11 +233,11 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       bool skip = false;
       if (P.wall[0] && (gx0 < 0 || gx0 >= P.nx)) {
         if (gx0 == -1) mx = rx + 1; else if (gx0 == P.nx) mx = rx - 1; else skip = true;
-        if (gx0 < 0 ? P.sym_lo[0] : P.sym_hi[0]) sod = -sod; else sgn = -sgn;
+        if (SYM && sym_side(P, 0, gx0 < 0)) sod = -sod; else sgn = -sgn;
       }
       if (P.wall[1] && (gy0 < 0 || gy0 >= P.ny)) {
         if (gy0 == -1) my = ry + 1; else if (gy0 == P.ny) my = ry - 1; else skip = true;
-        if (gy0 < 0 ? P.sym_lo[1] : P.sym_hi[1]) sod = -sod; else sgn = -sgn;
+        if (SYM && sym_side(P, 1, gy0 < 0)) sod = -sod; else sgn = -sgn;
       }
       CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
       if (!skip) {
@@ -591,8 +591,12 @@ hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void
                            double* mout, int mode, hipStream_t s) {
   dim3 grid(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   using raw = typename Store<ST>::raw;
-  hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT>), grid, dim3(NT), 0, s, P,
-                     (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  if (P.sym)
+    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, true>), grid, dim3(NT), 0, s, P,
+                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  else
+    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, false>), grid, dim3(NT), 0, s, P,
+                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   return hipGetLastError();
 }
 

@@ -44,14 +44,15 @@ __device__ __forceinline__ long long nidx3(const DevParams& P, int x, int y, int
 // periodic wrap, half-way bounce-back at a wall or specular reflection at a
 // symmetry plane on each axis, from per-axis source offsets computed once
 // per node.
-template <int Q, class ST, class CT>
+template <int Q, class ST, class CT, bool SYM>
 __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __restrict__ base,
                                               const DevParams& P, int x, int y, int z, CT f[Q]) {
   using L = Lat<Q>;
   AxisSrc ax, ay, az;
-  axis_src(x, P.nx, P.wall[0], P.sym_lo[0], P.sym_hi[0], 1, ax);
-  axis_src(y, P.ny, P.wall[1], P.sym_lo[1], P.sym_hi[1], P.nx, ay);
-  axis_src(z, P.nz, P.wall[2], P.sym_lo[2], P.sym_hi[2], P.nx * P.ny, az);
+  axis_src(x, P.nx, P.wall[0], SYM && sym_side(P, 0, true), SYM && sym_side(P, 0, false), 1, ax);
+  axis_src(y, P.ny, P.wall[1], SYM && sym_side(P, 1, true), SYM && sym_side(P, 1, false), P.nx, ay);
+  axis_src(z, P.nz, P.wall[2], SYM && sym_side(P, 2, true), SYM && sym_side(P, 2, false), P.nx * P.ny, az);
+  const int m = SYM ? sym_touch(P, x, y, z) : 0;
   const int own = (z * P.ny + y) * P.nx + x;     // the node count is below 2^31
   if (P.fast) {
     constexpr uint32_t S = sizeof(typename Store<ST>::raw);
@@ -60,7 +61,7 @@ __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __r
     for (int i = 0; i < Q; ++i) {
       const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
       const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
-      const int j = lat_reflected<Q>(i, ax.flip[cx], ay.flip[cy], az.flip[cz]);
+      const int j = SYM ? pulled_population<Q>(i, m) : i;
       const uint32_t e = b ? (uint32_t)L::opp[i] * N + (uint32_t)own
                            : (uint32_t)j * N + (uint32_t)(own + ax.off[cx] + ay.off[cy] + az.off[cz]);
       f[i] = Store<ST>::template ld<CT>(at_byte<ST>(base, e * S));
@@ -71,7 +72,7 @@ __device__ __forceinline__ void pull3_general(const typename Store<ST>::raw* __r
     for (int i = 0; i < Q; ++i) {
       const int cx = L::c[i][0] + 1, cy = L::c[i][1] + 1, cz = L::c[i][2] + 1;
       const bool b = ax.wall[cx] || ay.wall[cy] || az.wall[cz];
-      const int j = lat_reflected<Q>(i, ax.flip[cx], ay.flip[cy], az.flip[cz]);
+      const int j = SYM ? pulled_population<Q>(i, m) : i;
       const long long e = b ? (long long)L::opp[i] * N + own
                             : (long long)j * N + (own + ax.off[cx] + ay.off[cy] + az.off[cz]);
       f[i] = Store<ST>::template ld<CT>(base + e);
@@ -97,14 +98,14 @@ __device__ __forceinline__ void pull3_fast(const typename Store<ST>::raw* __rest
   }
 }
 
-template <int Q, class ST, class CT>
+template <int Q, class ST, class CT, bool SYM>
 __device__ __forceinline__ void pull3(bool fast, const typename Store<ST>::raw* __restrict__ base,
                                       const DevParams& P, int x, int y, int z, CT f[Q]) {
   if (fast) {
     const uint32_t nbyte = (uint32_t)((z * P.ny + y) * P.nx + x) * (uint32_t)sizeof(typename Store<ST>::raw);
     pull3_fast<Q, ST, CT>(base, P, nbyte, f);
   } else {
-    pull3_general<Q, ST, CT>(base, P, x, y, z, f);
+    pull3_general<Q, ST, CT, SYM>(base, P, x, y, z, f);
   }
 }
 
@@ -186,7 +187,7 @@ __device__ __forceinline__ void flow_node3(const KP<CT>& K, const CT* s_phi, con
   }
 }
 
-template <int FIELDS, class ST, class HT, class CT>
+template <int FIELDS, class ST, class HT, class CT, bool SYM>
 // FP32 compute: ask for three waves per SIMD (measured 12% faster on the
 // 256^3 FP16 workload than two, despite a few spilled registers)
 __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d_kernel(const DevParams P,
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       }
     }
     if constexpr (NS) {
-      pull3<QN, ST, CT>(fast, fin_ns, P, x, y, z, fns);
+      pull3<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, z, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) {
         if (LN::c[i][0]) j[0] += CT(LN::c[i][0]) * fns[i];
@@ -275,19 +276,19 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       }
     }
     if constexpr (PHI) {
-      pull3<QP, ST, CT>(fast, fin_phi, P, x, y, z, fph);
+      pull3<QP, ST, CT, SYM>(fast, fin_phi, P, x, y, z, fph);
 #pragma unroll
       for (int i = 0; i < QP; ++i) dphi += fph[i];
       phi = r_phi + dphi;
     }
     if constexpr (PSI) {
-      pull3<QS, ST, CT>(fast, fin_psi, P, x, y, z, fps);
+      pull3<QS, ST, CT, SYM>(fast, fin_psi, P, x, y, z, fps);
 #pragma unroll
       for (int i = 0; i < QS; ++i) dpsi += fps[i];
       psi = r_psi + dpsi;
     }
     if constexpr (CC) {
-      pull3<QS, ST, CT>(fast, fin_c, P, x, y, z, fc);
+      pull3<QS, ST, CT, SYM>(fast, fin_c, P, x, y, z, fc);
 #pragma unroll
       for (int i = 0; i < QS; ++i) dC += fc[i];
       C = r_C + dC;
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       U = (C * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull3<QS, ST, CT>(fast, fin_th, P, x, y, z, fth);
+      pull3<QS, ST, CT, SYM>(fast, fin_th, P, x, y, z, fth);
 #pragma unroll
       for (int i = 0; i < QS; ++i) dH += fth[i];
       H = r_H + dH;
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
     CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hj[3] = {CT(0), CT(0), CT(0)};
     if constexpr (PHI) {
       CT f[QP];
-      pull3<QP, ST, CT>(fast, fin_phi, P, gx, gy, gz, f);
+      pull3<QP, ST, CT, SYM>(fast, fin_phi, P, gx, gy, gz, f);
       CT d = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) d += f[i];
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull3<QS, ST, CT>(fast, fin_psi, P, gx, gy, gz, f);
+        pull3<QS, ST, CT, SYM>(fast, fin_psi, P, gx, gy, gz, f);
         CT d = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) d += f[i];
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       }
       if constexpr (CC) {
         CT f[QS];
-        pull3<QS, ST, CT>(fast, fin_c, P, gx, gy, gz, f);
+        pull3<QS, ST, CT, SYM>(fast, fin_c, P, gx, gy, gz, f);
         CT d = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) d += f[i];
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       }
       if constexpr (NS) {
         CT f[QN];
-        pull3<QN, ST, CT>(fast, fin_ns, P, gx, gy, gz, f);
+        pull3<QN, ST, CT, SYM>(fast, fin_ns, P, gx, gy, gz, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) {
           if (LN::c[i][0]) hj[0] += CT(LN::c[i][0]) * f[i];
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       for (int a = 0; a < 3; ++a) {
         if (P.wall[a] && (g[a] < 0 || g[a] >= n[a])) {
           if (g[a] == -1) m[a] += 1; else if (g[a] == n[a]) m[a] -= 1; else skip = true;
-          if (g[a] < 0 ? P.sym_lo[a] : P.sym_hi[a]) sc[a] = -sc[a]; else sgn = -sgn;
+          if (SYM && sym_side(P, a, g[a] < 0)) sc[a] = -sc[a]; else sgn = -sgn;
         }
       }
       CT D[3] = {CT(0), CT(0), CT(0)}, v0[3] = {CT(0), CT(0), CT(0)};
@@ -781,8 +782,12 @@ hipError_t launch_step3d_t(const DevParams& P, const void* fin, void* fout, void
   const long long tiles = (long long)((P.nx + T::TX - 1) / T::TX) * ((P.ny + T::TY - 1) / T::TY) *
                           ((P.nz + T::TZ - 1) / T::TZ);
   using raw = typename Store<ST>::raw;
-  hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
-                     (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  if (P.sym)
+    hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, true>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
+                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  else
+    hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, false>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
+                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   return hipGetLastError();
 }
 

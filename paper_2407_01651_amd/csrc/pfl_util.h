@@ -89,27 +89,52 @@ __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>
 }
 
 // Source offsets along one axis for a node at coordinate x: entry c + 1
-// holds the element offset of x - c (periodic wrap), whether x - c lies
+// holds the element offset of x - c (periodic wrap) and whether x - c lies
 // beyond a wall (then the population bounces back into the node's own
-// opposite slot), and whether it lies beyond a symmetry plane (then the
-// source is the mirror node, x itself, and the population the one with this
-// component reversed).  sym_lo / sym_hi: the low / high boundary is a plane.
+// opposite slot).  Beyond a symmetry plane (sym_lo / sym_hi: the low / high
+// boundary is one) the source is the mirror node, x itself on this axis
+// (offset 0, no bounce); which population it is comes from sym_touch.
 struct AxisSrc {
   int off[3];
   bool wall[3];
-  bool flip[3];
 };
 __device__ __forceinline__ void axis_src(int x, int n, int wall, int sym_lo, int sym_hi, int stride, AxisSrc& a) {
   const bool hi = x + 1 >= n, lo = x - 1 < 0;
   a.off[1] = 0;
   a.wall[1] = false;
-  a.flip[1] = false;
   a.wall[0] = wall && !sym_hi && hi;
-  a.flip[0] = wall && sym_hi && hi;
   a.off[0] = hi ? (wall ? 0 : (1 - n) * stride) : stride;
   a.wall[2] = wall && !sym_lo && lo;
-  a.flip[2] = wall && sym_lo && lo;
   a.off[2] = lo ? (wall ? 0 : (n - 1) * stride) : -stride;
+}
+
+// Symmetry planes next to node (x, y, z), one bit each: 0 low x, 1 high x,
+// 2 low y, 3 high y, 4 low z, 5 high z (zero without symmetry planes).
+__device__ __forceinline__ int sym_touch(const DevParams& P, int x, int y, int z) {
+  if (!P.sym) return 0;
+  const int c[3] = {x, y, z}, n[3] = {P.nx, P.ny, P.nz};
+  int m = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (c[a] == 0 && sym_side(P, a, true)) m |= 1 << (2 * a);
+    if (c[a] == n[a] - 1 && sym_side(P, a, false)) m |= 2 << (2 * a);
+  }
+  return m;
+}
+
+// The population read in place of population i at a node with sym_touch m:
+// the components whose source lies beyond a symmetry plane are reversed.
+template <int Q>
+__device__ __forceinline__ int pulled_population(int i, int m) {
+  using L = Lat<Q>;
+  int f = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // c_a > 0 reads across the low plane, c_a < 0 across the high one
+    if (L::c[i][a] > 0) f |= ((m >> (2 * a)) & 1) << a;
+    if (L::c[i][a] < 0) f |= ((m >> (2 * a + 1)) & 1) << a;
+  }
+  return f ? lat_reflected<Q>(i, f & 1, (f >> 1) & 1, (f >> 2) & 1) : i;
 }
 
 }  // namespace pfl
