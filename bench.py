@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward cost ratio on the 512^2 adjoint workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=None,
+                    help="shorten the adjoint workload (profiling runs); default its 2000 steps")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--calib", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration under rocprofv3)")
@@ -122,7 +124,7 @@ def time_gpu(w, store, steps, warmup, rounding=None):
                 achieved_gbs=gbs, nonfinite=r["nonfinite"], solid_fraction=r["solid_fraction"])
 
 
-def time_adjoint(name="adjoint2d_512", store="f32", K=100):
+def time_adjoint(name="adjoint2d_512", store="f32", K=100, steps=None):
     """Cost of the gradient of a morphology loss relative to the plain forward:
     (forward with checkpoints every K steps + checkpointed adjoint sweep) /
     (forward), both over the workload's full step count, HIP events on the
@@ -134,7 +136,7 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100):
     import paper_2407_01651_amd as pfl
     from paper_2407_01651_amd.adjoint import CheckpointedRun, ResidentRun, params_of, workload_at
     w = workloads.get(name)
-    steps = w["steps"]
+    steps = int(steps or w["steps"])
     p = params_of(w)
     tgt = CheckpointedRun(workload_at(w, [a + b for a, b in zip(p, [0.005, 0.01, 0.02] + [0.5] * (len(p) - 3))]),
                           store=store, K=steps)
@@ -243,7 +245,7 @@ def main():
     for item in [s for s in a.extra.split(",") if s]:
         cfg, st = item.split(":")
         variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding)
-    adj = None if a.no_adjoint else time_adjoint()
+    adj = None if a.no_adjoint else time_adjoint(steps=a.adjoint_steps)
     cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
     n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
     out = {
