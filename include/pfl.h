@@ -242,6 +242,32 @@ int pfl_step_raw_taped(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t st
 int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
                             const void* tape, const void* adj_in, void* adj_out, double* dparams);
 
+/* Flags of pfl_backward_sweep. */
+#define PFL_SWEEP_CONTINUE  1   /* add to the parameter partials left open by the previous sweep */
+#define PFL_SWEEP_DEFER_SUM 2   /* leave the partials open instead of adding them to dparams */
+
+/* The reverse of the n steps step0 .. step0 + n - 1 in one call: for
+ * k = n - 1 down to 0, the adjoint of step step0 + k at the raw image
+ * raw_states[k] (the state that step started from), with first-step flag
+ * (first0 && k == 0) and the tape tapes[k] of pfl_step_raw_taped, or, with
+ * tapes null, with the stencils recomputed as in pfl_step_backward_raw.
+ * raw_states and tapes are host arrays of n device pointers.  On entry adj
+ * holds lambda after the last step, on return lambda before the first (adjoint
+ * type of pfl_step_backward); adj_tmp is caller-owned device scratch of the
+ * same size.  The eps4 and k terms are kept as per-block FP64 partials summed
+ * over the steps in reverse order and added to dparams once, at the end, in a
+ * fixed order: the result is reproducible and differs from n calls of
+ * pfl_step_backward_taped only by the rounding of that order.  flags:
+ * PFL_SWEEP_DEFER_SUM leaves the partials open, PFL_SWEEP_CONTINUE carries on
+ * with the open partials of the previous sweep on this context (so the sweep of
+ * a run split into segments sums exactly as one sweep over the whole run).
+ * n = 0 only sums open partials (with PFL_SWEEP_CONTINUE, without
+ * PFL_SWEEP_DEFER_SUM).  Errors as pfl_step_backward; PFL_E_STATE for
+ * PFL_SWEEP_CONTINUE when no partials are open (any other adjoint call on the
+ * context closes them). */
+int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* const* tapes, int64_t n,
+                       int64_t step0, int first0, void* adj, void* adj_tmp, double* dparams, int flags);
+
 /* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
  * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling
  * (theta0 = -Omega when the heat equation is solved, U0 = -Omega otherwise)

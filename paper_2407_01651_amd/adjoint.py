@@ -10,13 +10,14 @@ Forward: one launch per step, with a raw checkpoint of the state (storage
 type, bit-exact) every K steps.  Backward, segment by segment from the last:
 the segment's states are recomputed from its checkpoint image to image with
 pfl_step_raw_taped (same stochastic rounding keys, so bit-identical), which
-also keeps each step's stencil results (its tape), then
-pfl_step_backward_taped takes the node-form adjoint back one step at a time at
-each image, with that step's tape, and accumulates dL/d(eps4, k); finally
-pfl_init_backward adds the gradient through the initial profiles.  The
-recompute of the previous segment runs on a second stream (its own
-forward-only context) while the current segment is reversed, into a second
-set of segment images and tapes.  Memory: one raw image per checkpoint plus
+also keeps each step's stencil results (its tape), then one
+pfl_backward_sweep call takes the node-form adjoint back over the segment,
+step by step at each image with that step's tape, keeping dL/d(eps4, k) as
+per-block partials that stay open from segment to segment and are summed once
+after the first segment; finally pfl_init_backward adds the gradient through
+the initial profiles.  The recompute of the previous segment runs on a second
+stream (its own forward-only context) while the current segment is reversed,
+into a second set of segment images and tapes.  Memory: one raw image per checkpoint plus
 2 (K - 1) raw images and 2 K tapes (nine planes of N values each).
 Every step of the path runs in the library's kernels; this module only
 orders the calls and holds the buffers.
@@ -175,14 +176,9 @@ class CheckpointedRun:
                 main.wait_event(ready[si])
             else:
                 self._recompute(si)
-            img = self._images(si)
-            tp = self._tapes(si) if self.taped else None
-            for j in range(n - 1, -1, -1):
-                if self.taped:
-                    sim.step_backward_taped(img[j], s0 + j, s0 + j == 0, tp[j], lam, other, dparams)
-                else:
-                    sim.step_backward_raw(img[j], s0 + j, s0 + j == 0, lam, other, dparams)
-                lam, other = other, lam
+            tp = self._tapes(si)[:n] if self.taped else None
+            sim.backward_sweep(self._images(si)[:n], s0, s0 == 0, tp, lam, other, dparams,
+                               cont=si < n_ck - 1, defer=si > 0)
             if self.overlap:
                 freed[si % 2].record(main)
         sim.init_backward(lam, dparams)
@@ -234,9 +230,7 @@ class ResidentRun:
         dparams = torch.zeros(3 + len(self.w["bubbles"]), dtype=torch.float64, device=sim.device)
         lam = lam.to(sim.adj_dtype).contiguous().clone()
         other = torch.empty_like(lam)
-        for j in range(self.steps - 1, -1, -1):
-            sim.step_backward_taped(self.imgs[j], j, j == 0, self.tapes[j], lam, other, dparams)
-            lam, other = other, lam
+        sim.backward_sweep(self.imgs, 0, True, self.tapes, lam, other, dparams, n=self.steps)
         sim.init_backward(lam, dparams)
         return dparams
 

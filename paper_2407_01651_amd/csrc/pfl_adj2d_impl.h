@@ -932,7 +932,8 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __
 // ------------------------------------------------------------------- R3
 template <int FIELDS, int QP, class CT>
 __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, const CT* __restrict__ S_in,
-                                                           CT* __restrict__ lam_out, double* __restrict__ part) {
+                                                           CT* __restrict__ lam_out, double* __restrict__ part,
+                                                           int accumulate) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   using LN = Lat<9>;
@@ -980,7 +981,12 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
       if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
       __syncthreads();
     }
-    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s_e[0]; part[2 * blockIdx.x + 1] = s_k[0]; }
+    // accumulate: a sweep over several steps adds each block's partials in
+    // step order (each block owns its slots), summed once at the end
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = (accumulate ? part[2 * blockIdx.x] : 0.0) + s_e[0];
+      part[2 * blockIdx.x + 1] = (accumulate ? part[2 * blockIdx.x + 1] : 0.0) + s_k[0];
+    }
   }
   if (!live) return;
   auto add = [&](int plane, CT v) { at_node(lam_out + (long long)plane * N, n) += v; };
@@ -1045,7 +1051,8 @@ inline size_t part_offset(long long N, size_t elem) {
 
 template <int FIELDS, int QP, class ST, class HT>
 hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const void* tape_v,
-                      const void* lam_in_v, void* lam_out_v, void* scratch, double* dparams, hipStream_t s) {
+                      const void* lam_in_v, void* lam_out_v, void* scratch, double* dparams, hipStream_t s,
+                      bool accumulate, bool sum) {
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
@@ -1070,8 +1077,9 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, (const RT*)S, lam_out,
-                     part);
+                     part, accumulate ? 1 : 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!sum) return hipSuccess;
   hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
   return hipGetLastError();
 }
@@ -1079,13 +1087,13 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
 template <class ST, class HT>
 hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const void* hist, const void* tape,
                         const void* lam_in, void* lam_out, void* S, double* dparams, hipStream_t s,
-                        bool& ok) {
+                        bool accumulate, bool sum, bool& ok) {
   ok = true;
   const bool q9 = P.q_phi == 9;
 #define PFL_ADJ(F)                                                                               \
   case F:                                                                                        \
-    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s)     \
-              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s);
+    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, accumulate, sum) \
+              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, accumulate, sum);
   switch (fields) {
     PFL_ADJ(F_NS | F_PHI | F_PSI | F_C | F_TH)
     PFL_ADJ(F_PSI | F_C)

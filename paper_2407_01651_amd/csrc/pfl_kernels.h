@@ -32,15 +32,19 @@ inline hipError_t launch_step(const DevParams& P, int fields, int store, const v
 // (P.tape), or null to redo the stencils.
 size_t adj_scratch_bytes(long long N, int store);
 bool adj2d_supported(int fields);
+// accumulate: add the parameter partials to those of the previous steps of a
+// sweep; sum: add the partials to dparams after this step.
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
                              const void* tape, const void* lam_in, void* lam_out, void* scratch,
-                             double* dparams, hipStream_t s, bool& ok);
+                             double* dparams, hipStream_t s, bool& ok, bool accumulate = false, bool sum = true);
 hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s);
+// Adds the per-block parameter partials left by the last step to dparams.
+hipError_t launch_adj_param_sum(const DevParams& P, int store, void* scratch, double* dparams, hipStream_t s);
 // The FP32-compute part of launch_adj_step2d (stores 1-3).
 hipError_t launch_adj_step2d_lowp(const DevParams& P, int fields, int store, const void* fin, const void* hist,
                                   const void* tape, const void* lam_in, void* lam_out, void* scratch,
-                                  double* dparams, hipStream_t s, bool& ok);
+                                  double* dparams, hipStream_t s, bool& ok, bool accumulate, bool sum);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
 // planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium

@@ -338,6 +338,73 @@ def test_step_raw_reproduces_step_bit_for_bit(store):
 
 
 @pytest.mark.parametrize("store", ["f64", "f32"])
+def test_backward_sweep_matches_single_steps(store):
+    """pfl_backward_sweep (the reverse of n steps in one call) against n calls
+    of pfl_step_backward_taped / _raw: the adjoint state bit for bit (odd and
+    even n, taped and recomputed stencils); dparams to the rounding of the
+    summation order (1e-12 relative), and bit for bit between one sweep and
+    the same reverse split into segments that carry the partials over, or
+    whose sum is deferred to an empty sweep."""
+    import paper_2407_01651_amd as pfl
+    w = _w(dict(nx=20, ny=14, seed=31))
+    sim = pfl.Sim(w, store=store, adjoint=True)
+    sim.init_fields()
+    n = 7
+    imgs = [sim.raw_buffer() for _ in range(n + 1)]
+    tapes = [sim.tape_buffer() for _ in range(n)]
+    sim.save_raw(imgs[0])
+    for j in range(n):
+        sim.step_raw_taped(imgs[j], imgs[j + 1], j, j == 0, tapes[j])
+    g = torch.Generator().manual_seed(107)
+    lam0 = torch.randn((sim.state_planes(),) + sim.shape, generator=g, dtype=torch.float64).to("cuda", sim.adj_dtype)
+    nb = 3 + len(w["bubbles"])
+
+    def single(m, taped):
+        lam, other = lam0.clone(), torch.empty_like(lam0)
+        dp = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        for j in range(m - 1, -1, -1):
+            if taped:
+                sim.step_backward_taped(imgs[j], j, j == 0, tapes[j], lam, other, dp)
+            else:
+                sim.step_backward_raw(imgs[j], j, j == 0, lam, other, dp)
+            lam, other = other, lam
+        return lam.cpu(), dp.cpu()
+
+    def sweep(parts, taped=True, empty_sum=False):
+        lam, tmp = lam0.clone(), torch.empty_like(lam0)
+        dp = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        for i, (a, b) in enumerate(parts):     # [a, b) in reverse order of a
+            last = i == len(parts) - 1
+            sim.backward_sweep(imgs[a:b], a, a == 0, tapes[a:b] if taped else None, lam, tmp, dp,
+                               cont=i > 0, defer=not last or empty_sum)
+        if empty_sum:
+            sim.backward_sweep([], 0, True, [], lam, tmp, dp, cont=True)
+        return lam.cpu(), dp.cpu()
+
+    for m in (n, n - 1):
+        for taped in (True, False):
+            l1, d1 = single(m, taped)
+            l2, d2 = sweep([(0, m)], taped)
+            assert torch.equal(l1, l2), (store, m, taped)
+            rel = float((d1 - d2).abs().max()) / float(d1[:2].abs().max())
+            log(f"[adjoint] sweep {store} n={m} taped={taped} dparams rel {rel:.1e}")
+            assert rel < 1e-12, (store, m, taped, rel)
+    whole = sweep([(0, n)])
+    for parts, es in (([(4, n), (1, 4), (0, 1)], False), ([(0, n)], True), ([(3, n), (0, 3)], True)):
+        got = sweep(parts, empty_sum=es)
+        assert torch.equal(got[0], whole[0]) and torch.equal(got[1], whole[1]), (parts, es)
+    # carrying on without open partials is an error, and so is it after any
+    # other adjoint call on the context
+    lam, tmp = lam0.clone(), torch.empty_like(lam0)
+    dp = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    sim.backward_sweep(imgs[1:n], 1, False, tapes[1:n], lam, tmp, dp, defer=True)
+    sim.step_backward_taped(imgs[0], 0, True, tapes[0], lam, tmp, dp)
+    with pytest.raises(Exception, match="CONTINUE"):
+        sim.backward_sweep(imgs[0:1], 0, True, tapes[0:1], lam, tmp, dp, cont=True)
+    sim.close()
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
 def test_resident_run_matches_checkpointed_run(store):
     """Every state and tape kept in HBM (no recompute) gives the gradient of
     the checkpointed sweep bit for bit: the recompute reproduces the images
