@@ -243,8 +243,8 @@ int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_coun
                             const void* tape, const void* adj_in, void* adj_out, double* dparams);
 
 /* Flags of pfl_backward_sweep. */
-#define PFL_SWEEP_CONTINUE  1   /* add to the parameter partials left open by the previous sweep */
-#define PFL_SWEEP_DEFER_SUM 2   /* leave the partials open instead of adding them to dparams */
+#define PFL_SWEEP_CONTINUE  1   /* carry on from the open sweep before (this context) */
+#define PFL_SWEEP_OPEN      2   /* leave this sweep open, to be continued */
 
 /* The reverse of the n steps step0 .. step0 + n - 1 in one call: for
  * k = n - 1 down to 0, the adjoint of step step0 + k at the raw image
@@ -254,17 +254,22 @@ int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_coun
  * raw_states and tapes are host arrays of n device pointers.  On entry adj
  * holds lambda after the last step, on return lambda before the first (adjoint
  * type of pfl_step_backward); adj_tmp is caller-owned device scratch of the
- * same size.  The eps4 and k terms are kept as per-block FP64 partials summed
- * over the steps in reverse order and added to dparams once, at the end, in a
- * fixed order: the result is reproducible and differs from n calls of
- * pfl_step_backward_taped only by the rounding of that order.  flags:
- * PFL_SWEEP_DEFER_SUM leaves the partials open, PFL_SWEEP_CONTINUE carries on
- * with the open partials of the previous sweep on this context (so the sweep of
- * a run split into segments sums exactly as one sweep over the whole run).
- * n = 0 only sums open partials (with PFL_SWEEP_CONTINUE, without
- * PFL_SWEEP_DEFER_SUM).  Errors as pfl_step_backward; PFL_E_STATE for
- * PFL_SWEEP_CONTINUE when no partials are open (any other adjoint call on the
- * context closes them). */
+ * same size.  Between steps the moment terms of lambda stay in the context's
+ * adjoint scratch and are added where the next step reads lambda (equal to n
+ * calls of pfl_step_backward_taped in FP64; in FP32 to rounding).  The eps4
+ * and k terms are kept as per-block FP64 partials summed over the steps in
+ * reverse order and added to dparams once, at the end, in a fixed order: the
+ * result is reproducible and differs from n single steps only by the rounding
+ * of that order.
+ * flags: PFL_SWEEP_OPEN leaves the sweep open: the partials are not added to
+ * dparams and adj on return lacks the last step's moment terms (it is not yet
+ * lambda); only a following sweep with PFL_SWEEP_CONTINUE on this context can
+ * use it, carrying on exactly as one sweep (a run reversed segment by segment
+ * gives the result of one sweep over the whole run, bit for bit).  n = 0 with
+ * PFL_SWEEP_CONTINUE and without PFL_SWEEP_OPEN closes the open sweep: adj
+ * becomes lambda and the partials are added to dparams.
+ * Errors as pfl_step_backward; PFL_E_STATE for PFL_SWEEP_CONTINUE when no
+ * sweep is open (any other adjoint call on the context closes it). */
 int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* const* tapes, int64_t n,
                        int64_t step0, int first0, void* adj, void* adj_tmp, double* dparams, int flags);
 

@@ -23,7 +23,7 @@ _lib = ct.CDLL(LIB_PATH)
 
 ABI_VERSION = 1
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
-SWEEP_CONTINUE, SWEEP_DEFER_SUM = 1, 2
+SWEEP_CONTINUE, SWEEP_OPEN = 1, 2
 NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
 F64, F32, F16, BF16 = 0, 1, 2, 3
 STORES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
@@ -252,22 +252,23 @@ class Sim:
         """Host array of the device addresses of tensors (for backward_sweep)."""
         return (ct.c_void_p * max(len(tensors), 1))(*[t.data_ptr() for t in tensors])
 
-    def backward_sweep(self, raws, step0, first0, tapes, lam, tmp, dparams, n=None, cont=False, defer=False):
+    def backward_sweep(self, raws, step0, first0, tapes, lam, tmp, dparams, n=None, cont=False, open=False):
         """The reverse of steps step0 .. step0 + n - 1 in one library call
         (pfl_backward_sweep): raws[k] is the image step step0 + k started
         from, tapes[k] its tape (tapes None: stencils recomputed).  raws and
         tapes are lists of tensors or arrays from pointers().  lam holds the
         adjoint after the last step on entry and before the first on return;
-        tmp is scratch of the same shape.  cont / defer: carry on with / leave
-        open the per-block parameter partials (a run reversed segment by
-        segment sums as one sweep)."""
+        tmp is scratch of the same shape.  open: leave the sweep open (lam
+        is not yet the adjoint, the partials not yet in dparams); cont: carry
+        on from the open sweep before, as one sweep would (n = 0 with cont
+        closes it)."""
         self._adj(lam, tmp)
         n = len(raws) if n is None else int(n)
         if n > len(raws) or (tapes is not None and n > len(tapes)):
             raise ValueError("fewer images or tapes than steps")
         rp = raws if isinstance(raws, ct.Array) else self.pointers(raws)
         tp = None if tapes is None else (tapes if isinstance(tapes, ct.Array) else self.pointers(tapes))
-        flags = (SWEEP_CONTINUE if cont else 0) | (SWEEP_DEFER_SUM if defer else 0)
+        flags = (SWEEP_CONTINUE if cont else 0) | (SWEEP_OPEN if open else 0)
         tpp = None if tp is None else ct.cast(tp, ct.c_void_p)
         _check(_lib.pfl_backward_sweep(self.ctx, ct.cast(rp, ct.c_void_p), tpp, n, int(step0), 1 if first0 else 0, ct.c_void_p(lam.data_ptr()),
                                        ct.c_void_p(tmp.data_ptr()), ct.c_void_p(dparams.data_ptr()), flags))

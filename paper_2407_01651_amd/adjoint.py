@@ -12,9 +12,10 @@ the segment's states are recomputed from its checkpoint image to image with
 pfl_step_raw_taped (same stochastic rounding keys, so bit-identical), which
 also keeps each step's stencil results (its tape), then one
 pfl_backward_sweep call takes the node-form adjoint back over the segment,
-step by step at each image with that step's tape, keeping dL/d(eps4, k) as
-per-block partials that stay open from segment to segment and are summed once
-after the first segment; finally pfl_init_backward adds the gradient through
+step by step at each image with that step's tape; the sweep stays open from
+segment to segment (moment terms of the adjoint and per-block dL/d(eps4, k)
+partials kept in the library's scratch), so the reverse is that of one sweep
+over the run; finally pfl_init_backward adds the gradient through
 the initial profiles.  The recompute of the previous segment runs on a second
 stream (its own forward-only context) while the current segment is reversed,
 into a second set of segment images and tapes.  Memory: one raw image per checkpoint plus
@@ -178,7 +179,7 @@ class CheckpointedRun:
                 self._recompute(si)
             tp = self._tapes(si)[:n] if self.taped else None
             sim.backward_sweep(self._images(si)[:n], s0, s0 == 0, tp, lam, other, dparams,
-                               cont=si < n_ck - 1, defer=si > 0)
+                               cont=si < n_ck - 1, open=si > 0)
             if self.overlap:
                 freed[si % 2].record(main)
         sim.init_backward(lam, dparams)

@@ -129,29 +129,19 @@ bool adj2d_supported(int fields) {
 
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
                              const void* tape, const void* lam_in, void* lam_out, void* scratch,
-                             double* dparams, hipStream_t s, bool& ok, bool accumulate, bool sum) {
+                             double* dparams, hipStream_t s, bool& ok, const AdjOpts& o) {
   hipError_t e;
   switch (store) {
     case 0:
-      e = adj_dispatch<double, double>(P, fields, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, accumulate,
-                                       sum, ok);
+      e = adj_dispatch<double, double>(P, fields, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, o, ok);
       break;
     case 1:
     case 2:
     case 3:
-      return launch_adj_step2d_lowp(P, fields, store, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, ok,
-                                    accumulate, sum);
+      return launch_adj_step2d_lowp(P, fields, store, fin, hist, tape, lam_in, lam_out, scratch, dparams, s, ok, o);
     default: ok = false; return hipSuccess;
   }
   return e;
-}
-
-hipError_t launch_adj_param_sum(const DevParams& P, int store, void* scratch, double* dparams, hipStream_t s) {
-  const size_t elem = store == 0 ? sizeof(double) : sizeof(float);
-  const unsigned nb = (unsigned)((P.N + 255) / 256);
-  const double* part = (const double*)((const char*)scratch + part_offset(P.N, elem));
-  hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
-  return hipGetLastError();
 }
 
 hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,

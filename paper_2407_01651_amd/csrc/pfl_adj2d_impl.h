@@ -22,9 +22,14 @@
 //     adjoint of X = D_phi (x) v0 at each node; reverse X and the flow
 //     quantities behind it.
 //  R3 (nodes): the transposed stencils turn the stencil-input adjoints into
-//     moment adjoints, U = U(C, psi; k) is reversed, moments are mapped onto
-//     populations, and the adjoints of the time-stretched store's reads of
-//     neighbours are gathered.
+//     moment adjoints and U = U(C, psi; k) is reversed.
+// The moment adjoints reach every population of a set (the momentum ones
+// through c_i), and the time-stretched store's reads of a neighbour's old
+// value reach that neighbour's population: lambda^n is the populations part R1
+// wrote plus these terms.  Within a sweep over many steps they are not added
+// to lambda^n: R3 keeps them in the P_ planes (and A_OLD holds the old-value
+// reads), and the next step's R1 adds them where it reads lambda^n.  The
+// broadcast kernel adds them to lambda^n where a sweep ends.
 // A read through a wall ghost (mirror node) is credited to the mirror node
 // with the direction reflected on that axis, and for X with its sign flipped.
 #pragma once
@@ -45,7 +50,8 @@ enum : int {
   FW_PHI, FW_PSI, FW_C, FW_JX, FW_JY, FW_GX, FW_GY, FW_LAP,            // forward values for R2/R3
   PG_EPS, PG_K1,                                                       // per-node parameter gradients
   A_OLD0,                                                              // 5 planes: time-stretched store reads
-  A_NPLANES = A_OLD0 + 5
+  P_JX = A_OLD0 + 5, P_JY, P_PHI, P_PSI, P_C, P_H,                     // moment terms of lambda^n not yet added
+  A_NPLANES
 };
 
 __device__ __forceinline__ int total_pop_planes(const DevParams& P) {
@@ -54,20 +60,6 @@ __device__ __forceinline__ int total_pop_planes(const DevParams& P) {
   if (P.o_psi >= 0) return P.o_psi + P.q_sc;
   if (P.o_phi >= 0) return P.o_phi + P.q_phi;
   return P.o_ns + P.q_ns;
-}
-
-// Node-form index that receives the value a node at (x, y) stores for
-// direction i of lattice L: plane i at x + c_i, or plane opp(i) at (x, y)
-// when x + c_i lies beyond a wall.
-template <int Q>
-__device__ __forceinline__ long long push_target(const DevParams& P, int base, int x, int y, int i) {
-  using L = Lat<Q>;
-  int tx = x + L::c[i][0], ty = y + L::c[i][1];
-  bool wall = false;
-  if (tx < 0 || tx >= P.nx) { if (P.wall[0]) wall = true; else tx = tx < 0 ? tx + P.nx : tx - P.nx; }
-  if (ty < 0 || ty >= P.ny) { if (P.wall[1]) wall = true; else ty = ty < 0 ? ty + P.ny : ty - P.ny; }
-  if (wall) return (long long)(base + L::opp[i]) * P.N + (long long)y * P.nx + x;
-  return (long long)(base + i) * P.N + (long long)ty * P.nx + tx;
 }
 
 // Element `node` of a plane, addressed by a 32-bit byte offset from the
@@ -81,16 +73,26 @@ __device__ __forceinline__ T& at_node(T* plane, uint32_t node) {
   return *(T*)((char*)plane + node * (uint32_t)sizeof(T));
 }
 
-// lam at the push target of direction i of the set at plane `base`, for a
-// node at (x, y) with flat index idx; in a fast tile x + c_i lies inside the
-// domain, so the target is plane base + i at idx + c_i (32-bit offset).
-template <int Q, class T>
-__device__ __forceinline__ T lam_pushed(const DevParams& P, const T* lam, bool fast, uint32_t idx, int base,
-                                        int x, int y, int i) {
+// The node-form entry that receives the value a node at (x, y), flat index
+// idx, stores for direction i: population j of node `node`, with j = i at
+// x + c_i, or j = opp(i) at the node itself across a wall (`wall`).  In a fast
+// tile x + c_i lies inside the domain.
+struct PushTarget {
+  uint32_t node;
+  int j;
+  bool wall;
+};
+template <int Q>
+__device__ __forceinline__ PushTarget push_to(const DevParams& P, bool fast, uint32_t idx, int x, int y, int i) {
   using L = Lat<Q>;
-  if (fast)
-    return at_node(lam + (long long)(base + i) * P.N, idx + (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx));
-  return lam[push_target<Q>(P, base, x, y, i)];
+  PushTarget t{idx + (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx), i, false};
+  if (fast) return t;
+  int tx = x + L::c[i][0], ty = y + L::c[i][1];
+  if (tx < 0 || tx >= P.nx) { if (P.wall[0]) t.wall = true; else tx = tx < 0 ? tx + P.nx : tx - P.nx; }
+  if (ty < 0 || ty >= P.ny) { if (P.wall[1]) t.wall = true; else ty = ty < 0 ? ty + P.ny : ty - P.ny; }
+  if (t.wall) { t.node = idx; t.j = L::opp[i]; }
+  else t.node = (uint32_t)ty * (uint32_t)P.nx + (uint32_t)tx;
+  return t;
 }
 
 // The reader of a stencil entry: node z is read by the node r = z - c at
@@ -407,6 +409,13 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   // ---- reverse
   const int QT = total_pop_planes(P);
   auto lam_hist = [&](int hp) -> CT { return lam_in[(long long)(QT + hp) * N + idx]; };
+  // lambda^{n+1} at a push target of the set at plane `base` (without the
+  // moment terms the previous reverse step left open) and those terms (zero
+  // planes when lambda^{n+1} is complete)
+  auto lam_at = [&](int base, const PushTarget& t) -> CT {
+    return at_node(lam_in + (long long)(base + t.j) * N, t.node);
+  };
+  auto pend_at = [&](int plane, const PushTarget& t) -> CT { return at_node(S + (long long)plane * N, t.node); };
   auto out_pop = [&](int plane, CT v) { lam_out[(long long)plane * N + idx] = v; };
   // adjoints of node-level quantities
   CT a_phi = 0, a_psi = 0, a_C = 0, a_H = 0, a_jx = 0, a_jy = 0, a_U = 0;
@@ -433,7 +442,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
-      const CT ao = lam_pushed<QS>(P, lam_in, fast, (uint32_t)idx, P.o_th, x, y, i);
+      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      CT ao = lam_at(P.o_th, t);
+      ao += pend_at(P_H, t);
       a_jhx += ao * (1 - s1) * cx * CT(0.5);
       a_jhy += ao * (1 - s1) * cy * CT(0.5);
       a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
@@ -475,7 +486,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
-      const CT ao = lam_pushed<QS>(P, lam_in, fast, (uint32_t)idx, P.o_c, x, y, i);
+      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      CT ao = lam_at(P.o_c, t);
+      ao += pend_at(P_C, t);
       a_C += ao * w;
       a_Bx += ao * 3 * w * cx;
       a_By += ao * 3 * w * cy;
@@ -545,7 +558,16 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                           (P.wall[1] && (y + dy < 0 || y + dy >= P.ny));
       const CT old = across ? fps[LS::opp[i]]
                             : Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx) + CT(P.ref_psi[i]);
-      const CT ao = lam_pushed<QS>(P, lam_in, fast, (uint32_t)idx, P.o_psi, x, y, i);
+      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      CT ao = lam_at(P.o_psi, t);
+      {
+        // the previous step's old-value read of this population is the
+        // node's own A_OLD entry (rewritten below by this step)
+        const CT old_prev = S[(long long)(A_OLD0 + i) * N + idx];
+        CT v = pend_at(P_PSI, t);
+        if (!t.wall) v += old_prev;
+        ao += v;
+      }
       const CT a_fstar = ao * inv_an;
       const CT a_oldi = -ao * (1 - an) * inv_an;
       a_an += ao * old * inv_an;
@@ -594,7 +616,9 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QP; ++i) {
       const CT cx = LP::c[i][0], cy = LP::c[i][1];
-      const CT ao = lam_pushed<QP>(P, lam_in, fast, (uint32_t)idx, P.o_phi, x, y, i);
+      const PushTarget t = push_to<QP>(P, fast, (uint32_t)idx, x, y, i);
+      CT ao = lam_at(P.o_phi, t);
+      ao += pend_at(P_PHI, t);
       a_feq[i] = ao;
       a_jfx += ao * (1 - s1) * cx * ifn; a_jfy += ao * (1 - s1) * cy * ifn;
       a_G[i] = ao * CT(0.5);
@@ -646,7 +670,16 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QN; ++i) {
       const CT cx = LN::c[i][0], cy = LN::c[i][1];
-      ao_[i] = lam_pushed<QN>(P, lam_in, fast, (uint32_t)idx, P.o_ns, x, y, i);
+      const PushTarget t = push_to<QN>(P, fast, (uint32_t)idx, x, y, i);
+      ao_[i] = lam_at(P.o_ns, t);
+      {
+        // c_j . a_j at the target, c_j = -c_i across a wall
+        CT v = CT(0);
+        if (LN::c[i][0] != 0) v += cx * pend_at(P_JX, t);
+        if (LN::c[i][1] != 0) v += cy * pend_at(P_JY, t);
+        if (t.wall) v = -v;
+        ao_[i] += v;
+      }
       a_r += ao_[i] * CT(0.25) * ((cx * cx - cy * cy) * m1 + (cx * cy) * m2);
       a_m1 += ao_[i] * r * CT(0.25) * (cx * cx - cy * cy);
       a_m2 += ao_[i] * r * CT(0.25) * (cx * cy);
@@ -930,10 +963,11 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __
 }
 
 // ------------------------------------------------------------------- R3
+// Writes the moment terms of lambda^n to the P_ planes and the per-block
+// parameter partials.
 template <int FIELDS, int QP, class CT>
-__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, const CT* __restrict__ S_in,
-                                                           CT* __restrict__ lam_out, double* __restrict__ part,
-                                                           int accumulate) {
+__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT* __restrict__ S,
+                                                           double* __restrict__ part, int accumulate) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   using LN = Lat<9>;
@@ -944,7 +978,7 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
   const long long N = P.N;
   const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
   const KP<CT>& K = kp<CT>(P);
-  auto pl = [&](int k) -> const CT* { return S_in + (long long)k * N; };
+  auto pl = [&](int k) -> const CT* { return S + (long long)k * N; };
   // transposed isotropic stencils (gradient 3 sum w c f, Laplacian 6 sum w (f - f0))
   CT a_phi = at_node(pl(AM_PHI), n) - CT(6.0 * (1.0 - LN::w[0])) * at_node(pl(AS_LAP), n);
   CT a_psi = at_node(pl(AM_PSI), n), a_U = at_node(pl(AM_U), n);
@@ -989,17 +1023,53 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
     }
   }
   if (!live) return;
-  auto add = [&](int plane, CT v) { at_node(lam_out + (long long)plane * N, n) += v; };
+  auto put = [&](int plane, CT v) { at_node(S + (long long)plane * N, n) = v; };
+  if constexpr (NS) { put(P_JX, at_node(pl(AM_JX), n)); put(P_JY, at_node(pl(AM_JY), n)); }
+  if constexpr (PHI) put(P_PHI, a_phi);
+  if constexpr (PSI) put(P_PSI, a_psi);
+  if constexpr (CC) put(P_C, a_C);
+  if constexpr (TH) put(P_H, at_node(pl(AM_H), n));
+}
+
+// Zeroes the planes of open moment terms (P_ and A_OLD): lambda^{n+1} is
+// complete.
+template <class CT>
+__global__ __launch_bounds__(256) void adj_clear_pending_kernel(CT* __restrict__ S, long long N) {
+  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n0 >= N) return;
+#pragma unroll
+  for (int k = A_OLD0; k < A_NPLANES; ++k) S[(long long)k * N + n0] = CT(0);
+}
+
+// ------------------------------------------------------------ broadcast
+// Adds the moment terms R3 left in the P_ planes (and the old-value reads in
+// A_OLD) to the populations of lambda^n: where a sweep ends.
+template <int FIELDS, int QP, class CT>
+__global__ __launch_bounds__(256) void adj_broadcast_kernel(const DevParams P, const CT* __restrict__ S,
+                                                            CT* __restrict__ lam) {
+  constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
+  constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
+  using LN = Lat<9>;
+  using LS = Lat<5>;
+  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n0 >= P.N) return;
+  const uint32_t n = (uint32_t)n0;
+  const long long N = P.N;
+  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
+  auto pl = [&](int k) -> const CT* { return S + (long long)k * N; };
+  auto add = [&](int plane, CT v) { at_node(lam + (long long)plane * N, n) += v; };
   if constexpr (NS) {
-    const CT ajx = at_node(pl(AM_JX), n), ajy = at_node(pl(AM_JY), n);
+    const CT ajx = at_node(pl(P_JX), n), ajy = at_node(pl(P_JY), n);
 #pragma unroll
     for (int i = 0; i < 9; ++i) add(P.o_ns + i, CT(LN::c[i][0]) * ajx + CT(LN::c[i][1]) * ajy);
   }
   if constexpr (PHI) {
+    const CT a_phi = at_node(pl(P_PHI), n);
 #pragma unroll
     for (int i = 0; i < QP; ++i) add(P.o_phi + i, a_phi);
   }
   if constexpr (PSI) {
+    const CT a_psi = at_node(pl(P_PSI), n);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       CT v = a_psi;
@@ -1014,11 +1084,12 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, co
     }
   }
   if constexpr (CC) {
+    const CT a_C = at_node(pl(P_C), n);
 #pragma unroll
     for (int i = 0; i < 5; ++i) add(P.o_c + i, a_C);
   }
   if constexpr (TH) {
-    const CT aH = at_node(pl(AM_H), n);
+    const CT aH = at_node(pl(P_H), n);
 #pragma unroll
     for (int i = 0; i < 5; ++i) add(P.o_th + i, aH);
   }
@@ -1052,7 +1123,7 @@ inline size_t part_offset(long long N, size_t elem) {
 template <int FIELDS, int QP, class ST, class HT>
 hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, const void* tape_v,
                       const void* lam_in_v, void* lam_out_v, void* scratch, double* dparams, hipStream_t s,
-                      bool accumulate, bool sum) {
+                      const AdjOpts& o) {
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
@@ -1064,22 +1135,33 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
   RT* S = (RT*)scratch;
   double* part = (double*)((char*)scratch + part_offset(N, sizeof(RT)));
   const RT* tape = (const RT*)tape_v;
-  if (tape)
-    hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true>), dim3(tiles), dim3(NT), 0, s, P,
-                       (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
-  else
-    hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false>), dim3(tiles), dim3(NT), 0, s, P,
-                       (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if constexpr ((FIELDS & F_NS) && (FIELDS & F_PHI)) {
-    hipLaunchKernelGGL((adj_flow_kernel<RT>), dim3(nb), dim3(256), 0, s, P, S);
+  hipError_t e = hipSuccess;
+  if (o.step) {
+    if (!o.pend_in) {
+      hipLaunchKernelGGL((adj_clear_pending_kernel<RT>), dim3(nb), dim3(256), 0, s, S, N);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (tape)
+      hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true>), dim3(tiles), dim3(NT), 0, s, P,
+                         (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
+    else
+      hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false>), dim3(tiles), dim3(NT), 0, s, P,
+                         (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if constexpr ((FIELDS & F_NS) && (FIELDS & F_PHI)) {
+      hipLaunchKernelGGL((adj_flow_kernel<RT>), dim3(nb), dim3(256), 0, s, P, S);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, S, part,
+                       o.accumulate ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, (const RT*)S, lam_out,
-                     part, accumulate ? 1 : 0);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (!sum) return hipSuccess;
+  if (!o.pend_out) {
+    hipLaunchKernelGGL((adj_broadcast_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, (const RT*)S,
+                       lam_out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (!o.sum) return hipSuccess;
   hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
   return hipGetLastError();
 }
@@ -1087,13 +1169,13 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
 template <class ST, class HT>
 hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const void* hist, const void* tape,
                         const void* lam_in, void* lam_out, void* S, double* dparams, hipStream_t s,
-                        bool accumulate, bool sum, bool& ok) {
+                        const AdjOpts& o, bool& ok) {
   ok = true;
   const bool q9 = P.q_phi == 9;
 #define PFL_ADJ(F)                                                                               \
   case F:                                                                                        \
-    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, accumulate, sum) \
-              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, accumulate, sum);
+    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, o) \
+              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, o);
   switch (fields) {
     PFL_ADJ(F_NS | F_PHI | F_PSI | F_C | F_TH)
     PFL_ADJ(F_PSI | F_C)

@@ -138,7 +138,7 @@ struct pfl_ctx {
   int cur;               // 0: state in pops_a, 1: in pops_b
   bool inited;
   int64_t steps;
-  bool partials_open;    // the last adjoint call was a sweep that left its parameter partials unsummed
+  bool sweep_open;       // the last adjoint call was a sweep left open (partials and moment terms)
   std::vector<double> cs, seeds, bubbles;   // host copies kept alive for async uploads
 };
 
@@ -179,7 +179,7 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   c->s = (hipStream_t)hip_stream;
   c->cur = 0;
   c->inited = false;
-  c->partials_open = false;
+  c->sweep_open = false;
   c->steps = 0;
   const Layout& L = c->L;
   DevParams& d = c->d;
@@ -495,7 +495,7 @@ int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dpa
   if (adj_in == adj_out) return fail(PFL_E_INVALID_ARG, "adj_in and adj_out must differ");
   const void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   bool ok = true;
-  c->partials_open = false;
+  c->sweep_open = false;
   hipError_t e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, fin, c->b.hist, nullptr, adj_in, adj_out,
                                    c->b.adj, dparams, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
@@ -514,7 +514,7 @@ static int backward_image(pfl_ctx* c, const void* raw_state, int64_t step_count,
   DevParams d = c->d;
   d.first = first ? 1 : 0;
   d.step_ctr = (uint32_t)step_count;
-  c->partials_open = false;
+  c->sweep_open = false;
   bool ok = true;
   hipError_t e = launch_adj_step2d(d, (int)c->p.fields, c->p.store, raw_state,
                                    (const char*)raw_state + c->L.pops_bytes, tape, adj_in, adj_out,
@@ -543,12 +543,12 @@ int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* co
   if (!adj || !adj_tmp || !dparams || (n > 0 && !raw_states)) return fail(PFL_E_INVALID_ARG, "null argument");
   if (adj == adj_tmp) return fail(PFL_E_INVALID_ARG, "adj and adj_tmp must differ");
   if (n < 0 || step0 < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
-  if (flags & ~(PFL_SWEEP_CONTINUE | PFL_SWEEP_DEFER_SUM)) return fail(PFL_E_INVALID_ARG, "unknown sweep flags");
+  if (flags & ~(PFL_SWEEP_CONTINUE | PFL_SWEEP_OPEN)) return fail(PFL_E_INVALID_ARG, "unknown sweep flags");
   const bool cont = (flags & PFL_SWEEP_CONTINUE) != 0;
-  const bool defer = (flags & PFL_SWEEP_DEFER_SUM) != 0;
-  if (cont && !c->partials_open)
-    return fail(PFL_E_STATE, "PFL_SWEEP_CONTINUE without open partials (the last adjoint call on this context "
-                             "was not a sweep with PFL_SWEEP_DEFER_SUM)");
+  const bool open = (flags & PFL_SWEEP_OPEN) != 0;
+  if (cont && !c->sweep_open)
+    return fail(PFL_E_STATE, "PFL_SWEEP_CONTINUE without an open sweep (the last adjoint call on this context "
+                             "was not a sweep with PFL_SWEEP_OPEN)");
   for (int64_t k = 0; k < n; ++k)
     if (!raw_states[k] || (tapes && !tapes[k])) return fail(PFL_E_INVALID_ARG, "null image or tape in the sweep");
   const void* in = adj;
@@ -559,27 +559,32 @@ int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* co
     DevParams d = c->d;
     d.first = first0 && k == 0 ? 1 : 0;
     d.step_ctr = (uint32_t)(step0 + k);
-    const bool acc = cont || k < n - 1;
-    const bool sum = !defer && k == 0;
+    AdjOpts o;
+    o.accumulate = o.pend_in = cont || k < n - 1;
+    o.sum = !open && k == 0;
+    o.pend_out = open || k > 0;
     e = launch_adj_step2d(d, (int)c->p.fields, c->p.store, raw_states[k],
                           (const char*)raw_states[k] + c->L.pops_bytes, tapes ? tapes[k] : nullptr, in, out,
-                          c->b.adj, dparams, c->s, ok, acc, sum);
+                          c->b.adj, dparams, c->s, ok, o);
     const void* t = in;
     in = out;
     out = (void*)t;
   }
   if (!ok) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
-  if (n == 0 && cont && !defer) {
-    e = launch_adj_param_sum(c->d, c->p.store, c->b.adj, dparams, c->s);
-    if (e != hipSuccess) return hip_fail(e, "parameter sum");
+  if (n == 0 && cont && !open) {   // close the open sweep: moment terms into adj, partials into dparams
+    AdjOpts o;
+    o.step = false;
+    e = launch_adj_step2d(c->d, (int)c->p.fields, c->p.store, nullptr, nullptr, nullptr, adj, adj, c->b.adj,
+                          dparams, c->s, ok, o);
+    if (e != hipSuccess) return hip_fail(e, "closing the sweep");
   }
   if (in != adj) {   // odd n: the result is in adj_tmp
     const size_t bytes = c->L.state_bytes / sizeof(double) * (c->p.store == 0 ? sizeof(double) : sizeof(float));
     e = hipMemcpyAsync(adj, in, bytes, hipMemcpyDeviceToDevice, c->s);
     if (e != hipSuccess) return hip_fail(e, "adjoint copy");
   }
-  c->partials_open = defer && (n > 0 || cont);
+  c->sweep_open = open && (n > 0 || cont);
   g_err.clear();
   return PFL_OK;
 }
@@ -588,7 +593,7 @@ int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams) {
   int rc = adj_check(c);
   if (rc) return rc;
   if (!adj0 || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
-  c->partials_open = false;    // the initial-state adjoint reuses the scratch
+  c->sweep_open = false;    // the initial-state adjoint reuses the scratch
   hipError_t e = launch_adj_init2d(c->d, (int)c->p.fields, c->p.store, adj0, c->b.adj, dparams, c->s);
   if (e != hipSuccess) return hip_fail(e, "initial-state adjoint kernels");
   g_err.clear();

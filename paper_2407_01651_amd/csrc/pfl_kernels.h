@@ -32,19 +32,25 @@ inline hipError_t launch_step(const DevParams& P, int fields, int store, const v
 // (P.tape), or null to redo the stencils.
 size_t adj_scratch_bytes(long long N, int store);
 bool adj2d_supported(int fields);
-// accumulate: add the parameter partials to those of the previous steps of a
-// sweep; sum: add the partials to dparams after this step.
+// How one reverse step fits into a sweep over many.
+struct AdjOpts {
+  bool accumulate = false;  // add the parameter partials to those of the previous steps
+  bool sum = true;          // add the partials to dparams after this step
+  bool pend_in = false;     // lam_in lacks the moment terms the previous step left in the scratch
+  bool pend_out = false;    // leave this step's moment terms in the scratch instead of adding them
+  bool step = true;         // false: no step; add the open moment terms to lam_out (unless pend_out)
+                            // and the partials to dparams (if sum)
+};
 hipError_t launch_adj_step2d(const DevParams& P, int fields, int store, const void* fin, const void* hist,
                              const void* tape, const void* lam_in, void* lam_out, void* scratch,
-                             double* dparams, hipStream_t s, bool& ok, bool accumulate = false, bool sum = true);
+                             double* dparams, hipStream_t s, bool& ok, const AdjOpts& o = AdjOpts());
 hipError_t launch_adj_init2d(const DevParams& P, int fields, int store, const void* lam0, void* scratch,
                              double* dparams, hipStream_t s);
-// Adds the per-block parameter partials left by the last step to dparams.
-hipError_t launch_adj_param_sum(const DevParams& P, int store, void* scratch, double* dparams, hipStream_t s);
+
 // The FP32-compute part of launch_adj_step2d (stores 1-3).
 hipError_t launch_adj_step2d_lowp(const DevParams& P, int fields, int store, const void* fin, const void* hist,
                                   const void* tape, const void* lam_in, void* lam_out, void* scratch,
-                                  double* dparams, hipStream_t s, bool& ok, bool accumulate, bool sum);
+                                  double* dparams, hipStream_t s, bool& ok, const AdjOpts& o);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
 // planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium
