@@ -22,7 +22,9 @@ Paper:
     relations (Appendix B); Lambda = M^-1 S M;
   * half-way bounce-back walls (Sec. 3);
   * symmetry planes treated with the symmetric scheme for the distribution
-    functions (Sec. 3, boundary paragraph).
+    functions (Sec. 3, boundary paragraph);
+  * far-field Dirichlet values psi = psi_l, C = 1, theta = -Omega on chosen
+    sides (Sec. 3.4 thermosolutal validation, Sec. 4 set-up).
 Readings (the paper defers the CAC, solute and NS schemes and the
 fluid-solid force to other works):
   * NS: pressure-based incompressible scheme, p recovered from the moving
@@ -55,6 +57,16 @@ fluid-solid force to other works):
     reversed (specular reflection).  Stencil ghosts are mirror images:
     scalars even, and each component of D_phi (x) v0 takes one factor -1
     per index along the plane's normal.
+  * Far-field sides lie half-way between nodes.  The paper names no scheme
+    for Dirichlet values of the scalar sets: the half-way anti-bounce-back
+    is taken, the Dirichlet counterpart of its no-flux bounce-back: a
+    population of psi, C or theta leaving across the side comes back as
+    -f*_i + 2 w_i zeta_b (for psi before the time stretch, whose old value is
+    the slot's own).  For a linear set this is exactly the odd mirror image of
+    f - w zeta_b about the side.  NS and the bubble phase see a wall there.
+    Stencil ghosts of psi and U are odd about psi_l and U_b = 0 (the value of
+    U at C = 1, psi = psi_l); the other ghosts are the wall's.
+    theta_b = theta0, the initial undercooling -Omega.
   * The double-well factor (phi_l - phi)(phi - phi_g) of the sharpening flux
     and the factor (phi_l - phi) of the vacuum flux are clamped at 0 outside
     [phi_g, phi_l].
@@ -142,6 +154,9 @@ class OracleParams:
     # non-periodic axes: True = symmetry planes on both sides, "lo" / "hi" = on
     # the low (coordinate -1/2) or high (n - 1/2) side only, a wall on the other
     symmetric: tuple = (False, False, False)
+    # non-periodic axes: far-field Dirichlet sides, True (both), "lo", "hi" or
+    # False; a side is a symmetry plane, a far-field side or a wall
+    farfield: tuple = (False, False, False)
 
     @classmethod
     def from_workload(cls, w):
@@ -156,7 +171,8 @@ class OracleParams:
                    beta_inter=w["beta_inter"], g=w["g"], delta_n2=w["delta_n2"],
                    seeds=[dict(s) for s in w["seeds"]],
                    bubbles=[dict(b) for b in w["bubbles"]],
-                   symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]))
+                   symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]),
+                   farfield=tuple(w.get("farfield", (False, False, False))[:dim]))
 
     # --- derived constants -------------------------------------------------
     @property
@@ -218,6 +234,10 @@ class OracleSim:
             raise ValueError("solute/heat need the solid order parameter")
         if P.isothermal and P.bubbles and "c" in P.fields and "phi" in P.fields:
             raise ValueError("isothermal runs with bubbles are unsupported (F(U) -> 0 in gas)")
+        for a in range(P.dim):
+            for lo in (True, False):
+                if not P.periodic[a] and self.sym(a, lo) and self.far(a, lo):
+                    raise ValueError("a side is a symmetry plane or a far-field side, not both")
         self.grid = tuple(reversed(P.shape))          # tensor shape: [z][y][x]
         self.n = 0
         self.first = True
@@ -254,11 +274,23 @@ class OracleSim:
             return not lo
         return bool(v)
 
-    def nb(self, f, e, anti=False):
+    def far(self, a, lo):
+        """Whether the low (lo) or high boundary of axis a is a far-field side."""
+        if self.p.periodic[a]:
+            return False
+        v = self.p.farfield[a]
+        if v == "lo":
+            return lo
+        if v == "hi":
+            return not lo
+        return bool(v)
+
+    def nb(self, f, e, anti=False, dval=None):
         """Field value at x + e; walls and symmetry planes mirror ghost nodes.
         anti: f is the tensor D_phi (x) v0 (leading two axes its components),
         negated at wall ghosts and given the parity of its components at
-        symmetry-plane ghosts."""
+        symmetry-plane ghosts.  dval: far-field value of the scalar f; its
+        ghosts across a far-field side are 2 dval - f(mirror)."""
         out = f
         for a, ea in enumerate(e):
             ea = int(ea)
@@ -274,6 +306,12 @@ class OracleSim:
                 idx = torch.where(idx < 0, -1 - idx, idx)
                 idx = torch.where(idx >= n, 2 * n - 1 - idx, idx)
                 out = torch.index_select(out, dim, idx)
+                if dval is not None and not anti:
+                    raw = torch.arange(n) + ea
+                    far_g = ((raw < 0) & self.far(a, True)) | ((raw >= n) & self.far(a, False))
+                    if bool(far_g.any()):
+                        shp = [n if k == dim else 1 for k in range(f.dim())]
+                        out = torch.where(far_g.view(shp), 2.0 * dval - out, out)
                 if anti:
                     # walls: every component odd; symmetry planes: component
                     # (i, j) odd when exactly one of i, j is a
@@ -291,12 +329,13 @@ class OracleSim:
                             out[i, j] = out[i, j] * sg
         return out
 
-    def grad(self, f):
-        """Isotropic gradient (1/cs2) sum_i w_i c_i f(x + c_i)."""
+    def grad(self, f, dval=None):
+        """Isotropic gradient (1/cs2) sum_i w_i c_i f(x + c_i); dval: the
+        far-field value of f (ghost rule of nb)."""
         L = self.L_st
         out = torch.zeros((self.d,) + f.shape, dtype=DT)
         for i in range(1, L.Q):
-            fi = self.nb(f, L.c[i])
+            fi = self.nb(f, L.c[i], dval=dval)
             for a in range(self.d):
                 if L.c[i, a] != 0:
                     out[a] = out[a] + L.w[i] * L.c[i, a] * fi
@@ -332,13 +371,16 @@ class OracleSim:
                 return j
         raise ValueError("velocity set not closed under reflection")
 
-    def stream(self, fs, L):
+    def stream(self, fs, L, dval=None):
         """out_i(y) = fs_i(y - c_i).  Across a wall, out_i(y) = fs_opp(i)(y);
         across a symmetry plane on axis a (and no wall), the source is the
-        mirror node and the population the one with c_a reversed."""
+        mirror node and the population the one with c_a reversed.  Across a
+        far-field side: -fs_opp(i)(y) + 2 w_i dval for a scalar set with
+        far-field value dval, a wall for the others (dval None)."""
         out = torch.empty_like(fs)
         for i in range(L.Q):
             wall = torch.zeros(self.grid, dtype=torch.bool)
+            farm = torch.zeros(self.grid, dtype=torch.bool)
             crossed = []                          # symmetry planes crossed: (axis, mask)
             for a in range(self.d):
                 ca = int(L.c[i, a])
@@ -355,6 +397,8 @@ class OracleSim:
                     crossed.append((a, m))
                 else:
                     wall = wall | m
+                    if dval is not None and self.far(a, ca > 0):
+                        farm = farm | m
             # every combination of crossed symmetry planes: reflect c on those
             # axes, take the source with the other components streamed
             res = torch.zeros(self.grid, dtype=DT)
@@ -376,6 +420,10 @@ class OracleSim:
                 res = torch.where(m & ~done, src, res)
                 done = done | m
             out[i] = torch.where(wall, fs[L.opp[i]], res)
+            if dval is not None:
+                # the scalar sets' velocities are axis-aligned: a population
+                # crosses one side at most
+                out[i] = torch.where(farm, -fs[L.opp[i]] + 2.0 * L.w[i] * dval, out[i])
         return out
 
     # ------------------------------------------------------------- collision
@@ -548,8 +596,8 @@ class OracleSim:
         # S3 stencils
         gphi = self.grad(phi)
         lphi = self.lap(phi)
-        gpsi = self.grad(psi)
-        gU = self.grad(U)
+        gpsi = self.grad(psi, dval=PSI_L)
+        gU = self.grad(U, dval=0.0)
         # S4 unit normals, regularised where the gradient vanishes:
         # n = g / sqrt(|g|^2 + delta_n2)
         nphi = gphi / torch.sqrt((gphi * gphi).sum(0) + P.delta_n2)
@@ -673,7 +721,7 @@ class OracleSim:
             an = q["a_s"] * q["a_s"]
             if self.an_override is not None:
                 an = torch.ones_like(an) * self.an_override
-            fs_str = self.stream(fstar, L)
+            fs_str = self.stream(fstar, L, dval=PSI_L)
             an_str = self.stream(an.unsqueeze(0).expand(L.Q, *an.shape).clone(), L)
             new["f_psi"] = (fs_str - (1 - an_str) * f) / an_str
         # solute: conserved C in the zeroth moment, diffusivity D q / m with
@@ -697,7 +745,7 @@ class OracleSim:
             s1 = 1.0 / (P.D * q["qf"] / (m * L.cs2) + 0.5)
             rates = {r: s1 for r in L.flux_rows}
             fstar = f - self.mrt(L, f, feq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
-            new["f_c"] = self.stream(fstar, L)
+            new["f_c"] = self.stream(fstar, L, dval=1.0)
             new["B_prev"] = B
         else:
             new["B_prev"] = st["B_prev"]
@@ -714,7 +762,7 @@ class OracleSim:
             s1 = 1.0 / (P.alpha / L.cs2 + 0.5)
             rates = {r: s1 for r in L.flux_rows}
             gstar = g - self.mrt(L, g, geq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
-            new["g_th"] = self.stream(gstar, L)
+            new["g_th"] = self.stream(gstar, L, dval=P.theta0)
         # history
         new["psi_prev"] = q["psi"]
         new["S_prev"] = q["S_psi"]
