@@ -97,10 +97,16 @@ typedef struct {
   int nx, ny, nz;           /* nz = 1 in 2D */
   int wall[3];              /* per axis: 0 periodic, 1 half-way bounce-back walls, 2 symmetry
                                planes on both sides, 3 a symmetry plane on the low side (at
-                               coordinate -1/2) and a wall on the high side, 4 the reverse.
+                               coordinate -1/2) and a wall on the high side, 4 the reverse,
+                               5 a wall on the low side and a far-field side on the high side,
+                               6 a symmetry plane on the low side and a far-field side on the
+                               high side (5 and 6: 2D only).
                                Symmetry planes lie half-way; a population crossing one comes
                                back as its mirror image, stencil ghosts are mirror images
-                               (Sec. 3). */
+                               (Sec. 3).  A far-field side (half-way) holds psi = psi_l,
+                               C = 1 and theta = theta0 (Sec. 3.4, Sec. 4): populations of
+                               those sets crossing it come back by anti-bounce-back,
+                               -f*_i + 2 w_i value; NS and phi see a wall there. */
   uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
   int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
   int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */

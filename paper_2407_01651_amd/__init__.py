@@ -121,9 +121,16 @@ def make_params(w, store=None, rounding=None):
     p.dim = w["dim"]
     p.nx, p.ny, p.nz = w["nx"], w["ny"], (w["nz"] if w["dim"] == 3 else 1)
     for a in range(3):
-        # symmetric[a]: True (both sides), "lo", "hi" or False
+        # symmetric[a]: True (both sides), "lo", "hi" or False; farfield[a]:
+        # "hi" (far-field high side, with a wall or a symmetry plane low) or False
         sym = w.get("symmetric", (False, False, False))
-        code = {"lo": 3, "hi": 4}.get(sym[a], 2) if sym[a] else 1
+        far = w.get("farfield", (False, False, False))
+        if far[a]:
+            if far[a] != "hi" or sym[a] not in (False, "lo"):
+                raise ValueError("far-field sides: the high side, with a wall or a symmetry plane on the low side")
+            code = 6 if sym[a] == "lo" else 5
+        else:
+            code = {"lo": 3, "hi": 4}.get(sym[a], 2) if sym[a] else 1
         p.wall[a] = 0 if (a >= w["dim"] or w["periodic"][a]) else code
     bits = 0
     for f in w["fields"]:

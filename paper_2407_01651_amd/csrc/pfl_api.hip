@@ -49,7 +49,10 @@ int validate(const pfl_params* p) {
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31))
     return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
   for (int a = 0; a < 3; ++a)
-    if (p->wall[a] < 0 || p->wall[a] > 4) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 4");
+    if (p->wall[a] < 0 || p->wall[a] > 6) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 6");
+  if (p->dim == 3)
+    for (int a = 0; a < 3; ++a)
+      if (p->wall[a] >= 5) return fail(PFL_E_UNSUPPORTED, "far-field sides are built for 2D");
   const uint32_t f = p->fields;
   if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
   if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");
@@ -189,6 +192,8 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
     d.wall[a] = p->wall[a] != 0;
     if (p->wall[a] == 2 || p->wall[a] == 3) d.sym |= 1 << a;
     if (p->wall[a] == 2 || p->wall[a] == 4) d.sym |= 1 << (3 + a);
+    if (p->wall[a] == 6) d.sym |= 1 << a;
+    if (p->wall[a] == 5 || p->wall[a] == 6) d.far |= 1 << (3 + a);
   }
   d.N = L.N;
   d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;

@@ -138,6 +138,7 @@ struct DevParams {
   int nx, ny, nz, dim;
   int wall[3];                 // non-periodic axis: a wall or a symmetry plane
   int sym;                     // symmetry planes: bit a = low side of axis a, bit 3 + a = high side
+  int far;                     // far-field Dirichlet sides, bits as sym
   long long N;                 // nodes
   // population plane offsets (-1 = set inactive)
   int o_ns, o_phi, o_psi, o_c, o_th;
@@ -170,6 +171,10 @@ struct DevParams {
 // Whether the low (lo) or high boundary of axis a is a symmetry plane.
 __device__ __forceinline__ bool sym_side(const DevParams& P, int a, bool lo) {
   return (P.sym >> (lo ? a : 3 + a)) & 1;
+}
+// Whether the low (lo) or high boundary of axis a is a far-field side.
+__device__ __forceinline__ bool far_side(const DevParams& P, int a, bool lo) {
+  return (P.far >> (lo ? a : 3 + a)) & 1;
 }
 
 // --------------------------------------------------------- storage types

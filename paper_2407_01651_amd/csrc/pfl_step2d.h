@@ -13,8 +13,8 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 // addressing: periodic wrap, half-way bounce-back at a wall (the node's own
 // opposite population), or specular reflection at a symmetry plane (the
 // mirror node's population with the normal component reversed) on each axis.
-// SYM: the grid has symmetry planes (a separate instantiation, so that grids
-// without them carry none of the reflection code).
+// SYM: the grid has symmetry planes or far-field sides (a separate
+// instantiation, so that grids without them carry none of that code).
 template <int Q, class ST, class CT, bool SYM = false>
 __device__ __forceinline__ void pull_general(const typename Store<ST>::raw* __restrict__ base,
                                              const DevParams& P, int x, int y, CT f[Q]) {

@@ -18,6 +18,10 @@
 // Tiles whose pulls stay inside the domain take a fast path: every load and
 // store is a scalar base plus a 32-bit byte offset, one integer add per
 // access.  Tiles on the domain edge use the general wrap/bounce addressing.
+// A far-field side is a wall for NS and phi; the populations of psi, C and
+// theta that leave across it are stored by anti-bounce-back, -f*_i +
+// 2 w_i value, so the pull reads them back as from a wall; the stencil
+// ghosts of psi and U there are odd about psi_l and U = 0.
 #pragma once
 #include "pfl_kernels.h"
 #include "pfl_step2d.h"
@@ -204,6 +208,16 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
       if (inner && gx0 < P.nx && gy0 < P.ny) continue;   // filled in A1
       halo_node(rx, ry, map_coord(gx0, P.nx, P.wall[0]), map_coord(gy0, P.ny, P.wall[1]), false);
+      if (SYM && P.far) {
+        // ghost across an odd number of far-field sides: psi and U odd about
+        // psi_l = -1 and U = 0 (each crossing mirrors once)
+        const bool fx = gx0 < 0 ? far_side(P, 0, true) : gx0 >= P.nx && far_side(P, 0, false);
+        const bool fy = gy0 < 0 ? far_side(P, 1, true) : gy0 >= P.ny && far_side(P, 1, false);
+        if (fx != fy) {
+          s_psi[ry][rx] = CT(-2) - s_psi[ry][rx];
+          s_U[ry][rx] = -s_U[ry][rx];
+        }
+      }
     }
   }
   __syncthreads();
@@ -256,6 +270,14 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 
   // ---- phase C: the rest of the step at the own node
   const int ry = ly + R, rx = lx + R;
+  // direction i of the 5-velocity sets leaves across a far-field side
+  auto far_out = [&](int i) -> bool {
+    if constexpr (!SYM) return false;
+    if (fast || !P.far) return false;
+    const int dx = LS::c[i][0], dy = LS::c[i][1];
+    return (dx > 0 && x == P.nx - 1 && far_side(P, 0, false)) || (dx < 0 && x == 0 && far_side(P, 0, true)) ||
+           (dy > 0 && y == P.ny - 1 && far_side(P, 1, false)) || (dy < 0 && y == 0 && far_side(P, 1, true));
+  };
   const CT h = (psi + CT(1)) * CT(0.5);
   const CT q = clamp01((CT(1) - psi) * CT(0.5));
   CT theta = TH ? (H + h) : K.theta0;
@@ -506,8 +528,10 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
       const CT w = CT(LS::w[i]);
       const CT G = w * (cx * gNx + cy * gNy);
-      const CT fstar = w * dpsi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
-                       CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
+      CT fstar = w * dpsi + (CT(1) - rate_psi) * (cx * jx_ + cy * jy_) * CT(0.5) + w * S_psi +
+                 CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
+      // anti-bounce-back to psi_l = -1 (stored less the rest value r_psi)
+      if (far_out(i)) fstar = CT(2) * w * (CT(-1) - r_psi) - fstar;
       // f_i(x + c_i) before this step; across a wall it is the own f_opp(i)
       const int dx = LS::c[i][0], dy = LS::c[i][1];
       const bool across = !fast && ((P.wall[0] && (x + dx < 0 || x + dx >= P.nx)) ||
@@ -545,7 +569,8 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       const CT w = CT(LS::w[i]);
       const CT feq = w * dC + w * (cx * Bx + cy * By) * CT(3);
       const CT G = w * (cx * dBx + cy * dBy) * CT(3);
-      const CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      CT fs = feq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      if (far_out(i)) fs = CT(2) * w * (CT(1) - r_C) - fs;      // anti-bounce-back to C = 1
       st(P.o_c, i, fs);
     }
     hst(P.h_B, Bx);
@@ -572,7 +597,8 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       CT geq = w * dtheta + w * (cx * Hvx + cy * Hvy) * CT(3);
       if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
       const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
-      const CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      if (far_out(i)) gs = CT(2) * w * (K.theta0 - r_H) - gs;   // anti-bounce-back to theta0
       st(P.o_th, i, gs);
     }
     hst(P.h_Hv, Hvx);
@@ -591,7 +617,7 @@ hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void
                            double* mout, int mode, hipStream_t s) {
   dim3 grid(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   using raw = typename Store<ST>::raw;
-  if (P.sym)
+  if (P.sym || P.far)
     hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, true>), grid, dim3(NT), 0, s, P,
                        (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   else

@@ -97,7 +97,8 @@ def test_bad_rounding_mode_is_rejected():
 
 def test_boundary_flags():
     """wall[a]: 0 periodic, 1 walls, 2 symmetry planes, 3 / 4 a symmetry plane
-    on the low / high side only; anything else is rejected."""
+    on the low / high side only, 5 / 6 a far-field high side with a wall /
+    symmetry plane low (2D); anything else is rejected."""
     import paper_2407_01651_amd as pfl
     w = workloads.get("coupled2d_128")
     w["symmetric"] = (True, True, False)
@@ -110,6 +111,20 @@ def test_boundary_flags():
     p = pfl.make_params(w, "f64", "nearest")
     assert list(p.wall) == [3, 4, 0]
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
-    p.wall[0] = 5
+    w["symmetric"] = ("lo", False, False)
+    w["farfield"] = ("hi", "hi", False)
+    p = pfl.make_params(w, "f64", "nearest")
+    assert list(p.wall) == [6, 5, 0]
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.wall[0] = 7
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
     assert "boundary" in pfl._lib.pfl_last_error().decode()
+    w["farfield"] = ("lo", False, False)
+    with pytest.raises(ValueError):
+        pfl.make_params(w, "f64", "nearest")
+    w3 = workloads.get("coupled3d_256")
+    w3["periodic"] = (True, False, True)
+    w3["farfield"] = (False, "hi", False)
+    p = pfl.make_params(w3, "f16", "stochastic")
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -2
+    assert "2D" in pfl._lib.pfl_last_error().decode()

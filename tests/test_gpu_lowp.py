@@ -41,6 +41,9 @@ CASES = {
     "small_45x37": (lambda: workloads.small(nx=45, ny=37, seed=3), 300),
     "alloy_40x33": (lambda: workloads.small(nx=40, ny=33, seed=5, fields=("psi", "c"),
                                             periodic=(True, True, True)), 300),
+    # symmetry in x, far-field top (the set-up of Sec. 4)
+    "farfield_44x36": (lambda: dict(workloads.small(nx=44, ny=36, seed=7, periodic=(False, False, True)),
+                                    symmetric=(True, False, False), farfield=(False, "hi", False)), 300),
 }
 
 _oracle_cache = {}

@@ -58,6 +58,22 @@ CASES = [
                                symmetric=("lo", "hi", False)), 30),
     ("psi_theta_corner_40x34", dict(nx=40, ny=34, seed=22, fields=("psi", "theta"), periodic=(False, False, True),
                                     symmetric=("lo", "lo", False)), 40),
+    # far-field sides (Sec. 3.4, Sec. 4): anti-bounce-back to psi_l, C = 1, theta0
+    ("all_yfar_28x22", dict(nx=28, ny=22, seed=24, periodic=(True, False, True), farfield=(False, "hi", False),
+                            g=2e-4, rho_g=0.01), 30),
+    # the set-up of Sec. 4: symmetry in x, no-flux bottom, far-field top
+    ("all_xsym_yfar_30x26", dict(nx=30, ny=26, seed=25, periodic=(False, False, True),
+                                 symmetric=(True, False, False), farfield=(False, "hi", False)), 30),
+    # the thermosolutal validation corner: symmetry low, far field high on both axes
+    ("alloy_theta_far_corner_34x30", dict(nx=34, ny=30, seed=26, fields=("psi", "c", "theta"),
+                                          periodic=(False, False, True), symmetric=("lo", "lo", False),
+                                          farfield=("hi", "hi", False),
+                                          seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=6.0, angle=0.0)]), 40),
+    # a seed at the far-field side: psi and U ghosts and the psi anti-bounce-back away from psi_l
+    ("alloy_far_seed_26x22", dict(nx=26, ny=22, seed=27, fields=("psi", "c"), Le=math.inf, U0=0.0,
+                                  theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, False, True),
+                                  farfield=(False, "hi", False),
+                                  seeds=[dict(x=13.0, y=19.5, z=0.0, r=4.0, angle=0.3)]), 40),
 ]
 
 
