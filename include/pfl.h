@@ -100,7 +100,7 @@ typedef struct {
                                coordinate -1/2) and a wall on the high side, 4 the reverse,
                                5 a wall on the low side and a far-field side on the high side,
                                6 a symmetry plane on the low side and a far-field side on the
-                               high side (5 and 6: 2D only).
+                               high side.
                                Symmetry planes lie half-way; a population crossing one comes
                                back as its mirror image, stencil ghosts are mirror images
                                (Sec. 3).  A far-field side (half-way) holds psi = psi_l,

@@ -50,9 +50,6 @@ int validate(const pfl_params* p) {
     return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
   for (int a = 0; a < 3; ++a)
     if (p->wall[a] < 0 || p->wall[a] > 6) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 6");
-  if (p->dim == 3)
-    for (int a = 0; a < 3; ++a)
-      if (p->wall[a] >= 5) return fail(PFL_E_UNSUPPORTED, "far-field sides are built for 2D");
   const uint32_t f = p->fields;
   if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
   if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");

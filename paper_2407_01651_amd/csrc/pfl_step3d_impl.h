@@ -363,6 +363,17 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
           if (LN::c[i][2]) hj[2] += CT(LN::c[i][2]) * f[i];
         }
       }
+      if (SYM && !fast && P.far) {
+        // ghost across an odd number of far-field sides: psi and U odd about
+        // psi_l = -1 and U = 0 (each crossing mirrors once)
+        const bool fx = gx0 < 0 ? far_side(P, 0, true) : gx0 >= P.nx && far_side(P, 0, false);
+        const bool fy = gy0 < 0 ? far_side(P, 1, true) : gy0 >= P.ny && far_side(P, 1, false);
+        const bool fz = gz0 < 0 ? far_side(P, 2, true) : gz0 >= P.nz && far_side(P, 2, false);
+        if (fx ^ fy ^ fz) {
+          hpsi = CT(-2) - hpsi;
+          hU = -hU;
+        }
+      }
       const int q1 = B1::at(tz + 1, ty + 1, tx + 1);
       s_psi[q1] = hpsi;
       if constexpr (CC) s_U[q1] = hU;
@@ -420,6 +431,22 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
   if (!own) return;
 
   // ---- phase C: the rest of the step at the own node
+  // direction i of the 7-velocity sets leaves across a far-field side, whose
+  // populations come back by anti-bounce-back, -f*_i + 2 w_i value
+  auto far_out = [&](int i) -> bool {
+    if constexpr (!SYM) return false;
+    if (fast || !P.far) return false;
+    const int n3[3] = {P.nx, P.ny, P.nz};
+    const int xyz[3] = {x, y, z};
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ca = LS::c[i][a];
+      if (ca > 0 && xyz[a] == n3[a] - 1 && far_side(P, a, false)) out = true;
+      if (ca < 0 && xyz[a] == 0 && far_side(P, a, true)) out = true;
+    }
+    return out;
+  };
   const CT h = (psi + CT(1)) * CT(0.5);
   const CT q = clamp01((CT(1) - psi) * CT(0.5));
   CT theta = TH ? (H + h) : K.theta0;
@@ -690,8 +717,10 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]), cz = CT(LS::c[i][2]);
       const CT w = CT(LS::w[i]);
       const CT G = w * (cx * gN[0] + cy * gN[1] + cz * gN[2]);
-      const CT fstar = w * dpsi + (CT(1) - rate_psi) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
-                       w * S_psi + CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
+      CT fstar = w * dpsi + (CT(1) - rate_psi) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
+                 w * S_psi + CT(0.5) * w * (S_psi - Sprev) + (CT(1) - CT(0.5) * rate_psi) * G;
+      // anti-bounce-back to psi_l = -1 (stored less the rest value r_psi)
+      if (far_out(i)) fstar = CT(2) * w * (CT(-1) - r_psi) - fstar;
       bool across = false;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -733,8 +762,9 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT w = CT(LS::w[i]);
       const CT feq = w * dC + w * (cx * B[0] + cy * B[1] + cz * B[2]) * CT(1.0 / LS::cs2);
       const CT G = w * (cx * dB[0] + cy * dB[1] + cz * dB[2]) * CT(1.0 / LS::cs2);
-      st(P.o_c, i, feq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
-                        (CT(1) - CT(0.5) * s1) * G);
+      CT fs = feq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      if (far_out(i)) fs = CT(2) * w * (CT(1) - r_C) - fs;      // anti-bounce-back to C = 1
+      st(P.o_c, i, fs);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) hst(P.h_B + a, B[a]);
@@ -762,8 +792,9 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       CT geq = w * dtheta + w * (cx * Hv[0] + cy * Hv[1] + cz * Hv[2]) * CT(1.0 / LS::cs2);
       if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
       const CT G = w * (cx * dHv[0] + cy * dHv[1] + cz * dHv[2]) * CT(1.0 / LS::cs2);
-      st(P.o_th, i, geq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) +
-                         (CT(1) - CT(0.5) * s1) * G);
+      CT gs = geq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
+      if (far_out(i)) gs = CT(2) * w * (K.theta0 - r_H) - gs;   // anti-bounce-back to theta0
+      st(P.o_th, i, gs);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) hst(P.h_Hv + a, Hv[a]);
@@ -782,7 +813,7 @@ hipError_t launch_step3d_t(const DevParams& P, const void* fin, void* fout, void
   const long long tiles = (long long)((P.nx + T::TX - 1) / T::TX) * ((P.ny + T::TY - 1) / T::TY) *
                           ((P.nz + T::TZ - 1) / T::TZ);
   using raw = typename Store<ST>::raw;
-  if (P.sym)
+  if (P.sym || P.far)
     hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, true>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
                        (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   else

@@ -98,7 +98,7 @@ def test_bad_rounding_mode_is_rejected():
 def test_boundary_flags():
     """wall[a]: 0 periodic, 1 walls, 2 symmetry planes, 3 / 4 a symmetry plane
     on the low / high side only, 5 / 6 a far-field high side with a wall /
-    symmetry plane low (2D); anything else is rejected."""
+    symmetry plane low; anything else is rejected."""
     import paper_2407_01651_amd as pfl
     w = workloads.get("coupled2d_128")
     w["symmetric"] = (True, True, False)
@@ -124,7 +124,8 @@ def test_boundary_flags():
         pfl.make_params(w, "f64", "nearest")
     w3 = workloads.get("coupled3d_256")
     w3["periodic"] = (True, False, True)
+    w3["symmetric"] = (False, "lo", False)
     w3["farfield"] = (False, "hi", False)
     p = pfl.make_params(w3, "f16", "stochastic")
-    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -2
-    assert "2D" in pfl._lib.pfl_last_error().decode()
+    assert list(p.wall) == [0, 6, 0]
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0

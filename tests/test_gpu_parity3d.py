@@ -42,6 +42,17 @@ CASES = [
                                  symmetric=(True, True, True)), 15),
     ("all_corner_xylo_zhi_16x12x9", dict(nx=16, ny=12, nz=9, seed=33, periodic=(False, False, False),
                                          symmetric=("lo", "lo", "hi")), 15),
+    # far-field sides: anti-bounce-back to psi_l, C = 1, theta0
+    ("all_yfar_16x14x8", dict(nx=16, ny=14, nz=8, seed=34, periodic=(True, False, True),
+                              farfield=(False, "hi", False), g=2e-4, rho_g=0.01), 20),
+    ("alloy_theta_far_corner_18x16x10", dict(nx=18, ny=16, nz=10, seed=35, fields=("psi", "c", "theta"),
+                                             periodic=(False, False, False), symmetric=("lo", "lo", "lo"),
+                                             farfield=("hi", "hi", "hi"),
+                                             seeds=[dict(x=-0.5, y=-0.5, z=-0.5, r=5.0, angle=0.0)]), 20),
+    ("alloy_far_seed_14x12x8", dict(nx=14, ny=12, nz=8, seed=36, fields=("psi", "c"), Le=math.inf, U0=0.0,
+                                    theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, False, True),
+                                    farfield=(False, "hi", False),
+                                    seeds=[dict(x=7.0, y=9.5, z=4.0, r=3.5, angle=0.3)]), 25),
 ]
 
 

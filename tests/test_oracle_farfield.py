@@ -43,15 +43,16 @@ def _mirror_y(t, val):
     return torch.cat([t, 2.0 * val - torch.flip(t, dims=[-2])], dim=-2)
 
 
-@pytest.mark.parametrize("low", ["wall", "sym"])
-def test_farfield_solute_and_heat_are_the_odd_mirror_of_the_doubled_run(low):
-    nx, ny, steps = 6, 10, 40
-    w = workloads.small(nx=nx, ny=ny, seed=5, fields=("psi", "c", "theta"))
+@pytest.mark.parametrize("dim,low", [(2, "wall"), (2, "sym"), (3, "sym")])
+def test_farfield_solute_and_heat_are_the_odd_mirror_of_the_doubled_run(dim, low):
+    nx, ny, nz, steps = 6, 10, 4, 40
+    w = workloads.small(dim=dim, nx=nx, ny=ny, nz=nz if dim == 3 else 1, seed=5, fields=("psi", "c", "theta"))
     w.update(periodic=(True, False, True), seeds=[], bubbles=[])
     theta_b = w["theta0"]
     g = torch.Generator().manual_seed(11)
-    C0 = 1.0 + 0.2 * torch.rand((ny, nx), generator=g, dtype=DT)
-    T0 = theta_b + 0.2 * torch.rand((ny, nx), generator=g, dtype=DT)
+    shape = (ny, nx) if dim == 2 else (nz, ny, nx)
+    C0 = 1.0 + 0.2 * torch.rand(shape, generator=g, dtype=DT)
+    T0 = theta_b + 0.2 * torch.rand(shape, generator=g, dtype=DT)
     wh = dict(w)
     wh.update(symmetric=(False, "lo" if low == "sym" else False, False), farfield=(False, "hi", False))
     wf = dict(w)
@@ -62,7 +63,7 @@ def test_farfield_solute_and_heat_are_the_odd_mirror_of_the_doubled_run(low):
     half.step(steps)
     full.step(steps)
     for key in ("f_c", "g_th", "f_psi"):
-        ref = full.state[key][:, :ny]
+        ref = full.state[key][..., :ny, :]
         err = float((half.state[key] - ref).abs().max()) / float(ref.abs().max())
         assert err < 1e-12, (low, key, err)
     # the fields moved: the check is not of a state at rest
