@@ -8,6 +8,17 @@
 namespace pfl {
 
 constexpr int TX = 32, TY = 8, NT = TX * TY;
+// The step kernel's tile, one node per thread: 32 x 8 nodes when the flow and
+// the bubble phase are both active (two halo rings), 32 x 4 otherwise.  The
+// shapes measured fastest: with one ring 32 x 4 against 32 x 2, 32 x 8,
+// 32 x 16, 64 x 4 and 16 x 8; with two rings 32 x 8 against 32 x 4, 32 x 16
+// and 16 x 16.
+template <int FIELDS>
+struct StepTile {
+  static constexpr int X = 32;
+  static constexpr int Y = ((FIELDS & F_NS) && (FIELDS & F_PHI)) ? 8 : 4;
+  static constexpr int N = X * Y;
+};
 
 // Pull the pre-collision population deviations of one set at node (x, y), general
 // addressing: periodic wrap, half-way bounce-back at a wall (the node's own
@@ -59,18 +70,18 @@ __device__ __forceinline__ void pull(bool fast, const typename Store<ST>::raw* _
   }
 }
 
-// Halo position k (0 <= k < RX*RY - TX*TY) of an R-ring tile: the R top
+// Halo position k (0 <= k < RX*RY - TW*TH) of an R-ring TW x TH tile: the R top
 // rows, the R bottom rows, then the side columns.
-template <int R>
+template <int R, int TW, int TH>
 __device__ __forceinline__ void halo_pos(int k, int& rx, int& ry) {
-  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  constexpr int RX = TW + 2 * R, RY = TH + 2 * R;
   if (k < R * RX) { ry = k / RX; rx = k % RX; return; }
   k -= R * RX;
   if (k < R * RX) { ry = RY - R + k / RX; rx = k % RX; return; }
   k -= R * RX;
   ry = R + k / (2 * R);
   const int c = k % (2 * R);
-  rx = c < R ? c : TX + c;
+  rx = c < R ? c : TW + c;
 }
 
 // Isotropic D2Q9 gradient and Laplacian from an LDS array.

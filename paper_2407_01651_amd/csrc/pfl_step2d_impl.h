@@ -2,8 +2,8 @@
 // one step (pull streaming, moments, isotropic stencils, anisotropy,
 // forces, MRT collisions in closed form, time-stretched AAC store, history).
 //
-// Work decomposition: a 256-thread workgroup owns a TX x TY tile of nodes,
-// one node per thread.  Moments of the tile plus a halo of R rings
+// Work decomposition: a workgroup owns a tile of nodes (StepTile: 32 x 8 with
+// two halo rings, 32 x 4 with one), one node per thread.  Moments of the tile plus a halo of R rings
 // (R = 2 when the flow and bubble phase are both active, else 1) are staged
 // in LDS; the flow phase then evaluates D_phi (x) v0 on the tile plus one
 // ring (LDS), and each thread finishes its own node from registers and LDS.
@@ -29,7 +29,7 @@
 namespace pfl {
 
 template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM>
-__global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
+__global__ __launch_bounds__(StepTile<FIELDS>::N) void step2d_kernel(const DevParams P,
                                                     const typename Store<ST>::raw* __restrict__ fin,
                                                     typename Store<ST>::raw* __restrict__ fout,
                                                     HT* hist, double* __restrict__ mout,
@@ -38,7 +38,8 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   constexpr bool FLOWX = NS && PHI;          // mass-flux force needs D_phi (x) v0 on ring 1
   constexpr int R = FLOWX ? 2 : 1;
-  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  constexpr int STX = StepTile<FIELDS>::X, STY = StepTile<FIELDS>::Y, SNT = StepTile<FIELDS>::N;
+  constexpr int RX = STX + 2 * R, RY = STY + 2 * R;
   constexpr int QN = 9, QS = 5;
   using LN = Lat<9>;
   using LS = Lat<5>;
@@ -58,18 +59,18 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
   __shared__ CT s_X[FLOWX ? 4 : 1][FLOWX ? RY : 1][FLOWX ? RX : 1];
 
   const int tid = threadIdx.x;
-  const int lx = tid % TX, ly = tid / TX;
-  const int gtx = (P.nx + TX - 1) / TX;
-  const int lt = logical_tile(blockIdx.x, gtx * ((P.ny + TY - 1) / TY));
+  const int lx = tid % STX, ly = tid / STX;
+  const int gtx = (P.nx + STX - 1) / STX;
+  const int lt = logical_tile(blockIdx.x, gtx * ((P.ny + STY - 1) / STY));
   const int tile_x = lt % gtx, tile_y = lt / gtx;
-  const int bx0 = tile_x * TX, by0 = tile_y * TY;
+  const int bx0 = tile_x * STX, by0 = tile_y * STY;
   const int x = bx0 + lx, y = by0 + ly;
   const bool own = (x < P.nx) && (y < P.ny);
   const long long N = P.N;
   const long long idx = (long long)y * P.nx + x;
   // every pull of the tile and its halo stays inside the domain
-  const bool fast = P.fast && bx0 >= R + 1 && by0 >= R + 1 && bx0 + TX + R + 1 <= P.nx &&
-                    by0 + TY + R + 1 <= P.ny;
+  const bool fast = P.fast && bx0 >= R + 1 && by0 >= R + 1 && bx0 + STX + R + 1 <= P.nx &&
+                    by0 + STY + R + 1 <= P.ny;
 
   const raw* fin_ns = fin + (long long)(NS ? P.o_ns : 0) * N;
   const raw* fin_phi = fin + (long long)(PHI ? P.o_phi : 0) * N;
@@ -194,18 +195,18 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
     if constexpr (NS) { s_jx[ry][rx] = hjx; s_jy[ry][rx] = hjy; }
   };
   if (fast) {
-    constexpr int NH = RX * RY - TX * TY;
-    for (int k = tid; k < NH; k += NT) {
+    constexpr int NH = RX * RY - STX * STY;
+    for (int k = tid; k < NH; k += SNT) {
       int rx, ry;
-      halo_pos<R>(k, rx, ry);
+      halo_pos<R, STX, STY>(k, rx, ry);
       halo_node(rx, ry, bx0 + rx - R, by0 + ry - R, true);
     }
   } else {
-    for (int k = tid; k < RX * RY; k += NT) {
+    for (int k = tid; k < RX * RY; k += SNT) {
       const int rx = k % RX, ry = k / RX;
       const int tx = rx - R, ty = ry - R;
       const int gx0 = bx0 + tx, gy0 = by0 + ty;
-      const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
+      const bool inner = tx >= 0 && tx < STX && ty >= 0 && ty < STY;
       if (inner && gx0 < P.nx && gy0 < P.ny) continue;   // filled in A1
       halo_node(rx, ry, map_coord(gx0, P.nx, P.wall[0]), map_coord(gy0, P.ny, P.wall[1]), false);
       if (SYM && P.far) {
@@ -232,12 +233,12 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
       s_X[2][ly + R][lx + R] = fo.Dy * fo.v0x;
       s_X[3][ly + R][lx + R] = fo.Dy * fo.v0y;
     }
-    constexpr int AX = TX + 2, AY = TY + 2;
-    for (int k = tid; k < AX * AY; k += NT) {
+    constexpr int AX = STX + 2, AY = STY + 2;
+    for (int k = tid; k < AX * AY; k += SNT) {
       const int rx = k % AX + R - 1, ry = k / AX + R - 1;
       const int tx = rx - R, ty = ry - R;
       const int gx0 = bx0 + tx, gy0 = by0 + ty;
-      const bool inner = tx >= 0 && tx < TX && ty >= 0 && ty < TY;
+      const bool inner = tx >= 0 && tx < STX && ty >= 0 && ty < STY;
       if (inner && gx0 < P.nx && gy0 < P.ny) continue;
       // ghosts across a wall take minus the value at their mirror node;
       // across a symmetry plane the mirror image: the off-diagonal
@@ -615,13 +616,14 @@ __global__ __launch_bounds__(NT) void step2d_kernel(const DevParams P,
 template <int FIELDS, int QP, class ST, class HT, class CT>
 hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void* hist,
                            double* mout, int mode, hipStream_t s) {
-  dim3 grid(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
+  constexpr int STX = StepTile<FIELDS>::X, STY = StepTile<FIELDS>::Y, SNT = StepTile<FIELDS>::N;
+  dim3 grid(((P.nx + STX - 1) / STX) * ((P.ny + STY - 1) / STY));
   using raw = typename Store<ST>::raw;
   if (P.sym || P.far)
-    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, true>), grid, dim3(NT), 0, s, P,
+    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, true>), grid, dim3(SNT), 0, s, P,
                        (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   else
-    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, false>), grid, dim3(NT), 0, s, P,
+    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, false>), grid, dim3(SNT), 0, s, P,
                        (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
   return hipGetLastError();
 }
