@@ -24,7 +24,13 @@ Paper:
   * symmetry planes treated with the symmetric scheme for the distribution
     functions (Sec. 3, boundary paragraph);
   * far-field Dirichlet values psi = psi_l, C = 1, theta = -Omega on chosen
-    sides (Sec. 3.4 thermosolutal validation, Sec. 4 set-up).
+    sides (Sec. 3.4 thermosolutal validation, Sec. 4 set-up);
+  * the heat LB with variable properties (Appendix B heat model, Sec. 2.2
+    property rule): H = c_p theta - c_p^s h(psi), H = sum g / rho,
+    g_eq,0 = rho H + (w_0 - 1) theta, g_eq,i = w_i theta + w_i c_i.rho H v/cs2,
+    auxiliary term from d(rho H v)/dt, k_T = (1/s_1 - 1/2) cs2, each of rho,
+    c_p, k_T interpolated linearly in phi between gas and liquid (solid =
+    liquid).
 Readings (the paper defers the CAC, solute and NS schemes and the
 fluid-solid force to other works):
   * NS: pressure-based incompressible scheme, p recovered from the moving
@@ -70,6 +76,12 @@ fluid-solid force to other works):
   * The double-well factor (phi_l - phi)(phi - phi_g) of the sharpening flux
     and the factor (phi_l - phi) of the vacuum flux are clamped at 0 outside
     [phi_g, phi_l].
+  * Heat properties are scaled by their liquid (= solid) values, so that
+    rho c_p = c_p^s = 1 and k_T = alpha in the liquid; the gas ratios
+    th_rho_g, th_cp_g, th_k_g default to 1 (matched properties, the form the
+    paper's solidification references use).  The heat equation's density
+    ratio is a parameter of its own, so that matched thermal properties stay
+    available beside the flow's density ratio.
   * Buoyancy F_b = -(rho - rho_l) g y^: the liquid's hydrostatic head is
     carried by the pressure, which leaves the incompressible dynamics of
     Sec. 2.2 unchanged and starts no pressure transient.
@@ -157,6 +169,10 @@ class OracleParams:
     # non-periodic axes: far-field Dirichlet sides, True (both), "lo", "hi" or
     # False; a side is a symmetry plane, a far-field side or a wall
     farfield: tuple = (False, False, False)
+    # gas-to-liquid ratios of rho, c_p and k_T in the heat equation
+    th_rho_g: float = 1.0
+    th_cp_g: float = 1.0
+    th_k_g: float = 1.0
 
     @classmethod
     def from_workload(cls, w):
@@ -172,7 +188,9 @@ class OracleParams:
                    seeds=[dict(s) for s in w["seeds"]],
                    bubbles=[dict(b) for b in w["bubbles"]],
                    symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]),
-                   farfield=tuple(w.get("farfield", (False, False, False))[:dim]))
+                   farfield=tuple(w.get("farfield", (False, False, False))[:dim]),
+                   th_rho_g=w.get("th_rho_g", 1.0), th_cp_g=w.get("th_cp_g", 1.0),
+                   th_k_g=w.get("th_k_g", 1.0))
 
     # --- derived constants -------------------------------------------------
     @property
@@ -261,6 +279,14 @@ class OracleSim:
                 dd = torch.minimum(dd, n - dd)
             d2 = d2 + dd * dd
         return d2
+
+    def heat_props(self, phi):
+        """rho, c_p, k_T / alpha of the heat equation at phi: zeta_g + (zeta_l -
+        zeta_g) (phi - phi_g) / (phi_l - phi_g), liquid values 1."""
+        P = self.p
+        t = (phi - PHI_G) / (PHI_L - PHI_G)
+        return (P.th_rho_g + (1 - P.th_rho_g) * t, P.th_cp_g + (1 - P.th_cp_g) * t,
+                P.th_k_g + (1 - P.th_k_g) * t)
 
     # ------------------------------------------------------------ stencil access
     def sym(self, a, lo):
@@ -509,9 +535,10 @@ class OracleSim:
             st["f_c"] = ws * C
         if "theta" in P.fields:
             theta = torch.full(self.grid, 1.0, dtype=DT) * P.theta0
-            H = theta - h
+            rh, cp, _ = self.heat_props(phi)
+            H = cp * theta - h
             gth = ws * theta
-            gth[0] = H + (Ls.w[0] - 1) * theta
+            gth[0] = rh * H + (Ls.w[0] - 1) * theta
             st["g_th"] = gth
         if "ns" in P.fields:
             st["f_ns"] = torch.zeros((Ln.Q,) + self.grid, dtype=DT)
@@ -548,8 +575,9 @@ class OracleSim:
             st["f_c"] = ws * C
         if "theta" in P.fields:
             theta = one * P.theta0 if theta is None else theta
+            rh, cp, _ = self.heat_props(phi)
             gth = ws * theta
-            gth[0] = (theta - h) + (Ls.w[0] - 1) * theta
+            gth[0] = rh * (cp * theta - h) + (Ls.w[0] - 1) * theta
             st["g_th"] = gth
         if "ns" in P.fields:
             vv = torch.zeros((self.d,) + self.grid, dtype=DT) if v is None else v
@@ -588,8 +616,10 @@ class OracleSim:
             C = None
             U = one * P.U0
         if "theta" in P.fields:
-            H = st["g_th"].sum(0)
-            theta = H + h
+            # H = c_p theta - c_p^s h = sum g / rho (c_p^s = 1)
+            rh, cp, _ = self.heat_props(phi)
+            H = st["g_th"].sum(0) / rh
+            theta = (H + h) / cp
         else:
             H = None
             theta = one * P.theta0
@@ -749,20 +779,23 @@ class OracleSim:
             new["B_prev"] = B
         else:
             new["B_prev"] = st["B_prev"]
-        # heat (Appendix B, rho c_p = c_p^s = 1)
-        Hv = (q["H"] * v) if q["H"] is not None else torch.zeros_like(v)
+        # heat (Appendix B), Hv = rho H v
         if "theta" in P.fields:
+            rh, _, kT = self.heat_props(q["phi"])
+            Hv = rh * q["H"] * v
             L = self.L_sc
             g = st["g_th"]
             w = self.wv(L, q["H"])
             geq = w * q["theta"] + w * self.cdot(L, Hv) / L.cs2
-            geq[0] = q["H"] + (L.w[0] - 1) * q["theta"]
+            geq[0] = rh * q["H"] + (L.w[0] - 1) * q["theta"]
             Hprev = Hv if first else st["Hv_prev"]
             G = w * self.cdot(L, Hv - Hprev) / L.cs2
-            s1 = 1.0 / (P.alpha / L.cs2 + 0.5)
+            s1 = 1.0 / (P.alpha * kT / L.cs2 + 0.5)
             rates = {r: s1 for r in L.flux_rows}
             gstar = g - self.mrt(L, g, geq, rates) + G - 0.5 * self.lam_apply(L, G, rates)
             new["g_th"] = self.stream(gstar, L, dval=P.theta0)
+        else:
+            Hv = torch.zeros_like(v)
         # history
         new["psi_prev"] = q["psi"]
         new["S_prev"] = q["S_psi"]
