@@ -115,6 +115,11 @@ typedef struct {
   double rho_l, rho_g, nu_l, nu_g, sigma, M_phi, xi, beta_inter, g;
   double delta_n2;          /* > 0: unit normals g / sqrt(|g|^2 + delta_n2); anisotropy
                                denominator (|g|^2 + delta_n2)^2 */
+  double th_rho_g, th_cp_g, th_k_g;
+                            /* > 0: gas-to-liquid ratios of rho, c_p and k_T in the heat
+                               equation (Appendix B heat model; each property linear in phi,
+                               solid = liquid, Sec. 2.2); 1, 1, 1 = matched properties.  The
+                               scheme is conditionally stable where rho c_p < 1. */
 } pfl_params;
 
 /* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */

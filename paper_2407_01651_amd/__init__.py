@@ -45,7 +45,7 @@ class Params(ct.Structure):
                 ("rounding", ct.c_int)] + \
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
-                                          "beta_inter", "g", "delta_n2")]
+                                          "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")]
 
 
 class Seed(ct.Structure):
@@ -142,6 +142,8 @@ def make_params(w, store=None, rounding=None):
     for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0", "rho_l", "rho_g",
               "nu_l", "nu_g", "sigma", "M_phi", "xi", "beta_inter", "g", "delta_n2"):
         setattr(p, n, float(w[n]))
+    for n in ("th_rho_g", "th_cp_g", "th_k_g"):
+        setattr(p, n, float(w.get(n, 1.0)))
     return p
 
 

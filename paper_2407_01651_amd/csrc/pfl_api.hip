@@ -75,6 +75,8 @@ int validate(const pfl_params* p) {
     return fail(PFL_E_INVALID_ARG, "sigma and beta_inter must be >= 0");
   if (!(p->delta_n2 > 0) || !std::isfinite(p->delta_n2))
     return fail(PFL_E_INVALID_ARG, "delta_n2 must be positive (regularisation of unit normals)");
+  for (double r : {p->th_rho_g, p->th_cp_g, p->th_k_g})
+    if (!(r > 0) || !std::isfinite(r)) return fail(PFL_E_INVALID_ARG, "heat property ratios must be positive");
   if (!std::isfinite(p->U0) || !std::isfinite(p->theta0) || !std::isfinite(p->eps4) || !std::isfinite(p->g))
     return fail(PFL_E_INVALID_ARG, "non-finite parameter");
   if (!(p->eps4 >= 0 && p->eps4 < 1.0 / 3)) return fail(PFL_E_INVALID_ARG, "eps4 must lie in [0, 1/3)");
@@ -216,6 +218,7 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   d.k_s = 6.0 * p->sigma / (d.W_phi * std::sqrt(0.5));
   d.M_phi = p->M_phi; d.beta_inter = p->beta_inter; d.g = p->g;
   d.delta_n2 = p->delta_n2;
+  d.th_rho_g = p->th_rho_g; d.th_cp_g = p->th_cp_g; d.th_k_g = p->th_k_g;
   d.s_phi = 1.0 / (p->M_phi / cs2_phi + 0.5);
   d.s_th = th ? 1.0 / (d.alpha / cs2_sc + 0.5) : 1.0;
   d.a_at = 1.0 / (2.0 * std::sqrt(2.0));
@@ -233,6 +236,9 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
       K.rho_l = (T)p->rho_l; K.rho_g = (T)p->rho_g; K.drho = (T)d.drho; K.mu_l = (T)d.mu_l;
       K.mu_g = (T)d.mu_g; K.g = (T)p->g; K.s_phi = (T)d.s_phi; K.s_th = (T)d.s_th;
       K.aW0 = (T)(d.a_at * p->W0);
+      K.th_rho_g = (T)p->th_rho_g; K.th_cp_g = (T)p->th_cp_g; K.th_k_g = (T)p->th_k_g;
+      K.alpha_cs = (T)(d.alpha / cs2_sc);
+      K.varheat = th && (p->th_rho_g != 1.0 || p->th_cp_g != 1.0 || p->th_k_g != 1.0);
     };
     fill(d.kd);
     fill(d.kf);
@@ -487,6 +493,7 @@ static int adj_check(pfl_ctx* c) {
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   for (int a = 0; a < 3; ++a)
     if (c->p.wall[a] >= 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for periodic axes and walls");
+  if (c->d.kd.varheat) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for matched heat properties");
   return PFL_OK;
 }
 

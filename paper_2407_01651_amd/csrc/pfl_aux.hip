@@ -148,7 +148,11 @@ __global__ __launch_bounds__(BT) void init_kernel(const DevParams P, int fields,
   if (fields & F_TH) {
     double f[QS];
     for (int i = 0; i < QS; ++i) f[i] = LS::w[i] * theta;
-    f[0] = (theta - h) + (LS::w[0] - 1.0) * theta;
+    // rest population rho H + (w_0 - 1) theta, H = c_p theta - h (rho, c_p
+    // linear in phi, liquid = solid = 1)
+    const double rh = P.th_rho_g + (1.0 - P.th_rho_g) * phi;
+    const double cp = P.th_cp_g + (1.0 - P.th_cp_g) * phi;
+    f[0] = rh * (cp * theta - h) + (LS::w[0] - 1.0) * theta;
     scatter_set<QS, ST>(P, pops + (long long)P.o_th * P.N, P.ref_th, x, y, z, f);
   }
   for (int hp = 0; hp < hist_planes; ++hp) hist[(long long)hp * P.N + n] = (HT)0;

@@ -127,6 +127,9 @@ struct KP {
   CT k1, inv_k1, U0, theta0, eps4, dn, d_psi, inv_tau0, D, lam, Mcinf, inv_Le, beta_inter;
   CT sharp, M_phi, Wphi2, k_s, rho_l, rho_g, drho, mu_l, mu_g, g, s_phi, s_th, aW0;
   CT C_ref;                     // bulk solute 1 + (1-k) U0 of the deviation storage
+  // heat properties (liquid = solid = 1): gas ratios of rho, c_p, k_T, alpha / cs2
+  CT th_rho_g, th_cp_g, th_k_g, alpha_cs;
+  int varheat;                  // a gas ratio differs from 1
 };
 
 // Planes of a 2D step tape (compute type, N nodes each): grad phi (x, y),
@@ -151,6 +154,7 @@ struct DevParams {
   double W0, tau0, d_psi, eps4, k, D, alpha, inv_Le, Mcinf, lam, U0, theta0;
   double rho_l, rho_g, drho, mu_l, mu_g, W_phi, sharp, k_s, M_phi, beta_inter, g;
   double delta_n2, s_phi, s_th, a_at;
+  double th_rho_g, th_cp_g, th_k_g;   // gas ratios of the heat properties
   double phi_tanh, psi_tanh;   // tanh arguments per unit distance of the initial profiles
   // device pointers inside the aux buffer
   const uint8_t* grain;        // nearest-seed id per node

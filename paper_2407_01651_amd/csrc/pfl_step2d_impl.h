@@ -281,7 +281,25 @@ __global__ __launch_bounds__(StepTile<FIELDS>::N) void step2d_kernel(const DevPa
   };
   const CT h = (psi + CT(1)) * CT(0.5);
   const CT q = clamp01((CT(1) - psi) * CT(0.5));
-  CT theta = TH ? (H + h) : K.theta0;
+  // temperature: H = c_p theta - c_p^s h with sum g = rho H; rho, c_p, k_T
+  // linear in phi between gas and liquid (liquid = solid = 1).  dtheta =
+  // theta - r_H, the deviation of the non-rest equilibria; s_th the heat
+  // relaxation rate from k_T.
+  CT theta = K.theta0, dtheta = CT(0), s_th = K.s_th;
+  if constexpr (TH) {
+    if (K.varheat) {
+      const CT rh = K.th_rho_g + (CT(1) - K.th_rho_g) * phi;
+      const CT cp = K.th_cp_g + (CT(1) - K.th_cp_g) * phi;
+      const CT kh = K.th_k_g + (CT(1) - K.th_k_g) * phi;
+      const CT rc = rh * cp;
+      dtheta = (dH + rh * h + r_H * (CT(1) - rc)) / rc;
+      theta = r_H + dtheta;
+      s_th = rcp(K.alpha_cs * kh + CT(0.5));
+    } else {
+      theta = H + h;
+      dtheta = dH + h;
+    }
+  }
 
   // gradients of psi and U
   CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
@@ -583,8 +601,7 @@ __global__ __launch_bounds__(StepTile<FIELDS>::N) void step2d_kernel(const DevPa
     const CT Hvx = H * vx, Hvy = H * vy;
     CT Hpx = Hvx, Hpy = Hvy;
     if (!first) { Hpx = h_Hv0; Hpy = h_Hv1; }
-    const CT s1 = K.s_th;
-    const CT dtheta = dH + h;
+    const CT s1 = s_th;
     CT jx_ = CT(0), jy_ = CT(0);
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jx_ += CT(LS::c[i][0]) * fth[i]; jy_ += CT(LS::c[i][1]) * fth[i]; }
@@ -594,9 +611,14 @@ __global__ __launch_bounds__(StepTile<FIELDS>::N) void step2d_kernel(const DevPa
     for (int i = 0; i < QS; ++i) {
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);
       const CT w = CT(LS::w[i]);
-      // equilibrium less r_i = w theta0 (dtheta = theta - r_H = dH + h)
+      // equilibrium less r_i = w theta0; H (the sum of g) is rho times the
+      // model's H, so the rest equilibrium rho H + (w - 1) theta is
+      // H + (w - 1) theta, less w theta0: dH + (w - 1) dtheta
       CT geq = w * dtheta + w * (cx * Hvx + cy * Hvy) * CT(3);
-      if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
+      if (i == 0) {
+        if constexpr (DEV) geq = K.varheat ? dH + (w - CT(1)) * dtheta : -h + w * dtheta;
+        else geq = H + (w - CT(1)) * theta;
+      }
       const CT G = w * (cx * dx_ + cy * dy_) * CT(3);
       CT gs = geq + (CT(1) - s1) * (cx * jx_ + cy * jy_) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
       if (far_out(i)) gs = CT(2) * w * (K.theta0 - r_H) - gs;   // anti-bounce-back to theta0

@@ -449,7 +449,25 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
   };
   const CT h = (psi + CT(1)) * CT(0.5);
   const CT q = clamp01((CT(1) - psi) * CT(0.5));
-  CT theta = TH ? (H + h) : K.theta0;
+  // temperature: H = c_p theta - c_p^s h with sum g = rho H; rho, c_p, k_T
+  // linear in phi between gas and liquid (liquid = solid = 1).  dtheta =
+  // theta - r_H, the deviation of the non-rest equilibria; s_th the heat
+  // relaxation rate from k_T.
+  CT theta = K.theta0, dtheta = CT(0), s_th = K.s_th;
+  if constexpr (TH) {
+    if (K.varheat) {
+      const CT rh = K.th_rho_g + (CT(1) - K.th_rho_g) * phi;
+      const CT cp = K.th_cp_g + (CT(1) - K.th_cp_g) * phi;
+      const CT kh = K.th_k_g + (CT(1) - K.th_k_g) * phi;
+      const CT rc = rh * cp;
+      dtheta = (dH + rh * h + r_H * (CT(1) - rc)) / rc;
+      theta = r_H + dtheta;
+      s_th = rcp(K.alpha_cs * kh + CT(0.5));
+    } else {
+      theta = H + h;
+      dtheta = dH + h;
+    }
+  }
   CT gp[3] = {CT(0), CT(0), CT(0)}, gU[3] = {CT(0), CT(0), CT(0)};
   if constexpr (PSI) grad19<CT, B1>(s_psi, lz + 1, ly + 1, lx + 1, gp);
   if constexpr (CC) grad19<CT, B1>(s_U, lz + 1, ly + 1, lx + 1, gU);
@@ -776,8 +794,7 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
     CT dHv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) dHv[a] = Hv[a] - (first ? Hv[a] : h_Hv[a]);
-    const CT s1 = K.s_th;
-    const CT dtheta = dH + h;
+    const CT s1 = s_th;
     CT jf[3] = {-Hv[0], -Hv[1], -Hv[2]};
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
@@ -790,7 +807,12 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]), cz = CT(LS::c[i][2]);
       const CT w = CT(LS::w[i]);
       CT geq = w * dtheta + w * (cx * Hv[0] + cy * Hv[1] + cz * Hv[2]) * CT(1.0 / LS::cs2);
-      if (i == 0) geq = DEV ? -h + w * dtheta : H + (w - CT(1)) * theta;
+      // H (the sum of g) is rho times the model's H: the rest equilibrium
+      // rho H + (w - 1) theta less w theta0 is dH + (w - 1) dtheta
+      if (i == 0) {
+        if constexpr (DEV) geq = K.varheat ? dH + (w - CT(1)) * dtheta : -h + w * dtheta;
+        else geq = H + (w - CT(1)) * theta;
+      }
       const CT G = w * (cx * dHv[0] + cy * dHv[1] + cz * dHv[2]) * CT(1.0 / LS::cs2);
       CT gs = geq + (CT(1) - s1) * (cx * jf[0] + cy * jf[1] + cz * jf[2]) * CT(0.5) + (CT(1) - CT(0.5) * s1) * G;
       if (far_out(i)) gs = CT(2) * w * (K.theta0 - r_H) - gs;   // anti-bounce-back to theta0

@@ -67,6 +67,8 @@ def test_sizes_of_the_coupled_workload():
     (dict(dim=3, nz=8, phi_q=9), -2),             # phi on 9 velocities in 3D
     (dict(phi_q=7), -1),
     (dict(delta_n2=0.0), -1),
+    (dict(th_cp_g=0.0), -1),                     # heat property ratios must be positive
+    (dict(th_k_g=-1.0), -1),
 ])
 def test_invalid_parameters_are_rejected(change, code):
     w = workloads.get("coupled2d_128")

@@ -44,6 +44,9 @@ CASES = {
     # symmetry in x, far-field top (the set-up of Sec. 4)
     "farfield_44x36": (lambda: dict(workloads.small(nx=44, ny=36, seed=7, periodic=(False, False, True)),
                                     symmetric=(True, False, False), farfield=(False, "hi", False)), 300),
+    # heat properties varying between gas and liquid
+    "varheat_40x34": (lambda: dict(workloads.small(nx=40, ny=34, seed=8), th_rho_g=0.7, th_cp_g=0.9,
+                                   th_k_g=0.5), 300),
 }
 
 _oracle_cache = {}

@@ -74,6 +74,12 @@ CASES = [
                                   theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, False, True),
                                   farfield=(False, "hi", False),
                                   seeds=[dict(x=13.0, y=19.5, z=0.0, r=4.0, angle=0.3)]), 40),
+    # heat properties varying between gas and liquid (Appendix B heat model, Sec. 2.2 rule)
+    ("all_varheat_30x24", dict(nx=30, ny=24, seed=28, g=2e-4, rho_g=0.01,
+                               th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 30),
+    ("noflow_varheat_far_28x26", dict(nx=28, ny=26, seed=29, fields=("phi", "psi", "c", "theta"),
+                                      periodic=(False, False, True), symmetric=(True, False, False),
+                                      farfield=(False, "hi", False), th_rho_g=0.7, th_cp_g=0.6, th_k_g=2.0), 40),
 ]
 
 

@@ -53,6 +53,8 @@ CASES = [
                                     theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, False, True),
                                     farfield=(False, "hi", False),
                                     seeds=[dict(x=7.0, y=9.5, z=4.0, r=3.5, angle=0.3)]), 25),
+    # heat properties varying between gas and liquid
+    ("all_varheat_16x14x10", dict(nx=16, ny=14, nz=10, seed=37, th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 20),
 ]
 
 
