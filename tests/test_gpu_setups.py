@@ -1,0 +1,64 @@
+"""The paper's boundary set-ups at full size on the GPU (FP64), checked by
+properties that hold at any size:
+
+* corner dendrites (Sec. 3.3 thermal, Sec. 3.4 thermosolutal with far-field
+  sides): the set-up is symmetric about the diagonal (corner seed with grain
+  angle 0, the same boundaries on x and y), so psi and theta stay symmetric
+  under x <-> y to rounding; the seed grows;
+* the Sec. 4 geometry (symmetry planes in x, no-flux bottom, far-field top,
+  two corner seeds, a bubble on the left plane): the run stays finite, the
+  bubble rises and keeps its volume, the seeds grow.
+"""
+import pytest
+import torch
+
+import workloads
+from parity_util import log
+from paper_2407_01651_amd.diagnostics import gas_stats, solid_fraction
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,steps", [("corner_thermal2d_256", 3000), ("corner_thermosolutal2d_512", 3000)])
+def test_corner_dendrite_stays_symmetric_about_the_diagonal(name, steps):
+    import paper_2407_01651_amd as pfl
+    w = workloads.get(name)
+    sim = pfl.Sim(w, store="f64")
+    sim.init_fields()
+    s0 = solid_fraction(sim.macros()["psi"])
+    sim.step(steps)
+    m = sim.macros()
+    r = sim.reduce()
+    assert r["nonfinite"] == 0
+    errs = {}
+    for k in ("psi", "theta"):
+        f = m[k].double().cpu()
+        errs[k] = float((f - f.t()).abs().max()) / float(f.abs().max())
+    s1 = solid_fraction(m["psi"])
+    log(f"[setups] {name} {steps} steps: transpose {errs}, solid {s0:.4g} -> {s1:.4g}")
+    assert max(errs.values()) < 1e-10, errs
+    assert s1 > 1.5 * s0
+    sim.close()
+
+
+def test_bubble_dendrites_geometry_runs():
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("bubble_dendrites2d_200x400")
+    sim = pfl.Sim(w, store="f64")
+    sim.init_fields()
+    m0 = sim.macros()
+    per = [False, False]
+    v0, b0 = gas_stats(m0["phi"].cpu(), per)
+    s0 = solid_fraction(m0["psi"])
+    sim.step(4000)
+    m = sim.macros()
+    assert sim.reduce()["nonfinite"] == 0
+    v1, b1 = gas_stats(m["phi"].cpu(), per)
+    s1 = solid_fraction(m["psi"])
+    log(f"[setups] bubble_dendrites: gas {v0:.1f} -> {v1:.1f}, centroid y {b0[0]['centroid'][1]:.2f} -> "
+        f"{b1[0]['centroid'][1]:.2f}, solid {s0:.4g} -> {s1:.4g}")
+    assert len(b1) == 1
+    assert abs(v1 / v0 - 1) < 0.02
+    assert b1[0]["centroid"][1] > b0[0]["centroid"][1] + 0.05
+    assert s1 > s0
+    sim.close()

@@ -228,6 +228,50 @@ def coupled3d_256(seed=5, store="f16", n=256):
     return c
 
 
+def corner_thermal2d_256():
+    """The thermal dendrite of a pure substance in the set-up of Sec. 3.3:
+    256 x 256, symmetry planes on the bottom and left sides and no-flux walls
+    on the others, a seed of radius 10 dx in the corner, undercooling 0.55,
+    eps4 0.05, Pe_D = 0.25 (Le = 1: the heat diffusivity alpha = W0^2 /
+    (Pe_D tau0)), dx = 0.4 W0, dt = 0.008 tau0; no solute (Mc_inf = 0)."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="corner_thermal2d_256", nx=256, ny=256, periodic=(False, False, True),
+             symmetric=("lo", "lo", False), fields=("psi", "theta"), tau0=125.0,
+             eps4=0.05, PeD=0.25, Le=1.0, Mcinf=0.0, U0=0.0, theta0=-0.55,
+             seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=10.0, angle=0.0)], bubbles=[], steps=20000)
+    return c
+
+
+def corner_thermosolutal2d_512():
+    """The thermosolutal dendrite in the set-up of Sec. 3.4, on a 512 x 512
+    grid: symmetry planes on the bottom and left sides, far-field values
+    psi_l, C = 1, theta = -Omega on the top and right sides, a corner seed,
+    Le = 1, k 0.15, eps4 0.02, Omega 0.55 (theta0 = -0.55, U0 = 0)."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="corner_thermosolutal2d_512", nx=512, ny=512, periodic=(False, False, True),
+             symmetric=("lo", "lo", False), farfield=("hi", "hi", False),
+             fields=("psi", "c", "theta"), eps4=0.02, Le=1.0, U0=0.0, theta0=-0.55,
+             seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=10.0, angle=0.0)], bubbles=[], steps=20000)
+    return c
+
+
+def bubble_dendrites2d_200x400():
+    """The geometry of the coupled runs of Sec. 4: 200 x 400, symmetry planes
+    on both x sides, a no-flux bottom and a far-field top, seeds of radius
+    10 dx at the two bottom corners and a bubble of diameter 40 centred on the
+    left symmetry plane at y = Ly / 5; k 0.15, eps4 0.02, Omega 0.55.  The
+    flow parameters are the coupled workloads' (density ratio 100, gravity
+    -y), not the paper's dimensionless groups."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="bubble_dendrites2d_200x400", nx=200, ny=400, periodic=(False, False, True),
+             symmetric=(True, False, False), farfield=(False, "hi", False), eps4=0.02,
+             rho_g=0.01, g=1e-5, U0=0.0, theta0=-0.55,
+             seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=10.0, angle=0.0),
+                    dict(x=199.5, y=-0.5, z=0.0, r=10.0, angle=0.0)],
+             bubbles=[dict(x=-0.5, y=80.0, z=0.0, r=20.0)], steps=20000)
+    return c
+
+
 def small(dim=2, nx=12, ny=10, nz=1, fields=FIELDS_ALL, seed=0, periodic=None,
           **over):
     """Tiny grids for brute-force parity: one seed and one bubble placed at
@@ -253,6 +297,9 @@ def small(dim=2, nx=12, ny=10, nz=1, fields=FIELDS_ALL, seed=0, periodic=None,
 
 CONFIGS = {
     "coupled2d_128": coupled2d_128,
+    "corner_thermal2d_256": corner_thermal2d_256,
+    "corner_thermosolutal2d_512": corner_thermosolutal2d_512,
+    "bubble_dendrites2d_200x400": bubble_dendrites2d_200x400,
     "alloy2d_1024": alloy2d_1024,
     "coupled2d_2048": coupled2d_2048,
     "coupled2d_2048_q9": coupled2d_2048_q9,
