@@ -120,6 +120,10 @@ bool adj2d_supported(int fields) {
     case F_PSI | F_C:
     case F_PSI | F_C | F_TH:
     case F_NS | F_PHI:
+    case F_PHI | F_PSI | F_C | F_TH:
+    case F_PHI:
+    case F_NS | F_PSI | F_TH:
+    case F_PSI | F_TH:
     case F_PSI:
       return true;
     default:

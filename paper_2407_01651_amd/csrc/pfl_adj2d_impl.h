@@ -1172,16 +1172,23 @@ hipError_t adj_dispatch(const DevParams& P, int fields, const void* fin, const v
                         const AdjOpts& o, bool& ok) {
   ok = true;
   const bool q9 = P.q_phi == 9;
-#define PFL_ADJ(F)                                                                               \
-  case F:                                                                                        \
-    return q9 ? adj_step_t<F, 9, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, o) \
-              : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, o);
+  // the lattice of phi matters only where phi is evolved: one instantiation otherwise
+#define PFL_ADJ(F)                                                                                        \
+  case F:                                                                                                 \
+    return (q9 && ((F) & F_PHI))                                                                          \
+               ? adj_step_t<F, ((F) & F_PHI) ? 9 : 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S,     \
+                                                               dparams, s, o)                             \
+               : adj_step_t<F, 5, ST, HT>(P, fin, hist, tape, lam_in, lam_out, S, dparams, s, o);
   switch (fields) {
     PFL_ADJ(F_NS | F_PHI | F_PSI | F_C | F_TH)
     PFL_ADJ(F_PSI | F_C)
     PFL_ADJ(F_PSI | F_C | F_TH)
     PFL_ADJ(F_NS | F_PHI)
     PFL_ADJ(F_PSI)
+    PFL_ADJ(F_PHI | F_PSI | F_C | F_TH)
+    PFL_ADJ(F_PHI)
+    PFL_ADJ(F_NS | F_PSI | F_TH)
+    PFL_ADJ(F_PSI | F_TH)
     default:
       ok = false;
       return hipSuccess;

@@ -35,6 +35,11 @@ CASES = [
     ("alloy_theta_18x11", dict(nx=18, ny=11, seed=36, fields=("psi", "c", "theta")), 3),
     ("nsphi_21x21", dict(nx=21, ny=21, seed=37, fields=("ns", "phi")), 4),
     ("psi_only_16x16", dict(nx=16, ny=16, seed=38, fields=("psi",), Le=math.inf, theta0=-0.3), 3),
+    ("all_phiq9_21x17", dict(nx=21, ny=17, seed=46, phi_q=9), 3),
+    ("noflow_23x17", dict(nx=23, ny=17, seed=47, fields=("phi", "psi", "c", "theta")), 3),
+    ("phi_only_18x14", dict(nx=18, ny=14, seed=48, fields=("phi",)), 3),
+    ("ns_psi_theta_22x12", dict(nx=22, ny=12, seed=49, fields=("ns", "psi", "theta")), 3),
+    ("psi_theta_21x13", dict(nx=21, ny=13, seed=50, fields=("psi", "theta")), 3),
 ]
 
 
