@@ -75,23 +75,49 @@ __device__ __forceinline__ T& at_node(T* plane, uint32_t node) {
 
 // The node-form entry that receives the value a node at (x, y), flat index
 // idx, stores for direction i: population j of node `node`, with j = i at
-// x + c_i, or j = opp(i) at the node itself across a wall (`wall`).  In a fast
-// tile x + c_i lies inside the domain.
+// x + c_i (`regular`), j = opp(i) at the node itself across a wall or a
+// far-field side (`wall`; `far` when a far-field side was crossed), or, across
+// a symmetry plane (SYM), the population with that component of c_i reversed
+// at x + c_i with that coordinate kept.  c_j = (sx c_ix, sy c_iy).  A wall
+// dominates at corners.  In a fast tile x + c_i lies inside the domain.
 struct PushTarget {
   uint32_t node;
   int j;
-  bool wall;
+  bool wall, regular, far;
+  int sx, sy;
 };
-template <int Q>
+template <int Q, bool SYM = false>
 __device__ __forceinline__ PushTarget push_to(const DevParams& P, bool fast, uint32_t idx, int x, int y, int i) {
   using L = Lat<Q>;
-  PushTarget t{idx + (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx), i, false};
+  PushTarget t{idx + (uint32_t)(L::c[i][0] + L::c[i][1] * P.nx), i, false, true, false, 1, 1};
   if (fast) return t;
   int tx = x + L::c[i][0], ty = y + L::c[i][1];
-  if (tx < 0 || tx >= P.nx) { if (P.wall[0]) t.wall = true; else tx = tx < 0 ? tx + P.nx : tx - P.nx; }
-  if (ty < 0 || ty >= P.ny) { if (P.wall[1]) t.wall = true; else ty = ty < 0 ? ty + P.ny : ty - P.ny; }
-  if (t.wall) { t.node = idx; t.j = L::opp[i]; }
-  else t.node = (uint32_t)ty * (uint32_t)P.nx + (uint32_t)tx;
+  bool symx = false, symy = false;
+  if (tx < 0 || tx >= P.nx) {
+    if (P.wall[0]) {
+      const bool lo = tx < 0;
+      if (SYM && sym_side(P, 0, lo)) symx = true;
+      else { t.wall = true; t.far = t.far || (SYM && far_side(P, 0, lo)); }
+    } else tx = tx < 0 ? tx + P.nx : tx - P.nx;
+  }
+  if (ty < 0 || ty >= P.ny) {
+    if (P.wall[1]) {
+      const bool lo = ty < 0;
+      if (SYM && sym_side(P, 1, lo)) symy = true;
+      else { t.wall = true; t.far = t.far || (SYM && far_side(P, 1, lo)); }
+    } else ty = ty < 0 ? ty + P.ny : ty - P.ny;
+  }
+  if (t.wall) {
+    t.node = idx; t.j = L::opp[i]; t.regular = false; t.sx = -1; t.sy = -1;
+    return t;
+  }
+  if (SYM && (symx || symy)) {
+    t.regular = false;
+    if (symx) { tx = x; t.sx = -1; }
+    if (symy) { ty = y; t.sy = -1; }
+    t.j = symx ? (symy ? L::refl[1][L::refl[0][i]] : L::refl[0][i]) : L::refl[1][i];
+  }
+  t.node = (uint32_t)ty * (uint32_t)P.nx + (uint32_t)tx;
   return t;
 }
 
@@ -101,19 +127,29 @@ __device__ __forceinline__ PushTarget push_to(const DevParams& P, bool fast, uin
 struct Reader {
   uint32_t node;
   int cx, cy;      // offset as seen from the reader
-  int sign;        // (-1)^(walls crossed): the sign of an odd (antisymmetric) ghost
+  int sign;        // (-1)^(walls and far-field sides crossed): D_phi (x) v0 is odd there
+  int osign;       // (-1)^(symmetry planes crossed): its off-diagonal components are odd there
+  int fsign;       // (-1)^(far-field sides crossed): psi and U ghosts are odd there
 };
 __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, int cx, int cy) {
   Reader r;
   int rx = x - cx, ry = y - cy;
-  r.cx = cx; r.cy = cy; r.sign = 1;
+  r.cx = cx; r.cy = cy; r.sign = 1; r.osign = 1; r.fsign = 1;
   if (rx < 0 || rx >= P.nx) {
-    if (P.wall[0]) { rx = rx < 0 ? -1 - rx : 2 * P.nx - 1 - rx; r.cx = -cx; r.sign = -r.sign; }
-    else rx = rx < 0 ? rx + P.nx : rx - P.nx;
+    if (P.wall[0]) {
+      const bool lo = rx < 0;
+      rx = lo ? -1 - rx : 2 * P.nx - 1 - rx; r.cx = -cx;
+      if (sym_side(P, 0, lo)) r.osign = -r.osign;
+      else { r.sign = -r.sign; if (far_side(P, 0, lo)) r.fsign = -r.fsign; }
+    } else rx = rx < 0 ? rx + P.nx : rx - P.nx;
   }
   if (ry < 0 || ry >= P.ny) {
-    if (P.wall[1]) { ry = ry < 0 ? -1 - ry : 2 * P.ny - 1 - ry; r.cy = -cy; r.sign = -r.sign; }
-    else ry = ry < 0 ? ry + P.ny : ry - P.ny;
+    if (P.wall[1]) {
+      const bool lo = ry < 0;
+      ry = lo ? -1 - ry : 2 * P.ny - 1 - ry; r.cy = -cy;
+      if (sym_side(P, 1, lo)) r.osign = -r.osign;
+      else { r.sign = -r.sign; if (far_side(P, 1, lo)) r.fsign = -r.fsign; }
+    } else ry = ry < 0 ? ry + P.ny : ry - P.ny;
   }
   r.node = (uint32_t)ry * (uint32_t)P.nx + (uint32_t)rx;
   return r;
@@ -124,7 +160,7 @@ __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, in
 // TAPED: the step's stencil results (grad and Laplacian of phi, grad psi,
 // grad U, mass-flux force) are read from the tape the forward step wrote, so
 // the tile's halo and its LDS stencils are not redone.
-template <int FIELDS, int QP, class ST, class HT, class CT, bool TAPED>
+template <int FIELDS, int QP, class ST, class HT, class CT, bool TAPED, bool SYM = false>
 __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                                                        const typename Store<ST>::raw* __restrict__ fin,
                                                        const HT* __restrict__ hist,
@@ -187,7 +223,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       if constexpr (TH) { h_Hv0 = hld(P.h_Hv); h_Hv1 = hld(P.h_Hv + 1); }
     }
     if constexpr (NS) {
-      pull<QN, ST, CT>(fast, fin_ns, P, x, y, fns);
+      pull<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, fns);
 #pragma unroll
       for (int i = 0; i < QN; ++i) {
         fns[i] += CT(P.ref_ns[i]);
@@ -196,26 +232,26 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       }
     }
     if constexpr (PHI) {
-      pull<QP, ST, CT>(fast, fin_phi, P, x, y, fph);
+      pull<QP, ST, CT, SYM>(fast, fin_phi, P, x, y, fph);
       phi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) { fph[i] += CT(P.ref_phi[i]); phi += fph[i]; }
     }
     if constexpr (PSI) {
-      pull<QS, ST, CT>(fast, fin_psi, P, x, y, fps);
+      pull<QS, ST, CT, SYM>(fast, fin_psi, P, x, y, fps);
       psi = CT(0);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fps[i] += CT(P.ref_psi[i]); psi += fps[i]; }
     }
     if constexpr (CC) {
-      pull<QS, ST, CT>(fast, fin_c, P, x, y, fc);
+      pull<QS, ST, CT, SYM>(fast, fin_c, P, x, y, fc);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fc[i] += CT(P.ref_c[i]); C += fc[i]; }
       const CT h0 = (psi + CT(1)) * CT(CT(0.5));
       U = (C / (CT(1) - k1 * h0) - CT(1)) * K.inv_k1;
     }
     if constexpr (TH) {
-      pull<QS, ST, CT>(fast, fin_th, P, x, y, fth);
+      pull<QS, ST, CT, SYM>(fast, fin_th, P, x, y, fth);
 #pragma unroll
       for (int i = 0; i < QS; ++i) { fth[i] += CT(P.ref_th[i]); H += fth[i]; }
     }
@@ -442,9 +478,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
-      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      const PushTarget t = push_to<QS, SYM>(P, fast, (uint32_t)idx, x, y, i);
       CT ao = lam_at(P.o_th, t);
       ao += pend_at(P_H, t);
+      if (SYM && t.far) ao = -ao;     // stored by anti-bounce-back: 2 w theta0 - g*
       a_jhx += ao * (1 - s1) * cx * CT(0.5);
       a_jhy += ao * (1 - s1) * cy * CT(0.5);
       a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
@@ -486,9 +523,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = LS::c[i][0], cy = LS::c[i][1], w = LS::w[i];
-      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      const PushTarget t = push_to<QS, SYM>(P, fast, (uint32_t)idx, x, y, i);
       CT ao = lam_at(P.o_c, t);
       ao += pend_at(P_C, t);
+      if (SYM && t.far) ao = -ao;     // stored by anti-bounce-back: 2 w - f*
       a_C += ao * w;
       a_Bx += ao * 3 * w * cx;
       a_By += ao * 3 * w * cy;
@@ -558,20 +596,23 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
                           (P.wall[1] && (y + dy < 0 || y + dy >= P.ny));
       const CT old = across ? fps[LS::opp[i]]
                             : Store<ST>::template ld<CT>(fin_psi + (long long)i * N + idx) + CT(P.ref_psi[i]);
-      const PushTarget t = push_to<QS>(P, fast, (uint32_t)idx, x, y, i);
+      const PushTarget t = push_to<QS, SYM>(P, fast, (uint32_t)idx, x, y, i);
       CT ao = lam_at(P.o_psi, t);
       {
         // the previous step's old-value read of this population is the
         // node's own A_OLD entry (rewritten below by this step)
         const CT old_prev = S[(long long)(A_OLD0 + i) * N + idx];
         CT v = pend_at(P_PSI, t);
-        if (!t.wall) v += old_prev;
+        if (t.regular) v += old_prev;
         ao += v;
       }
-      const CT a_fstar = ao * inv_an;
+      // across a far-field side f* was replaced by its anti-bounce-back 2 w psi_l - f*
+      const bool abb = SYM && t.far;
+      const CT fst = abb ? CT(-2) * w - fstar : fstar;
+      const CT a_fstar = (abb ? -ao : ao) * inv_an;
       const CT a_oldi = -ao * (1 - an) * inv_an;
       a_an += ao * old * inv_an;
-      a_inv_an += ao * (fstar - (1 - an) * old);
+      a_inv_an += ao * (fst - (1 - an) * old);
       if (across) a_fps[LS::opp[i]] += a_oldi; else a_old[i] += a_oldi;
       a_psi += a_fstar * w;
       a_rate += a_fstar * (-(cx * jax + cy * jay) * CT(0.5) - CT(0.5) * Gi);
@@ -616,7 +657,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QP; ++i) {
       const CT cx = LP::c[i][0], cy = LP::c[i][1];
-      const PushTarget t = push_to<QP>(P, fast, (uint32_t)idx, x, y, i);
+      const PushTarget t = push_to<QP, SYM>(P, fast, (uint32_t)idx, x, y, i);
       CT ao = lam_at(P.o_phi, t);
       ao += pend_at(P_PHI, t);
       a_feq[i] = ao;
@@ -670,14 +711,14 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QN; ++i) {
       const CT cx = LN::c[i][0], cy = LN::c[i][1];
-      const PushTarget t = push_to<QN>(P, fast, (uint32_t)idx, x, y, i);
+      const PushTarget t = push_to<QN, SYM>(P, fast, (uint32_t)idx, x, y, i);
       ao_[i] = lam_at(P.o_ns, t);
       {
-        // c_j . a_j at the target, c_j = -c_i across a wall
+        // c_j . a_j at the target: c_j = -c_i across a wall, c_i with the
+        // plane's component reversed across a symmetry plane
         CT v = CT(0);
-        if (LN::c[i][0] != 0) v += cx * pend_at(P_JX, t);
-        if (LN::c[i][1] != 0) v += cy * pend_at(P_JY, t);
-        if (t.wall) v = -v;
+        if (LN::c[i][0] != 0) v += CT(t.sx) * cx * pend_at(P_JX, t);
+        if (LN::c[i][1] != 0) v += CT(t.sy) * cy * pend_at(P_JY, t);
         ao_[i] += v;
       }
       a_r += ao_[i] * CT(0.25) * ((cx * cx - cy * cy) * m1 + (cx * cy) * m2);
@@ -903,10 +944,11 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __
   for (int i = 1; i < 9; ++i) {
     const Reader r = reader_of(P, x, y, LN::c[i][0], LN::c[i][1]);
     const CT f = CT(3.0 * LN::w[i]) * K.drho * CT(r.sign);
+    const CT fo = f * CT(r.osign);    // off-diagonal components: odd across symmetry planes
     const CT fmx = at_node(pl(AS_FMX), r.node), fmy = at_node(pl(AS_FMY), r.node);
     aX0 += f * CT(r.cx) * fmx;   // X_xx feeds Fm_x through c_x
-    aX1 += f * CT(r.cx) * fmy;   // X_xy feeds Fm_y through c_x
-    aX2 += f * CT(r.cy) * fmx;   // X_yx feeds Fm_x through c_y
+    aX1 += fo * CT(r.cx) * fmy;  // X_xy feeds Fm_y through c_x
+    aX2 += fo * CT(r.cy) * fmx;  // X_yx feeds Fm_x through c_y
     aX3 += f * CT(r.cy) * fmy;   // X_yy feeds Fm_y through c_y
   }
   const CT phi = at_node(pl(FW_PHI), n), psi = at_node(pl(FW_PSI), n);
@@ -990,8 +1032,10 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT
     if constexpr (PHI)
       a_phi += w3 * (cx * at_node(pl(AS_GPHX), r.node) + cy * at_node(pl(AS_GPHY), r.node)) +
                w6 * at_node(pl(AS_LAP), r.node);
-    if constexpr (PSI) a_psi += w3 * (cx * at_node(pl(AS_GPSX), r.node) + cy * at_node(pl(AS_GPSY), r.node));
-    if constexpr (CC) a_U += w3 * (cx * at_node(pl(AS_GUX), r.node) + cy * at_node(pl(AS_GUY), r.node));
+    // psi and U ghosts across a far-field side are odd about their far-field values
+    const CT wf = w3 * CT(r.fsign);
+    if constexpr (PSI) a_psi += wf * (cx * at_node(pl(AS_GPSX), r.node) + cy * at_node(pl(AS_GPSY), r.node));
+    if constexpr (CC) a_U += wf * (cx * at_node(pl(AS_GUX), r.node) + cy * at_node(pl(AS_GUY), r.node));
   }
   CT a_C = at_node(pl(AM_C), n);
   CT a_k1 = at_node(pl(PG_K1), n);
@@ -1141,7 +1185,12 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
       hipLaunchKernelGGL((adj_clear_pending_kernel<RT>), dim3(nb), dim3(256), 0, s, S, N);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (tape)
+    // symmetry planes and far-field sides: taped only (the recompute of the
+    // stencils in the untaped form keeps the wall ghosts)
+    if (tape && (P.sym || P.far))
+      hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true, true>), dim3(tiles), dim3(NT), 0, s, P,
+                         (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
+    else if (tape)
       hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true>), dim3(tiles), dim3(NT), 0, s, P,
                          (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
     else
