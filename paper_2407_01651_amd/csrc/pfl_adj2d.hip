@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void adj_init_sum_kernel(long long N, const do
 size_t adj_scratch_bytes(long long N, int store) {
   const size_t elem = store == 0 ? sizeof(double) : sizeof(float);
   const size_t nb = (size_t)((N + 255) / 256);
-  const size_t bytes = part_offset(N, elem) + 2 * nb * sizeof(double);
+  const size_t bytes = part_offset(N, elem) + 3 * nb * sizeof(double);
   // the initial-state adjoint uses four FP64 planes of the same buffer
   const size_t init = 4 * (size_t)N * sizeof(double);
   return bytes > init ? bytes : init;

@@ -48,7 +48,7 @@ enum : int {
   AM_PHI = 0, AM_PSI, AM_C, AM_H, AM_JX, AM_JY, AM_U,                  // moment adjoints
   AS_GPHX, AS_GPHY, AS_LAP, AS_GPSX, AS_GPSY, AS_GUX, AS_GUY, AS_FMX, AS_FMY,  // stencil-input adjoints
   FW_PHI, FW_PSI, FW_C, FW_JX, FW_JY, FW_GX, FW_GY, FW_LAP,            // forward values for R2/R3
-  PG_EPS, PG_K1,                                                       // per-node parameter gradients
+  PG_EPS, PG_K1, PG_OM,                                                // per-node parameter gradients
   A_OLD0,                                                              // 5 planes: time-stretched store reads
   P_JX = A_OLD0 + 5, P_JY, P_PHI, P_PSI, P_C, P_H,                     // moment terms of lambda^n not yet added
   A_NPLANES
@@ -460,6 +460,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   CT a_S = 0, a_rate = 0, a_gpx = 0, a_gpy = 0, a_ex = 0, a_ey = 0, a_gUx = 0, a_gUy = 0;
   CT a_om = 0, a_sharp = 0, a_fnx = 0, a_fny = 0, a_chi = 0, a_Fsx = 0, a_Fsy = 0, a_Fmx = 0, a_Fmy = 0;
   CT a_eps = 0, a_k1 = 0;
+  CT a_Omega = 0;  // Omega through the far-field value theta0 = -Omega of the heat set
   CT a_fns[NS ? QN : 1] = {}, a_fph[PHI ? QP : 1] = {}, a_fps[PSI ? QS : 1] = {};
   CT a_fc[CC ? QS : 1] = {}, a_fth[TH ? QS : 1] = {}, a_old[PSI ? QS : 1] = {};
   CT a_hpsi = 0, a_hS = 0, a_hpv0 = 0, a_hpv1 = 0, a_hB0 = 0, a_hB1 = 0, a_hHv0 = 0, a_hHv1 = 0;
@@ -481,7 +482,10 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       const PushTarget t = push_to<QS, SYM>(P, fast, (uint32_t)idx, x, y, i);
       CT ao = lam_at(P.o_th, t);
       ao += pend_at(P_H, t);
-      if (SYM && t.far) ao = -ao;     // stored by anti-bounce-back: 2 w theta0 - g*
+      if (SYM && t.far) {             // stored by anti-bounce-back: 2 w theta0 - g*, theta0 = -Omega
+        a_Omega -= CT(2) * w * ao;
+        ao = -ao;
+      }
       a_jhx += ao * (1 - s1) * cx * CT(0.5);
       a_jhy += ao * (1 - s1) * cy * CT(0.5);
       a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
@@ -923,6 +927,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   S[AS_FMY * N + idx] = a_Fmy;
   S[PG_EPS * N + idx] = a_eps;
   S[PG_K1 * N + idx] = a_k1;
+  if constexpr (SYM) S[PG_OM * N + idx] = a_Omega;
 }
 
 // ------------------------------------------------------------------- R2
@@ -1051,19 +1056,27 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT
   }
   // per-block partial sums of the parameter gradients (FP64, fixed order)
   {
-    __shared__ double s_e[256], s_k[256];
+    __shared__ double s_e[256], s_k[256], s_o[256];
     s_e[threadIdx.x] = live ? (double)at_node(pl(PG_EPS), n) : 0.0;
     s_k[threadIdx.x] = live ? (double)a_k1 : 0.0;
+    // Omega through the far-field temperature (written by the reverse that handles far-field sides)
+    s_o[threadIdx.x] = (live && P.far) ? (double)at_node(pl(PG_OM), n) : 0.0;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
+      if (threadIdx.x < off) {
+        s_e[threadIdx.x] += s_e[threadIdx.x + off];
+        s_k[threadIdx.x] += s_k[threadIdx.x + off];
+        s_o[threadIdx.x] += s_o[threadIdx.x + off];
+      }
       __syncthreads();
     }
     // accumulate: a sweep over several steps adds each block's partials in
     // step order (each block owns its slots), summed once at the end
     if (threadIdx.x == 0) {
-      part[2 * blockIdx.x] = (accumulate ? part[2 * blockIdx.x] : 0.0) + s_e[0];
-      part[2 * blockIdx.x + 1] = (accumulate ? part[2 * blockIdx.x + 1] : 0.0) + s_k[0];
+      double* pb = part + 3 * blockIdx.x;
+      pb[0] = (accumulate ? pb[0] : 0.0) + s_e[0];
+      pb[1] = (accumulate ? pb[1] : 0.0) + s_k[0];
+      pb[2] = (accumulate ? pb[2] : 0.0) + s_o[0];
     }
   }
   if (!live) return;
@@ -1141,21 +1154,26 @@ __global__ __launch_bounds__(256) void adj_broadcast_kernel(const DevParams P, c
 
 // Step parameter gradients from the per-block partials of the assembly pass:
 // 256 threads take fixed strided subsets, then a fixed-order tree; thread 0
-// adds the eps4 sum to dparams[0] and minus the k1 sum to dparams[1]
-// (k = 1 - k1).  Deterministic.
+// adds the eps4 sum to dparams[0], minus the k1 sum to dparams[1]
+// (k = 1 - k1) and the Omega sum to dparams[2].  Deterministic.
 __global__ __launch_bounds__(256) void adj_param_sum_kernel(int nblocks, const double* __restrict__ part,
                                                             double* __restrict__ dparams) {
-  __shared__ double s_e[256], s_k[256];
-  double e = 0.0, k = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 256) { e += part[2 * b]; k += part[2 * b + 1]; }
+  __shared__ double s_e[256], s_k[256], s_o[256];
+  double e = 0.0, k = 0.0, o = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) { e += part[3 * b]; k += part[3 * b + 1]; o += part[3 * b + 2]; }
   s_e[threadIdx.x] = e;
   s_k[threadIdx.x] = k;
+  s_o[threadIdx.x] = o;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) { s_e[threadIdx.x] += s_e[threadIdx.x + off]; s_k[threadIdx.x] += s_k[threadIdx.x + off]; }
+    if (threadIdx.x < off) {
+      s_e[threadIdx.x] += s_e[threadIdx.x + off];
+      s_k[threadIdx.x] += s_k[threadIdx.x + off];
+      s_o[threadIdx.x] += s_o[threadIdx.x + off];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) { dparams[0] += s_e[0]; dparams[1] -= s_k[0]; }
+  if (threadIdx.x == 0) { dparams[0] += s_e[0]; dparams[1] -= s_k[0]; dparams[2] += s_o[0]; }
 }
 
 // Byte offset of the per-block partials in the scratch buffer, after the

@@ -367,6 +367,46 @@ def test_checkpointed_gradient_matches_oracle_and_fd():
         assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
 
 
+def test_gradient_in_the_coupled_geometry_of_sec4():
+    """The geometry of the paper's coupled runs (symmetry planes in x, a
+    no-flux bottom, a far-field top, seeds at the bottom corners, a bubble on
+    the left plane) on a 40 x 48 grid: 40 steps, checkpoints every 16; the
+    gradient of the phi/psi loss against the oracle's reverse mode over the
+    whole run (1e-9) and against central differences of the GPU forward (1e-4)."""
+    from paper_2407_01651_amd.adjoint import params_of, run_with_gradient
+    w = workloads.get("adjoint2d_64")
+    w.update(nx=40, ny=48, periodic=(False, False, True), symmetric=(True, False, False),
+             farfield=(False, "hi", False), U0=0.0,
+             seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=5.0, angle=0.0), dict(x=39.5, y=-0.5, z=0.0, r=5.0, angle=0.0)],
+             bubbles=[dict(x=-0.5, y=14.0, z=0.0, r=7.0)])
+    steps = 40
+    phi_t, psi_t = _target(w, steps, [0.01, 0.02, 0.03, 0.5])
+    p0 = params_of(w)
+    p = torch.tensor(p0, dtype=torch.float64, device="cuda", requires_grad=True)
+    phi, psi = run_with_gradient(p, w, steps, K=16)
+    L = ((phi - phi_t) ** 2).sum() + ((psi - psi_t) ** 2).sum()
+    L.backward()
+    g = p.grad.cpu().tolist()
+    pt = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in p0]
+    Lo = run_loss(w, pt, steps, phi_t.cpu(), psi_t.cpu())
+    Lo.backward()
+    gref = [float(t.grad) for t in pt]
+    log(f"[adjoint] sec4 geometry grad gpu {g}")
+    log(f"[adjoint] sec4 geometry grad ref {gref}")
+    gmax = max(abs(v) for v in gref)
+    # 1e-9: without the far-field temperature's dependence on Omega the
+    # Omega component misses by 3.5e-8 here
+    for a, b in zip(g, gref):
+        assert abs(a - b) <= 1e-9 * max(abs(b), 1e-3 * gmax), (g, gref)
+    h = 1e-3
+    for j in range(len(p0)):
+        pp = list(p0); pm = list(p0)
+        pp[j] += h; pm[j] -= h
+        fd = (_gpu_loss(w, pp, steps, phi_t, psi_t) - _gpu_loss(w, pm, steps, phi_t, psi_t)) / (2 * h)
+        log(f"[adjoint] sec4 geometry fd {j}: {fd:.8e} adjoint {g[j]:.8e}")
+        assert abs(fd - g[j]) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (j, fd, g[j])
+
+
 def test_adjoint2d_64_full_run_matches_fd():
     """The 64 x 64 copy of the adjoint workload, FP64, all 2000 steps with
     checkpoints every 100: gradient with respect to [eps4, k, Omega, R_1, R_2]
