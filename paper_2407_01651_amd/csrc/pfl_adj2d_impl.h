@@ -274,7 +274,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     CT hphi = CT(1), hpsi = CT(-1), hU = K.U0, hjx = CT(0), hjy = CT(0);
     if constexpr (PHI) {
       CT f[QP];
-      pull<QP, ST, CT>(fast, fin_phi, P, gx, gy, f);
+      pull<QP, ST, CT, SYM>(fast, fin_phi, P, gx, gy, f);
       hphi = CT(0);
 #pragma unroll
       for (int i = 0; i < QP; ++i) hphi += f[i] + CT(P.ref_phi[i]);
@@ -282,14 +282,14 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     if (ring1) {
       if constexpr (PSI) {
         CT f[QS];
-        pull<QS, ST, CT>(fast, fin_psi, P, gx, gy, f);
+        pull<QS, ST, CT, SYM>(fast, fin_psi, P, gx, gy, f);
         hpsi = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) hpsi += f[i] + CT(P.ref_psi[i]);
       }
       if constexpr (CC) {
         CT f[QS];
-        pull<QS, ST, CT>(fast, fin_c, P, gx, gy, f);
+        pull<QS, ST, CT, SYM>(fast, fin_c, P, gx, gy, f);
         CT hC = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) hC += f[i] + CT(P.ref_c[i]);
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       }
       if constexpr (NS) {
         CT f[QN];
-        pull<QN, ST, CT>(fast, fin_ns, P, gx, gy, f);
+        pull<QN, ST, CT, SYM>(fast, fin_ns, P, gx, gy, f);
 #pragma unroll
         for (int i = 0; i < QN; ++i) {
           f[i] += CT(P.ref_ns[i]);
@@ -306,6 +306,13 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
           hjy += CT(LN::c[i][1]) * f[i];
         }
       }
+    }
+    if (SYM && P.far) {
+      // ghost across an odd number of far-field sides: psi and U odd about
+      // psi_l = -1 and U = 0 (as the forward step)
+      const bool fx = gx0 < 0 ? far_side(P, 0, true) : gx0 >= P.nx && far_side(P, 0, false);
+      const bool fy = gy0 < 0 ? far_side(P, 1, true) : gy0 >= P.ny && far_side(P, 1, false);
+      if (fx != fy) { hpsi = CT(-2) - hpsi; hU = -hU; }
     }
     s_phi[ry][rx] = hphi;
     s_psi[ry][rx] = hpsi;
@@ -323,22 +330,22 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       const int rx = k % AX + R - 1, ry = k / AX + R - 1;
       const int gx0 = bx0 + rx - R, gy0 = by0 + ry - R;
       int mx = rx, my = ry;
-      CT sgn = CT(1);
+      CT sgn = CT(1), sod = CT(1);    // walls: all components odd; symmetry planes: off-diagonal odd
       bool skip = false;
       if (P.wall[0] && (gx0 < 0 || gx0 >= P.nx)) {
         if (gx0 == -1) mx = rx + 1; else if (gx0 == P.nx) mx = rx - 1; else skip = true;
-        sgn = -sgn;
+        if (SYM && sym_side(P, 0, gx0 < 0)) sod = -sod; else sgn = -sgn;
       }
       if (P.wall[1] && (gy0 < 0 || gy0 >= P.ny)) {
         if (gy0 == -1) my = ry + 1; else if (gy0 == P.ny) my = ry - 1; else skip = true;
-        sgn = -sgn;
+        if (SYM && sym_side(P, 1, gy0 < 0)) sod = -sod; else sgn = -sgn;
       }
       CT X0 = CT(0), X1 = CT(0), X2 = CT(0), X3 = CT(0);
       if (!skip) {
         FlowNode<CT> hn;
         flow_node<NS, PHI, CT, RX>(K, s_phi, s_psi, s_jx, s_jy, my, mx, hn);
-        X0 = sgn * hn.Dx * hn.v0x; X1 = sgn * hn.Dx * hn.v0y;
-        X2 = sgn * hn.Dy * hn.v0x; X3 = sgn * hn.Dy * hn.v0y;
+        X0 = sgn * hn.Dx * hn.v0x; X1 = sgn * sod * hn.Dx * hn.v0y;
+        X2 = sgn * sod * hn.Dy * hn.v0x; X3 = sgn * hn.Dy * hn.v0y;
       }
       s_X[0][ry][rx] = X0; s_X[1][ry][rx] = X1; s_X[2][ry][rx] = X2; s_X[3][ry][rx] = X3;
     }
@@ -1203,13 +1210,16 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
       hipLaunchKernelGGL((adj_clear_pending_kernel<RT>), dim3(nb), dim3(256), 0, s, S, N);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // symmetry planes and far-field sides: taped only (the recompute of the
-    // stencils in the untaped form keeps the wall ghosts)
-    if (tape && (P.sym || P.far))
+    // symmetry planes and far-field sides: a separate instantiation
+    const bool sym = P.sym || P.far;
+    if (tape && sym)
       hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true, true>), dim3(tiles), dim3(NT), 0, s, P,
                          (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
     else if (tape)
       hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, true>), dim3(tiles), dim3(NT), 0, s, P,
+                         (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
+    else if (sym)
+      hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false, true>), dim3(tiles), dim3(NT), 0, s, P,
                          (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
     else
       hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false>), dim3(tiles), dim3(NT), 0, s, P,

@@ -485,16 +485,12 @@ int pfl_step_raw_taped(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t st
   return step_image(c, raw_in, raw_out, step_count, first, tape);
 }
 
-static int adj_check(pfl_ctx* c, bool taped = false) {
+static int adj_check(pfl_ctx* c) {
   if (!c) return fail(PFL_E_INVALID_ARG, "null context");
   if (!c->inited) return fail(PFL_E_STATE, "adjoint before init");
   if (!c->b.adj) return fail(PFL_E_STATE, "no adjoint scratch buffer (pfl_buffers.adj)");
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
-  // symmetry planes and far-field sides: the taped reverse only
-  for (int a = 0; a < 3; ++a)
-    if (c->p.wall[a] >= 2 && !taped)
-      return fail(PFL_E_UNSUPPORTED, "symmetry planes and far-field sides need the taped adjoint");
   if (c->d.kd.varheat) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for matched heat properties");
   return PFL_OK;
 }
@@ -517,7 +513,7 @@ int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dpa
 
 static int backward_image(pfl_ctx* c, const void* raw_state, int64_t step_count, int first, const void* tape,
                           const void* adj_in, void* adj_out, double* dparams) {
-  int rc = adj_check(c, tape != nullptr);
+  int rc = adj_check(c);
   if (rc) return rc;
   if (!raw_state || !adj_in || !adj_out || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
   if (adj_in == adj_out) return fail(PFL_E_INVALID_ARG, "adj_in and adj_out must differ");
@@ -549,7 +545,7 @@ int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_coun
 
 int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* const* tapes, int64_t n,
                        int64_t step0, int first0, void* adj, void* adj_tmp, double* dparams, int flags) {
-  int rc = adj_check(c, tapes != nullptr);
+  int rc = adj_check(c);
   if (rc) return rc;
   if (!adj || !adj_tmp || !dparams || (n > 0 && !raw_states)) return fail(PFL_E_INVALID_ARG, "null argument");
   if (adj == adj_tmp) return fail(PFL_E_INVALID_ARG, "adj and adj_tmp must differ");
@@ -601,7 +597,7 @@ int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* co
 }
 
 int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams) {
-  int rc = adj_check(c, true);     // the initial state does not depend on the boundaries
+  int rc = adj_check(c);
   if (rc) return rc;
   if (!adj0 || !dparams) return fail(PFL_E_INVALID_ARG, "null argument");
   c->sweep_open = false;    // the initial-state adjoint reuses the scratch

@@ -214,13 +214,14 @@ SYM_CASES = [
 ]
 
 
+@pytest.mark.parametrize("taped", [True, False], ids=["taped", "recomputed"])
 @pytest.mark.parametrize("name,over,n_pre", SYM_CASES, ids=[c[0] for c in SYM_CASES])
-def test_taped_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pre):
-    """The taped reverse (stencil results from the tape) with symmetry planes
-    (specular pushes, mirror-parity ghosts) and far-field sides (anti-bounce-
-    back stores, odd psi and U ghosts) against the oracle's reverse mode, bar
-    1e-9 as the other one-step adjoints; NS and phi on D2Q9 cover the diagonal
-    reflections."""
+def test_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pre, taped):
+    """The reverse with symmetry planes (specular pushes, mirror-parity
+    ghosts) and far-field sides (anti-bounce-back stores, odd psi and U
+    ghosts), with the stencil results from the step's tape or recomputed with
+    the same ghosts, against the oracle's reverse mode, bar 1e-9 as the other
+    one-step adjoints; NS and phi on D2Q9 cover the diagonal reflections."""
     import paper_2407_01651_amd as pfl
     w = _w(over)
     osim = OracleSim(OracleParams.from_workload(w))
@@ -240,11 +241,14 @@ def test_taped_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pr
     lin = lam_next.cuda()
     lout = torch.empty_like(lin)
     dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
-    sim.step_backward_taped(img, n_pre, first, tape, lin, lout, dp)
+    if taped:
+        sim.step_backward_taped(img, n_pre, first, tape, lin, lout, dp)
+    else:
+        sim.step_backward_raw(img, n_pre, first, lin, lout, dp)
     torch.cuda.synchronize()
     err = _relerr(lout.cpu(), lam_ref)
     dpc = dp.cpu()
-    log(f"[adjoint] {name} taped lambda {err:.2e} d_eps {float(dpc[0]):.6e}/{d_eps:.6e} "
+    log(f"[adjoint] {name} taped={taped} lambda {err:.2e} d_eps {float(dpc[0]):.6e}/{d_eps:.6e} "
         f"d_k {float(dpc[1]):.6e}/{d_k:.6e}")
     for i in range(shape[0]):
         e = float((lout[i].cpu() - lam_ref[i]).abs().max()) / max(float(lam_ref.abs().max()), 1e-300)
@@ -252,22 +256,6 @@ def test_taped_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pr
     scale = max(abs(d_eps), abs(d_k), 1e-300)
     assert abs(float(dpc[0]) - d_eps) <= TOL * max(abs(d_eps), 1e-3 * scale)
     assert abs(float(dpc[1]) - d_k) <= TOL * max(abs(d_k), 1e-3 * scale)
-    sim.close()
-
-
-def test_adjoint_rejects_symmetry_planes():
-    """The untaped reverse recomputes the stencils with the wall ghosts: with
-    symmetry planes it reports PFL_E_UNSUPPORTED instead of computing."""
-    import paper_2407_01651_amd as pfl
-    w = _w(dict(nx=20, ny=14, seed=31))
-    w.update(periodic=(False, False, True), symmetric=(True, False, False))
-    sim = pfl.Sim(w, adjoint=True)
-    sim.init_fields()
-    lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=torch.float64, device="cuda")
-    out = torch.empty_like(lam)
-    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
-    with pytest.raises(Exception, match="symmetry|periodic axes and walls"):
-        sim.step_backward(lam, out, dp)
     sim.close()
 
 
