@@ -226,8 +226,8 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
  * state_bytes / 8 elements; dparams is a device FP64 vector
  * [eps4, k, Omega, R_1..R_nbub] (accumulated in FP64).  The state is not
  * changed.  Errors: PFL_E_STATE before init or without an adj buffer;
- * PFL_E_UNSUPPORTED in 3D or with heat property ratios other than 1 (built for every
- * field combination and boundary type the 2D step runs, phi on either lattice). */
+ * PFL_E_UNSUPPORTED in 3D (built for every field combination, boundary type and heat
+ * property the 2D step runs, phi on either lattice). */
 int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dparams);
 
 /* pfl_step_backward at the state held in a raw image (pfl_save_raw /

@@ -72,6 +72,13 @@ __global__ __launch_bounds__(256) void adj_init_kernel(const DevParams P, int fi
   double gR = (lphi + lC * cfac) * dphi_dR;
   double gk1 = lC * phi * (U0 * (1.0 - k1 * h) - h * (1.0 + k1 * U0));
   double gOm = (fields & F_TH) ? -lth : -lC * phi * k1 * (1.0 - k1 * h);
+  if ((fields & F_TH) && P.kd.varheat) {
+    // rest population rho (c_p theta0 - h) + (w_0 - 1) theta0, rho and c_p linear in phi
+    const double l0 = (double)lam0[(long long)P.o_th * N + n];
+    const double rh = P.th_rho_g + (1.0 - P.th_rho_g) * phi, cp = P.th_cp_g + (1.0 - P.th_cp_g) * phi;
+    gOm -= l0 * (rh * cp - 1.0);
+    gR += l0 * ((1.0 - P.th_rho_g) * (cp * P.theta0 - h) + rh * (1.0 - P.th_cp_g) * P.theta0) * dphi_dR;
+  }
   S[0 * N + n] = gk1;
   S[1 * N + n] = gOm;
   S[2 * N + n] = gR;

@@ -373,7 +373,20 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   const CT h = (psi + CT(1)) * CT(CT(0.5));
   const CT qraw = (CT(1) - psi) * CT(CT(0.5));
   const CT q = clamp01(qraw);
-  const CT theta = TH ? (H + h) : K.theta0;
+  // temperature (theta = (sum g / rho + h) / c_p with the heat properties
+  // linear in phi; H + h when they are matched) and the heat rate
+  CT theta = K.theta0, th_rh = CT(1), th_cp = CT(1), th_s1 = K.s_th;
+  if constexpr (TH) {
+    if (K.varheat) {
+      th_rh = K.th_rho_g + (CT(1) - K.th_rho_g) * phi;
+      th_cp = K.th_cp_g + (CT(1) - K.th_cp_g) * phi;
+      const CT kh = K.th_k_g + (CT(1) - K.th_k_g) * phi;
+      theta = (H + th_rh * h) / (th_rh * th_cp);
+      th_s1 = CT(1) / (K.alpha_cs * kh + CT(0.5));
+    } else {
+      theta = H + h;
+    }
+  }
   CT gpx = CT(0), gpy = CT(0), gUx = CT(0), gUy = CT(0);
   if constexpr (TAPED) {
     gpx = tp(3); gpy = tp(4); gUx = tp(5); gUy = tp(6);
@@ -468,6 +481,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
   CT a_om = 0, a_sharp = 0, a_fnx = 0, a_fny = 0, a_chi = 0, a_Fsx = 0, a_Fsy = 0, a_Fmx = 0, a_Fmy = 0;
   CT a_eps = 0, a_k1 = 0;
   CT a_Omega = 0;  // Omega through the far-field value theta0 = -Omega of the heat set
+  CT a_th_s1 = 0;  // the heat relaxation rate
   CT a_fns[NS ? QN : 1] = {}, a_fph[PHI ? QP : 1] = {}, a_fps[PSI ? QS : 1] = {};
   CT a_fc[CC ? QS : 1] = {}, a_fth[TH ? QS : 1] = {}, a_old[PSI ? QS : 1] = {};
   CT a_hpsi = 0, a_hS = 0, a_hpv0 = 0, a_hpv1 = 0, a_hB0 = 0, a_hB1 = 0, a_hHv0 = 0, a_hHv1 = 0;
@@ -480,7 +494,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 #pragma unroll
     for (int i = 0; i < QS; ++i) { jhx += CT(LS::c[i][0]) * fth[i]; jhy += CT(LS::c[i][1]) * fth[i]; }
     const CT dx_ = Hvx - Hpx, dy_ = Hvy - Hpy;
-    const CT s1 = K.s_th;
+    const CT s1 = th_s1;
     CT a_Hvx = lam_hist(P.h_Hv), a_Hvy = lam_hist(P.h_Hv + 1);
     CT a_jhx = 0, a_jhy = 0, a_dx = 0, a_dy = 0;
 #pragma unroll
@@ -497,6 +511,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_jhy += ao * (1 - s1) * cy * CT(0.5);
       a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
       a_dy += ao * (1 - CT(0.5) * s1) * 3 * w * cy;
+      // the heat rate (per node with variable k_T)
+      a_th_s1 -= ao * CT(0.5) * ((cx * jhx + cy * jhy) + 3 * w * (cx * dx_ + cy * dy_));
       if (i == 0) { a_H += ao; a_theta += ao * (w - 1); }
       else { a_theta += ao * w; a_Hvx += ao * 3 * w * cx; a_Hvy += ao * 3 * w * cy; }
     }
@@ -849,8 +865,17 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 
   // h, q, theta (= H + h with the heat equation, the constant theta0 without), e_psi
   if constexpr (TH) {
-    a_H += a_theta;
-    a_h += a_theta;
+    if (K.varheat) {
+      // theta = (H / rho + h) / c_p; rho, c_p, k_T (through the rate) linear in phi
+      a_H += a_theta / (th_rh * th_cp);
+      a_h += a_theta / th_cp;
+      a_phi += a_theta * (-(H / (th_rh * th_rh * th_cp)) * (CT(1) - K.th_rho_g) -
+                          theta / th_cp * (CT(1) - K.th_cp_g));
+      a_phi -= a_th_s1 * th_s1 * th_s1 * K.alpha_cs * (CT(1) - K.th_k_g);
+    } else {
+      a_H += a_theta;
+      a_h += a_theta;
+    }
   }
   a_psi += CT(0.5) * a_h;
   if (qraw > 0 && qraw < 1) a_psi -= CT(0.5) * a_q;

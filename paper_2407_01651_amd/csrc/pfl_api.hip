@@ -491,7 +491,6 @@ static int adj_check(pfl_ctx* c) {
   if (!c->b.adj) return fail(PFL_E_STATE, "no adjoint scratch buffer (pfl_buffers.adj)");
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
-  if (c->d.kd.varheat) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for matched heat properties");
   return PFL_OK;
 }
 

@@ -211,17 +211,24 @@ SYM_CASES = [
                                   theta0=-0.55, Mcinf=0.5325, tau0=50.0, periodic=(True, False, True),
                                   farfield=(False, "hi", False),
                                   seeds=[dict(x=12.0, y=17.5, z=0.0, r=4.0, angle=0.3)]), 4),
+    # heat properties varying between gas and liquid
+    ("all_varheat_22x16", dict(nx=22, ny=16, seed=56, th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 3),
+    ("noflow_varheat_xsym_far_24x20", dict(nx=24, ny=20, seed=57, fields=("phi", "psi", "c", "theta"),
+                                           periodic=(False, False, True), symmetric=(True, False, False),
+                                           farfield=(False, "hi", False), th_rho_g=0.6, th_cp_g=0.8,
+                                           th_k_g=1.5), 3),
 ]
 
 
 @pytest.mark.parametrize("taped", [True, False], ids=["taped", "recomputed"])
 @pytest.mark.parametrize("name,over,n_pre", SYM_CASES, ids=[c[0] for c in SYM_CASES])
-def test_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pre, taped):
+def test_adjoint_with_boundaries_and_heat_properties(name, over, n_pre, taped):
     """The reverse with symmetry planes (specular pushes, mirror-parity
-    ghosts) and far-field sides (anti-bounce-back stores, odd psi and U
-    ghosts), with the stencil results from the step's tape or recomputed with
-    the same ghosts, against the oracle's reverse mode, bar 1e-9 as the other
-    one-step adjoints; NS and phi on D2Q9 cover the diagonal reflections."""
+    ghosts), far-field sides (anti-bounce-back stores, odd psi and U ghosts)
+    and variable heat properties (theta and the heat rate through phi), with
+    the stencil results from the step's tape or recomputed with the same
+    ghosts, against the oracle's reverse mode, bar 1e-9 as the other one-step
+    adjoints; NS and phi on D2Q9 cover the diagonal reflections."""
     import paper_2407_01651_amd as pfl
     w = _w(over)
     osim = OracleSim(OracleParams.from_workload(w))
@@ -259,26 +266,12 @@ def test_adjoint_with_symmetry_planes_and_far_field_sides(name, over, n_pre, tap
     sim.close()
 
 
-def test_adjoint_rejects_variable_heat_properties():
-    """The adjoint is built for matched heat properties: with gas ratios
-    other than 1 it reports PFL_E_UNSUPPORTED instead of computing."""
+@pytest.mark.parametrize("fields,heat", [(workloads.FIELDS_ALL, {}), (("psi", "c"), {}),
+                                         (workloads.FIELDS_ALL, dict(th_rho_g=0.6, th_cp_g=0.8, th_k_g=1.5))],
+                         ids=["all", "alloy", "all_varheat"])
+def test_init_adjoint_matches_oracle(fields, heat):
     import paper_2407_01651_amd as pfl
-    w = _w(dict(nx=20, ny=14, seed=31))
-    w.update(th_rho_g=0.5)
-    sim = pfl.Sim(w, adjoint=True)
-    sim.init_fields()
-    lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=torch.float64, device="cuda")
-    out = torch.empty_like(lam)
-    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
-    with pytest.raises(Exception, match="matched heat properties"):
-        sim.step_backward(lam, out, dp)
-    sim.close()
-
-
-@pytest.mark.parametrize("fields", [workloads.FIELDS_ALL, ("psi", "c")], ids=["all", "alloy"])
-def test_init_adjoint_matches_oracle(fields):
-    import paper_2407_01651_amd as pfl
-    w = _w(dict(nx=30, ny=26, seed=39, fields=fields))
+    w = _w(dict(nx=30, ny=26, seed=39, fields=fields, **heat))
     if "phi" in fields:
         w["bubbles"].append(dict(x=5.0, y=20.0, z=0.0, r=3.5))
     else:
