@@ -512,7 +512,7 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_dx += ao * (1 - CT(0.5) * s1) * 3 * w * cx;
       a_dy += ao * (1 - CT(0.5) * s1) * 3 * w * cy;
       // the heat rate (per node with variable k_T)
-      a_th_s1 -= ao * CT(0.5) * ((cx * jhx + cy * jhy) + 3 * w * (cx * dx_ + cy * dy_));
+      if (K.varheat) a_th_s1 -= ao * CT(0.5) * ((cx * jhx + cy * jhy) + 3 * w * (cx * dx_ + cy * dy_));
       if (i == 0) { a_H += ao; a_theta += ao * (w - 1); }
       else { a_theta += ao * w; a_Hvx += ao * 3 * w * cx; a_Hvy += ao * 3 * w * cy; }
     }
