@@ -223,8 +223,9 @@ def time_cpu(w, steps):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py: the library steps one GPU's domain; runs on more than one GPU are not "
+              "supported (one process per GPU with a halo exchange is the intended sharding).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads
