@@ -112,10 +112,13 @@ __global__ __launch_bounds__(256) void adj_init_sum_kernel(long long N, const do
 }  // namespace
 
 
-size_t adj_scratch_bytes(long long N, int store) {
+size_t adj_scratch_bytes(int nx, int ny, int store) {
+  const long long N = (long long)nx * ny;
   const size_t elem = store == 0 ? sizeof(double) : sizeof(float);
+  // partial slots: one per 256 nodes, or one per tile of the fused flow pass
   const size_t nb = (size_t)((N + 255) / 256);
-  const size_t bytes = part_offset(N, elem) + 3 * nb * sizeof(double);
+  const size_t tiles = (size_t)((nx + TX - 1) / TX) * (size_t)((ny + TY - 1) / TY);
+  const size_t bytes = part_offset(N, elem) + 3 * (nb > tiles ? nb : tiles) * sizeof(double);
   // the initial-state adjoint uses four FP64 planes of the same buffer
   const size_t init = 4 * (size_t)N * sizeof(double);
   return bytes > init ? bytes : init;

@@ -10,19 +10,20 @@
 // i becomes the node-form population i of x + c_i at the next step (or of the
 // node itself in direction opp(i) across a wall).
 //
-// Three passes per step, in the forward's compute type (FP64 for FP64
-// storage, FP32 otherwise); the adjoint state and the scratch planes are held
-// in that type, the parameter-gradient sums in FP64:
+// Two passes per step, in the forward's compute type (FP64 for FP64 storage,
+// FP32 otherwise); the adjoint state and the scratch planes are held in that
+// type, the parameter-gradient sums in FP64:
 //  R1 (tile kernel): recompute the forward step of the tile as the forward
 //     kernel does, then reverse the node-local phase (collisions, forces,
 //     anisotropy, kinetics) by hand.  Writes the adjoints of the node's own
 //     populations and history, of its moments, and of the stencil inputs it
 //     read (grad phi, lap phi, grad psi, grad U, the mass-flux force F_m).
-//  R2 (nodes, flow with bubbles only): the transposed divergence gives the
-//     adjoint of X = D_phi (x) v0 at each node; reverse X and the flow
-//     quantities behind it.
-//  R3 (nodes): the transposed stencils turn the stencil-input adjoints into
-//     moment adjoints and U = U(C, psi; k) is reversed.
+//  R2 (flow with bubbles only): the transposed divergence gives the adjoint
+//     of X = D_phi (x) v0 at each node; reverse X and the flow quantities
+//     behind it.  Computed on the tile of R3 and its ring into LDS.
+//  R3: the transposed stencils turn the stencil-input adjoints into moment
+//     adjoints and U = U(C, psi; k) is reversed (a tile pass with R2, a node
+//     pass otherwise).
 // The moment adjoints reach every population of a set (the momentum ones
 // through c_i), and the time-stretched store's reads of a neighbour's old
 // value reach that neighbour's population: lambda^n is the populations part R1
@@ -963,18 +964,20 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
 }
 
 // ------------------------------------------------------------------- R2
-// Adjoint of X = D_phi (x) v0 at every node, from the transposed divergence of
-// the mass-flux force adjoints, reversed through the node's flow quantities.
+// Adjoint of X = D_phi (x) v0 at node n, from the transposed divergence of
+// the mass-flux force adjoints, reversed through the node's flow quantities:
+// the increments of the stencil-input and moment adjoints at n.
 template <class CT>
-__global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __restrict__ S) {
+struct FlowDelta {
+  CT gx, gy, lap, phi, psi, jx, jy;
+};
+template <class CT>
+__device__ __forceinline__ FlowDelta<CT> flow_delta(const DevParams& P, const CT* __restrict__ S, uint32_t n,
+                                                    int x, int y) {
   using LN = Lat<9>;
-  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (n0 >= P.N) return;
-  const uint32_t n = (uint32_t)n0;
   const long long N = P.N;
-  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
   const KP<CT>& K = kp<CT>(P);
-  auto pl = [&](int k) -> CT* { return S + (long long)k * N; };
+  auto pl = [&](int k) -> const CT* { return S + (long long)k * N; };
   // X-bar_ab(z) = sum over readers 3 drho w c'_a Fm-bar_b(reader) (odd ghosts)
   CT aX0 = CT(0), aX1 = CT(0), aX2 = CT(0), aX3 = CT(0);
 #pragma unroll
@@ -1012,14 +1015,16 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __
   const CT a_v0x = aX0 * Dx + aX2 * Dy, a_v0y = aX1 * Dx + aX3 * Dy;
   // v0 = s (j + (Fs + Fb)/2)
   const CT a_s = a_v0x * ux + a_v0y * uy;
-  const CT a_jx = sc * a_v0x, a_jy = sc * a_v0y;
+  FlowDelta<CT> d;
+  d.jx = sc * a_v0x;
+  d.jy = sc * a_v0y;
   const CT a_Fsx = CT(0.5) * sc * a_v0x, a_Fsy = CT(0.5) * sc * a_v0y, a_Fby = CT(0.5) * sc * a_v0y;
   const CT a_chi = -a_s / rho;
   CT a_rho = -a_s * (CT(1) - chi) / (rho * rho) - K.g * a_Fby;
   const CT a_mu = K.k_s * (a_Fsx * gx + a_Fsy * gy);
   CT a_gx = a_Fsx * K.k_s * mu + K.M_phi * a_Dx;
   CT a_gy = a_Fsy * K.k_s * mu + K.M_phi * a_Dy;
-  const CT a_lap = -K.Wphi2 * a_mu;
+  d.lap = -K.Wphi2 * a_mu;
   CT a_phi = a_mu * (CT(0.5) * (CT(1) - CT(6) * phi + CT(6) * phi * phi) + CT(2) * K.beta_inter * ps1 * ps1);
   CT a_psi = a_mu * (CT(-4) * K.beta_inter * om * ps1);
   // D = M (g - sharp n)
@@ -1032,43 +1037,50 @@ __global__ __launch_bounds__(256) void adj_flow_kernel(const DevParams P, CT* __
   a_gy -= a_inv * gy * inv * inv * inv;
   a_phi += a_rho * K.drho;
   if (h > CT(0) && h < CT(1)) a_psi += CT(0.5) * a_chi;
-  at_node(pl(AS_GPHX), n) += a_gx;
-  at_node(pl(AS_GPHY), n) += a_gy;
-  at_node(pl(AS_LAP), n) += a_lap;
-  at_node(pl(AM_PHI), n) += a_phi;
-  at_node(pl(AM_PSI), n) += a_psi;
-  at_node(pl(AM_JX), n) += a_jx;
-  at_node(pl(AM_JY), n) += a_jy;
+  d.gx = a_gx; d.gy = a_gy; d.phi = a_phi; d.psi = a_psi;
+  return d;
 }
 
 // ------------------------------------------------------------------- R3
-// Writes the moment terms of lambda^n to the P_ planes and the per-block
-// parameter partials.
-template <int FIELDS, int QP, class CT>
-__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT* __restrict__ S,
-                                                           double* __restrict__ part, int accumulate) {
+// Transposed stencils and U(C, psi; k) at node n: writes the moment terms of
+// lambda^n to the P_ planes and the block's parameter partials (slot `slot`).
+// Dl supplies the R2 increments not yet in the planes: at the node (own) and
+// at the reader of direction i (at), or nothing (Dl::active false).
+struct NoDelta {
+  static constexpr bool active = false;
+};
+template <int FIELDS, int QP, class CT, class Dl>
+__device__ __forceinline__ void assemble_node(const DevParams& P, CT* __restrict__ S, uint32_t n, int x, int y,
+                                              bool live, double* __restrict__ part, int slot, int accumulate,
+                                              const Dl& dl) {
   constexpr bool NS = FIELDS & F_NS, PHI = FIELDS & F_PHI, PSI = FIELDS & F_PSI;
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   using LN = Lat<9>;
-  using LS = Lat<5>;
-  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
-  const bool live = n0 < P.N;
-  const uint32_t n = (uint32_t)(live ? n0 : P.N - 1);
   const long long N = P.N;
-  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
   const KP<CT>& K = kp<CT>(P);
   auto pl = [&](int k) -> const CT* { return S + (long long)k * N; };
+  CT am_phi = at_node(pl(AM_PHI), n), as_lap = at_node(pl(AS_LAP), n), am_psi = at_node(pl(AM_PSI), n);
+  CT am_jx = at_node(pl(AM_JX), n), am_jy = at_node(pl(AM_JY), n);
+  if constexpr (Dl::active) {
+    const FlowDelta<CT> d = dl.own();
+    am_phi += d.phi; as_lap += d.lap; am_psi += d.psi; am_jx += d.jx; am_jy += d.jy;
+  }
   // transposed isotropic stencils (gradient 3 sum w c f, Laplacian 6 sum w (f - f0))
-  CT a_phi = at_node(pl(AM_PHI), n) - CT(6.0 * (1.0 - LN::w[0])) * at_node(pl(AS_LAP), n);
-  CT a_psi = at_node(pl(AM_PSI), n), a_U = at_node(pl(AM_U), n);
+  CT a_phi = am_phi - CT(6.0 * (1.0 - LN::w[0])) * as_lap;
+  CT a_psi = am_psi, a_U = at_node(pl(AM_U), n);
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const Reader r = reader_of(P, x, y, LN::c[i][0], LN::c[i][1]);
     const CT w3 = CT(3.0 * LN::w[i]), w6 = CT(6.0 * LN::w[i]);
     const CT cx = CT(r.cx), cy = CT(r.cy);
-    if constexpr (PHI)
-      a_phi += w3 * (cx * at_node(pl(AS_GPHX), r.node) + cy * at_node(pl(AS_GPHY), r.node)) +
-               w6 * at_node(pl(AS_LAP), r.node);
+    if constexpr (PHI) {
+      CT gpx = at_node(pl(AS_GPHX), r.node), gpy = at_node(pl(AS_GPHY), r.node), lp = at_node(pl(AS_LAP), r.node);
+      if constexpr (Dl::active) {
+        const FlowDelta<CT> d = dl.at(i);
+        gpx += d.gx; gpy += d.gy; lp += d.lap;
+      }
+      a_phi += w3 * (cx * gpx + cy * gpy) + w6 * lp;
+    }
     // psi and U ghosts across a far-field side are odd about their far-field values
     const CT wf = w3 * CT(r.fsign);
     if constexpr (PSI) a_psi += wf * (cx * at_node(pl(AS_GPSX), r.node) + cy * at_node(pl(AS_GPSY), r.node));
@@ -1105,7 +1117,7 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT
     // accumulate: a sweep over several steps adds each block's partials in
     // step order (each block owns its slots), summed once at the end
     if (threadIdx.x == 0) {
-      double* pb = part + 3 * blockIdx.x;
+      double* pb = part + 3 * slot;
       pb[0] = (accumulate ? pb[0] : 0.0) + s_e[0];
       pb[1] = (accumulate ? pb[1] : 0.0) + s_k[0];
       pb[2] = (accumulate ? pb[2] : 0.0) + s_o[0];
@@ -1113,11 +1125,67 @@ __global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT
   }
   if (!live) return;
   auto put = [&](int plane, CT v) { at_node(S + (long long)plane * N, n) = v; };
-  if constexpr (NS) { put(P_JX, at_node(pl(AM_JX), n)); put(P_JY, at_node(pl(AM_JY), n)); }
+  if constexpr (NS) { put(P_JX, am_jx); put(P_JY, am_jy); }
   if constexpr (PHI) put(P_PHI, a_phi);
   if constexpr (PSI) put(P_PSI, a_psi);
   if constexpr (CC) put(P_C, a_C);
   if constexpr (TH) put(P_H, at_node(pl(AM_H), n));
+}
+
+template <int FIELDS, int QP, class CT>
+__global__ __launch_bounds__(256) void adj_assemble_kernel(const DevParams P, CT* __restrict__ S,
+                                                           double* __restrict__ part, int accumulate) {
+  const long long n0 = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool live = n0 < P.N;
+  const uint32_t n = (uint32_t)(live ? n0 : P.N - 1);
+  const int x = (int)(n % (uint32_t)P.nx), y = (int)(n / (uint32_t)P.nx);
+  assemble_node<FIELDS, QP, CT>(P, S, n, x, y, live, part, (int)blockIdx.x, accumulate, NoDelta{});
+}
+
+// R2 and R3 in one tile pass (flow with bubbles): the R2 increments of the
+// tile and its ring are computed into LDS (a ring slot holds the node its
+// coordinates map to: periodic wrap, or the mirror node across a wall,
+// symmetry plane or far-field side, which is the node the transposed stencil
+// reads), then R3 runs on the tile; the increments are never written.
+template <class CT>
+struct TileDelta {
+  static constexpr bool active = true;
+  const CT (*s)[TY + 2][TX + 2];
+  int ly, lx;
+  __device__ FlowDelta<CT> get(int yy, int xx) const {
+    FlowDelta<CT> d;
+    d.gx = s[0][yy][xx]; d.gy = s[1][yy][xx]; d.lap = s[2][yy][xx]; d.phi = s[3][yy][xx];
+    d.psi = s[4][yy][xx]; d.jx = s[5][yy][xx]; d.jy = s[6][yy][xx];
+    return d;
+  }
+  __device__ FlowDelta<CT> own() const { return get(ly + 1, lx + 1); }
+  // the reader of direction i sits at x - c_i
+  __device__ FlowDelta<CT> at(int i) const { return get(ly + 1 - Lat<9>::c[i][1], lx + 1 - Lat<9>::c[i][0]); }
+};
+template <int FIELDS, int QP, class CT>
+__global__ __launch_bounds__(NT) void adj_flow_assemble_kernel(const DevParams P, CT* __restrict__ S,
+                                                               double* __restrict__ part, int accumulate) {
+  constexpr int RX = TX + 2, RY = TY + 2;
+  __shared__ CT s_d[7][RY][RX];
+  const int tid = threadIdx.x;
+  const int gtx = (P.nx + TX - 1) / TX;
+  const int lt = logical_tile(blockIdx.x, gtx * ((P.ny + TY - 1) / TY));
+  const int bx0 = (lt % gtx) * TX, by0 = (lt / gtx) * TY;
+  for (int k = tid; k < RX * RY; k += NT) {
+    const int rx = k % RX, ry = k / RX;
+    const int mx = map_coord(bx0 + rx - 1, P.nx, P.wall[0]), my = map_coord(by0 + ry - 1, P.ny, P.wall[1]);
+    const FlowDelta<CT> d = flow_delta<CT>(P, S, (uint32_t)my * (uint32_t)P.nx + (uint32_t)mx, mx, my);
+    s_d[0][ry][rx] = d.gx; s_d[1][ry][rx] = d.gy; s_d[2][ry][rx] = d.lap; s_d[3][ry][rx] = d.phi;
+    s_d[4][ry][rx] = d.psi; s_d[5][ry][rx] = d.jx; s_d[6][ry][rx] = d.jy;
+  }
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = bx0 + lx, y = by0 + ly;
+  const bool live = x < P.nx && y < P.ny;
+  const int xc = live ? x : 0, yc = live ? y : 0;
+  const uint32_t n = (uint32_t)yc * (uint32_t)P.nx + (uint32_t)xc;
+  TileDelta<CT> dl{(const CT(*)[RY][RX])s_d, ly, lx};
+  assemble_node<FIELDS, QP, CT>(P, S, n, xc, yc, live, part, (int)blockIdx.x, accumulate, dl);
 }
 
 // Zeroes the planes of open moment terms (P_ and A_OLD): lambda^{n+1} is
@@ -1221,6 +1289,7 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
   const long long N = P.N;
   const unsigned tiles = (unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY));
   const unsigned nb = (unsigned)((N + 255) / 256);
+  constexpr bool FLOWX = (FIELDS & F_NS) && (FIELDS & F_PHI);
   // the reverse runs in the forward's compute type, which is also the type
   // of the adjoint state and of the scratch planes
   using RT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
@@ -1250,12 +1319,12 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
       hipLaunchKernelGGL((adj_local_kernel<FIELDS, QP, ST, HT, RT, false>), dim3(tiles), dim3(NT), 0, s, P,
                          (const typename Store<ST>::raw*)fin, (const HT*)hist, tape, lam_in, lam_out, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if constexpr ((FIELDS & F_NS) && (FIELDS & F_PHI)) {
-      hipLaunchKernelGGL((adj_flow_kernel<RT>), dim3(nb), dim3(256), 0, s, P, S);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, S, part,
-                       o.accumulate ? 1 : 0);
+    if constexpr (FLOWX)   // R2 and R3 in one tile pass, partials per tile
+      hipLaunchKernelGGL((adj_flow_assemble_kernel<FIELDS, QP, RT>), dim3(tiles), dim3(NT), 0, s, P, S, part,
+                         o.accumulate ? 1 : 0);
+    else
+      hipLaunchKernelGGL((adj_assemble_kernel<FIELDS, QP, RT>), dim3(nb), dim3(256), 0, s, P, S, part,
+                         o.accumulate ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (!o.pend_out) {
@@ -1264,7 +1333,7 @@ hipError_t adj_step_t(const DevParams& P, const void* fin, const void* hist, con
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (!o.sum) return hipSuccess;
-  hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)nb, part, dparams);
+  hipLaunchKernelGGL(adj_param_sum_kernel, dim3(1), dim3(256), 0, s, (int)(FLOWX ? tiles : nb), part, dparams);
   return hipGetLastError();
 }
 

@@ -159,7 +159,7 @@ int pfl_query_sizes(const pfl_params* p, pfl_sizes* out) {
   out->macros_bytes = L.macros_bytes;
   out->state_bytes = L.state_bytes;
   out->reduce_bytes = L.reduce_bytes;
-  out->adj_bytes = p->dim == 2 ? adj_scratch_bytes(L.N, p->store) : 0;
+  out->adj_bytes = p->dim == 2 ? adj_scratch_bytes(p->nx, p->ny, p->store) : 0;
   out->raw_bytes = L.pops_bytes + L.hist_bytes;
   out->tape_bytes = p->dim == 2 ? (size_t)TAPE_PLANES * L.N * (p->store == 0 ? sizeof(double) : sizeof(float)) : 0;
   g_err.clear();

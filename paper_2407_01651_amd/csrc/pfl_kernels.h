@@ -27,10 +27,10 @@ inline hipError_t launch_step(const DevParams& P, int fields, int store, const v
 // Adjoint of one 2D step at the state fin/hist (node-form adjoints lam_in ->
 // lam_out in the compute type: FP64 for FP64 storage, FP32 otherwise;
 // parameter gradient accumulated into the FP64 dparams[0..1]) and of the
-// initial state (dparams[1..]).  scratch holds adj_scratch_bytes(N, store).
+// initial state (dparams[1..]).  scratch holds adj_scratch_bytes(nx, ny, store).
 // tape: the step's TAPE_PLANES stencil planes written by the forward step
 // (P.tape), or null to redo the stencils.
-size_t adj_scratch_bytes(long long N, int store);
+size_t adj_scratch_bytes(int nx, int ny, int store);
 bool adj2d_supported(int fields);
 // How one reverse step fits into a sweep over many.
 struct AdjOpts {
