@@ -41,6 +41,32 @@ def test_corner_dendrite_stays_symmetric_about_the_diagonal(name, steps):
     sim.close()
 
 
+def test_corner_dendrite_3d_stays_symmetric_under_axis_permutations():
+    """The 3D corner (symmetry planes low, far-field sides high on all three
+    axes, grain angle 0): the cubic anisotropy and the boundaries are
+    invariant under permutations of x, y, z, so psi and theta stay so to
+    rounding (FP64, 600 steps on 96^3); the seed grows."""
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("corner_thermosolutal3d_96")
+    sim = pfl.Sim(w, store="f64")
+    sim.init_fields()
+    s0 = solid_fraction(sim.macros()["psi"])
+    sim.step(600)
+    m = sim.macros()
+    assert sim.reduce()["nonfinite"] == 0
+    errs = {}
+    for k in ("psi", "theta"):
+        f = m[k].double().cpu()                          # [z][y][x]
+        den = float(f.abs().max())
+        errs[k] = max(float((f - f.permute(0, 2, 1)).abs().max()),
+                      float((f - f.permute(2, 1, 0)).abs().max())) / den
+    s1 = solid_fraction(m["psi"])
+    log(f"[setups] corner 3D 600 steps: permutation {errs}, solid {s0:.4g} -> {s1:.4g}")
+    assert max(errs.values()) < 1e-10, errs
+    assert s1 > s0
+    sim.close()
+
+
 def test_bubble_dendrites_geometry_runs():
     import paper_2407_01651_amd as pfl
     w = workloads.get("bubble_dendrites2d_200x400")

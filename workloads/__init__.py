@@ -255,6 +255,18 @@ def corner_thermosolutal2d_512():
     return c
 
 
+def corner_thermosolutal3d_96():
+    """The corner set-up of Sec. 3.4 in 3D, 96^3: symmetry planes on the three
+    low sides, far-field values on the three high sides, a seed of radius
+    10 dx in the corner, Le = 1, k 0.15, eps4 0.02, Omega 0.55."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="corner_thermosolutal3d_96", dim=3, nx=96, ny=96, nz=96, phi_q=7,
+             periodic=(False, False, False), symmetric=("lo", "lo", "lo"), farfield=("hi", "hi", "hi"),
+             fields=("psi", "c", "theta"), eps4=0.02, Le=1.0, U0=0.0, theta0=-0.55,
+             seeds=[dict(x=-0.5, y=-0.5, z=-0.5, r=10.0, angle=0.0)], bubbles=[], steps=5000)
+    return c
+
+
 def bubble_dendrites2d_200x400():
     """The geometry of the coupled runs of Sec. 4: 200 x 400, symmetry planes
     on both x sides, a no-flux bottom and a far-field top, seeds of radius
@@ -300,6 +312,7 @@ CONFIGS = {
     "corner_thermal2d_256": corner_thermal2d_256,
     "corner_thermosolutal2d_512": corner_thermosolutal2d_512,
     "bubble_dendrites2d_200x400": bubble_dendrites2d_200x400,
+    "corner_thermosolutal3d_96": corner_thermosolutal3d_96,
     "alloy2d_1024": alloy2d_1024,
     "coupled2d_2048": coupled2d_2048,
     "coupled2d_2048_q9": coupled2d_2048_q9,
