@@ -18,6 +18,19 @@ struct StepTile {
   static constexpr int X = 32;
   static constexpr int Y = ((FIELDS & F_NS) && (FIELDS & F_PHI)) ? 8 : 4;
   static constexpr int N = X * Y;
+  // Minimum waves per SIMD asked of the register allocator.  The FP32-compute
+  // step without flow, bubble phase or heat needs 64 VGPRs but over 100 SGPRs,
+  // which would hold it at 7 waves; asking for 8 moves a few SGPRs into VGPR
+  // lanes (no scratch) and gives 8 (alloy FP32 step 43.4k -> 46.0k MLUPS on
+  // 1024^2).  Larger kernels spill to scratch when pushed and get slower
+  // (coupled FP16 at 5 instead of 4 waves: 17.6k -> 14.0k), so they keep
+  // the default (1 = no minimum).
+  template <class ST, class CT, bool SYM>
+  static constexpr int waves() {
+    if (SYM) return 1;
+    if (sizeof(CT) == 4 && !(FIELDS & (F_NS | F_PHI | F_TH))) return 8;
+    return 1;
+  }
 };
 
 // Pull the pre-collision population deviations of one set at node (x, y), general

@@ -29,7 +29,9 @@
 namespace pfl {
 
 template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM>
-__global__ __launch_bounds__(StepTile<FIELDS>::N) void step2d_kernel(const DevParams P,
+__global__ __launch_bounds__(StepTile<FIELDS>::N)
+__attribute__((amdgpu_waves_per_eu(StepTile<FIELDS>::template waves<ST, CT, SYM>())))
+void step2d_kernel(const DevParams P,
                                                     const typename Store<ST>::raw* __restrict__ fin,
                                                     typename Store<ST>::raw* __restrict__ fout,
                                                     HT* hist, double* __restrict__ mout,
