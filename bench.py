@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward cost ratio on the 512^2 adjoint workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--write-policy", default="auto", choices=("auto", "cached", "stream"),
+                    help="cache policy of the step's stores (auto: streaming in 2D FP64/FP32 when the state exceeds the "
+                         "256 MiB last-level cache)")
     ap.add_argument("--adjoint-steps", type=int, default=None,
                     help="shorten the adjoint workload (profiling runs); default its 2000 steps")
     ap.add_argument("--cpu-steps", type=int, default=20)
@@ -99,10 +102,10 @@ def algorithmic_bytes(w, store):
     return 2 * q * sp + 2 * nh * sh
 
 
-def time_gpu(w, store, steps, warmup, rounding=None):
+def time_gpu(w, store, steps, warmup, rounding=None, write_policy="auto"):
     import torch
     import paper_2407_01651_amd as pfl
-    sim = pfl.Sim(w, store=store, rounding=rounding)
+    sim = pfl.Sim(dict(w, write_policy=write_policy), store=store, rounding=rounding)
     sim.init_fields()
     sim.step(warmup)
     stream = torch.cuda.current_stream()
@@ -239,13 +242,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_run = time_gpu(w, a.store, a.steps, a.warmup, a.rounding)
+    main_run = time_gpu(w, a.store, a.steps, a.warmup, a.rounding, a.write_policy)
     variants = {}
     for st in [s for s in a.also.split(",") if s and s != a.store]:
-        variants[st] = time_gpu(w, st, a.steps, a.warmup, a.rounding)
+        variants[st] = time_gpu(w, st, a.steps, a.warmup, a.rounding, a.write_policy)
     for item in [s for s in a.extra.split(",") if s]:
         cfg, st = item.split(":")
-        variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding)
+        variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding, a.write_policy)
     adj = None if a.no_adjoint else time_adjoint(steps=a.adjoint_steps)
     cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
     n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)

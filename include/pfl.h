@@ -74,6 +74,13 @@ enum { PFL_F64 = 0, PFL_F32 = 1, PFL_F16 = 2, PFL_BF16 = 3 };
  * NaN and Inf are stored unchanged.  Nearest: the hardware conversion
  * (round to nearest, ties to even). */
 enum { PFL_ROUND_STOCHASTIC = 0, PFL_ROUND_NEAREST = 1 };
+/* Cache policy of the step's population and history stores.  AUTO streams
+   them past the last-level cache (non-temporal writes) in 2D with FP64 or
+   FP32 storage when the state read plus written per step exceeds its 256 MiB,
+   and caches them otherwise (16-bit storage and 3D tiles write partial
+   128-byte lines per wave, which streaming makes slower); the other two force
+   one policy.  Results are identical under every policy. */
+enum { PFL_WRITE_AUTO = 0, PFL_WRITE_CACHED = 1, PFL_WRITE_STREAM = 2 };
 
 /* Macro-field planes written by pfl_get_macros (node form, in this order). */
 enum { PFL_M_PHI = 0, PFL_M_PSI, PFL_M_C, PFL_M_THETA, PFL_M_U, PFL_M_P,
@@ -120,6 +127,7 @@ typedef struct {
                                equation (Appendix B heat model; each property linear in phi,
                                solid = liquid, Sec. 2.2); 1, 1, 1 = matched properties.  The
                                scheme is conditionally stable where rho c_p < 1. */
+  int write_policy;         /* PFL_WRITE_AUTO (0, default), PFL_WRITE_CACHED, PFL_WRITE_STREAM */
 } pfl_params;
 
 /* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */

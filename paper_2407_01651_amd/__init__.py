@@ -28,6 +28,7 @@ NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
 F64, F32, F16, BF16 = 0, 1, 2, 3
 STORES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 ROUNDINGS = {"stochastic": 0, "nearest": 1}
+WRITE_POLICIES = {"auto": 0, "cached": 1, "stream": 2}
 FIELD_BITS = {"ns": NS, "phi": PHI, "psi": PSI, "c": CONC, "theta": THETA}
 MACROS = ("phi", "psi", "C", "theta", "U", "p", "vx", "vy", "vz")
 
@@ -45,7 +46,8 @@ class Params(ct.Structure):
                 ("rounding", ct.c_int)] + \
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
-                                          "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")]
+                                          "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")] + \
+               [("write_policy", ct.c_int)]
 
 
 class Seed(ct.Structure):
@@ -112,9 +114,11 @@ def _check(rc):
     return rc
 
 
-def make_params(w, store=None, rounding=None):
+def make_params(w, store=None, rounding=None, write_policy=None):
     """pfl_params from a workload description (primary inputs only).
-    rounding: "stochastic" (default) or "nearest", for 16-bit storage."""
+    rounding: "stochastic" (default) or "nearest", for 16-bit storage;
+    write_policy: "auto" (default), "cached" or "stream" (cache policy of the
+    step's stores, no effect on results)."""
     p = Params()
     p.abi_version = ABI_VERSION
     p.struct_size = ct.sizeof(Params)
@@ -144,6 +148,7 @@ def make_params(w, store=None, rounding=None):
         setattr(p, n, float(w[n]))
     for n in ("th_rho_g", "th_cp_g", "th_k_g"):
         setattr(p, n, float(w.get(n, 1.0)))
+    p.write_policy = WRITE_POLICIES[write_policy or w.get("write_policy", "auto")]
     return p
 
 

@@ -164,6 +164,7 @@ struct DevParams {
   int fast;                    // byte offsets of every buffer fit in 32 bits
   const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
+  int nt;                      // step stores non-temporal (streamed past the last-level cache)
   uint32_t step_ctr;           // step counter, part of the rounding key
   void* tape;                  // 2D: stencil results written here when set (TAPE_PLANES planes)
   KP<double> kd;
@@ -214,31 +215,42 @@ struct half_dev { __half v; };
 struct bf16_dev { __hip_bfloat16 v; };
 
 template <class ST> struct Store;
+// Storage forms: ld/st convert between the stored value and the compute type;
+// enc / enc_sr give the stored bits (16-bit forms: round to nearest /
+// stochastically with the random bits r), written by the step's stores.
 template <> struct Store<double> {
   using raw = double;
+  using bits = double;
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = (double)v; }
+  template <class CT> __device__ static bits enc(CT v) { return (double)v; }
 };
 template <> struct Store<float> {
   using raw = float;
+  using bits = float;
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = (float)v; }
+  template <class CT> __device__ static bits enc(CT v) { return (float)v; }
 };
 template <> struct Store<half_dev> {
   using raw = __half;
+  using bits = unsigned short;
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)__half2float(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2half_rn((float)v); }
-  template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
-    *p = __float2half_rn(__uint_as_float(sround_bits<13>((float)v, r)));
+  template <class CT> __device__ static bits enc(CT v) { return __half_as_ushort(__float2half_rn((float)v)); }
+  template <class CT> __device__ static bits enc_sr(CT v, uint32_t r) {
+    return __half_as_ushort(__float2half_rn(__uint_as_float(sround_bits<13>((float)v, r))));
   }
 };
 template <> struct Store<bf16_dev> {
   using raw = __hip_bfloat16;
+  using bits = unsigned short;
   template <class CT> __device__ static CT ld(const raw* p) { return (CT)__bfloat162float(*p); }
   template <class CT> __device__ static void st(raw* p, CT v) { *p = __float2bfloat16((float)v); }
-  template <class CT> __device__ static void st_sr(raw* p, CT v, uint32_t r) {
+  template <class CT> __device__ static bits enc(CT v) { return __bfloat16_as_ushort(__float2bfloat16((float)v)); }
+  template <class CT> __device__ static bits enc_sr(CT v, uint32_t r) {
     // the low 16 bits are zero after rounding: the top half is the BF16 value
-    *p = __ushort_as_bfloat16((unsigned short)(sround_bits<16>((float)v, r) >> 16));
+    return (unsigned short)(sround_bits<16>((float)v, r) >> 16);
   }
 };
 

@@ -28,7 +28,7 @@
 
 namespace pfl {
 
-template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM>
+template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM, bool STREAM>
 __global__ __launch_bounds__(StepTile<FIELDS>::N)
 __attribute__((amdgpu_waves_per_eu(StepTile<FIELDS>::template waves<ST, CT, SYM>())))
 void step2d_kernel(const DevParams P,
@@ -423,11 +423,11 @@ void step2d_kernel(const DevParams P,
                                         : fout + (long long)plane * N + idx;
     uint32_t r = 0u;
     if constexpr (LOWP) r = rb.bits(i);
-    store_pop<ST, CT>(P, p, v, r);
+    store_pop<ST, CT, STREAM>(P, p, v, r);
   };
   auto hst = [&](int plane, CT v) {
-    if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)v;
-    else hist[(long long)plane * N + idx] = (HT)v;
+    HT* q = P.fast ? (HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) : hist + (long long)plane * N + idx;
+    put<STREAM, HT>(q, (HT)v);
   };
 
   // ---- NS collision: f* = feq + F/2 + (1 - s_nu) P_s (f - feq + F/2),
@@ -643,12 +643,15 @@ hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void
   constexpr int STX = StepTile<FIELDS>::X, STY = StepTile<FIELDS>::Y, SNT = StepTile<FIELDS>::N;
   dim3 grid(((P.nx + STX - 1) / STX) * ((P.ny + STY - 1) / STY));
   using raw = typename Store<ST>::raw;
-  if (P.sym || P.far)
-    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, true>), grid, dim3(SNT), 0, s, P,
-                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
-  else
-    hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, false>), grid, dim3(SNT), 0, s, P,
-                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  const bool sym = P.sym || P.far;
+#define PFL_LAUNCH2(SYMV, NTV)                                                                  \
+  hipLaunchKernelGGL((step2d_kernel<FIELDS, QP, ST, HT, CT, SYMV, NTV>), grid, dim3(SNT), 0, s, P, \
+                     (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode)
+  if (sym && P.nt) PFL_LAUNCH2(true, true);
+  else if (sym) PFL_LAUNCH2(true, false);
+  else if (P.nt) PFL_LAUNCH2(false, true);
+  else PFL_LAUNCH2(false, false);
+#undef PFL_LAUNCH2
   return hipGetLastError();
 }
 

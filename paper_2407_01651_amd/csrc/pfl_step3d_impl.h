@@ -187,7 +187,7 @@ __device__ __forceinline__ void flow_node3(const KP<CT>& K, const CT* s_phi, con
   }
 }
 
-template <int FIELDS, class ST, class HT, class CT, bool SYM>
+template <int FIELDS, class ST, class HT, class CT, bool SYM, bool STREAM>
 // FP32 compute: ask for three waves per SIMD (measured 12% faster on the
 // 256^3 FP16 workload than two, despite a few spilled registers)
 __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d_kernel(const DevParams P,
@@ -581,11 +581,11 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
                       : fout + (long long)plane * N + idx;
     uint32_t r = 0u;
     if constexpr (LOWP) r = rb.bits(i);
-    store_pop<ST, CT>(P, ptr, val, r);
+    store_pop<ST, CT, STREAM>(P, ptr, val, r);
   };
   auto hst = [&](int plane, CT val) {
-    if (P.fast) *(HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) = (HT)val;
-    else hist[(long long)plane * N + idx] = (HT)val;
+    HT* q = P.fast ? (HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) : hist + (long long)plane * N + idx;
+    put<STREAM, HT>(q, (HT)val);
   };
 
   // ---- NS collision: f* = feq + F/2 + (1 - s_nu) P_s (f - feq + F/2), P_s
@@ -835,12 +835,15 @@ hipError_t launch_step3d_t(const DevParams& P, const void* fin, void* fout, void
   const long long tiles = (long long)((P.nx + T::TX - 1) / T::TX) * ((P.ny + T::TY - 1) / T::TY) *
                           ((P.nz + T::TZ - 1) / T::TZ);
   using raw = typename Store<ST>::raw;
-  if (P.sym || P.far)
-    hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, true>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
-                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
-  else
-    hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, false>), dim3((unsigned)tiles), dim3(T::NT), 0, s, P,
-                       (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode);
+  const bool sym = P.sym || P.far;
+#define PFL_LAUNCH3(SYMV, NTV)                                                                    \
+  hipLaunchKernelGGL((step3d_kernel<FIELDS, ST, HT, CT, SYMV, NTV>), dim3((unsigned)tiles), dim3(T::NT), 0, s, \
+                     P, (const raw*)fin, (raw*)fout, (HT*)hist, mout, mode)
+  if (sym && P.nt) PFL_LAUNCH3(true, true);
+  else if (sym) PFL_LAUNCH3(true, false);
+  else if (P.nt) PFL_LAUNCH3(false, true);
+  else PFL_LAUNCH3(false, false);
+#undef PFL_LAUNCH3
   return hipGetLastError();
 }
 

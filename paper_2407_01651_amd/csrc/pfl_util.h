@@ -77,15 +77,29 @@ __device__ __forceinline__ uint32_t round_seed(const DevParams& P, uint32_t node
   return pcg_hash(node ^ pcg_hash(P.step_ctr));
 }
 
+// Write of one value, non-temporal when NT is set.  A step whose state is
+// larger than the last-level cache writes non-temporally: the value is read
+// again only in the next step, after the rest of the state has passed through
+// the cache, so caching it only evicts what the step is about to read.
+// A state that fits is written normally and the next step's pulls hit it.
+// (A compile-time choice: the two forms of a store differ only in metadata,
+// and a runtime branch between them is merged into one plain store.)
+template <bool NT, class B>
+__device__ __forceinline__ void put(B* p, B v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Store of one post-collision value: 16-bit storage rounds stochastically
 // with the random bits r when P.sr is set.
-template <class ST, class CT>
+template <class ST, class CT, bool NT>
 __device__ __forceinline__ void store_pop(const DevParams& P, typename Store<ST>::raw* p, CT v,
                                           uint32_t r) {
-  if constexpr (sizeof(typename Store<ST>::raw) == 2) {
-    if (P.sr) { Store<ST>::st_sr(p, v, r); return; }
-  }
-  Store<ST>::st(p, v);
+  using B = typename Store<ST>::bits;
+  B b;
+  if constexpr (sizeof(B) == 2) b = P.sr ? Store<ST>::enc_sr(v, r) : Store<ST>::enc(v);
+  else b = Store<ST>::enc(v);
+  put<NT, B>((B*)p, b);
 }
 
 // Source offsets along one axis for a node at coordinate x: entry c + 1

@@ -97,6 +97,20 @@ def test_bad_rounding_mode_is_rejected():
     assert "rounding" in pfl._lib.pfl_last_error().decode()
 
 
+
+def test_write_policy_values():
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("coupled2d_128")
+    s = pfl.Sizes()
+    for name, code in (("auto", 0), ("cached", 1), ("stream", 2)):
+        p = pfl.make_params(dict(w, write_policy=name))
+        assert p.write_policy == code
+        assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.write_policy = 3
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    assert "write policy" in pfl._lib.pfl_last_error().decode()
+
+
 def test_boundary_flags():
     """wall[a]: 0 periodic, 1 walls, 2 symmetry planes, 3 / 4 a symmetry plane
     on the low / high side only, 5 / 6 a far-field high side with a wall /
