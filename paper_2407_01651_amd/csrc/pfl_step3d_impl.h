@@ -23,9 +23,13 @@ namespace pfl {
 
 namespace {
 
+// Box shape: 32 x 4 x 2 in FP32 compute (256 threads; rows of 32 nodes keep
+// each wave's loads and stores in whole or half 128-byte lines).  Measured on
+// the 256^3 coupled step against 16 x 4 x 4, 32 x 2 x 4 and 16 x 8 x 2: FP16
+// storage 5.84k -> 6.09k MLUPS, FP32 4.55k -> 4.84k.  FP64: 16 x 4 x 2 (LDS).
 template <class CT>
 struct Tile3 {
-  static constexpr int TX = 16, TY = 4, TZ = sizeof(CT) == 8 ? 2 : 4;
+  static constexpr int TX = sizeof(CT) == 8 ? 16 : 32, TY = 4, TZ = 2;
   static constexpr int NT = TX * TY * TZ;
 };
 
