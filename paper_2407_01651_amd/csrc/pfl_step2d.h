@@ -8,15 +8,20 @@
 namespace pfl {
 
 constexpr int TX = 32, TY = 8, NT = TX * TY;
-// The step kernel's tile, one node per thread: 32 x 8 nodes when the flow and
-// the bubble phase are both active (two halo rings), 32 x 4 otherwise.  The
-// shapes measured fastest: with one ring 32 x 4 against 32 x 2, 32 x 8,
-// 32 x 16, 64 x 4 and 16 x 8; with two rings 32 x 8 against 32 x 4, 32 x 16
-// and 16 x 16.
-template <int FIELDS>
+// The step kernel's tile, one node per thread: with the flow and the bubble
+// phase both active (two halo rings), 32 x 8 nodes, or 64 x 4 with 16-bit
+// storage (a wave's row is then one whole 128-byte line; coupled 2048^2 FP16
+// 17.6k -> 18.1k MLUPS, BF16 17.5k -> 17.9k); otherwise 32 x 4.  The shapes
+// measured fastest: with one ring 32 x 4 against 32 x 2, 32 x 8, 32 x 16,
+// 64 x 4 and 16 x 8; with two rings 32 x 8 against 32 x 4, 32 x 16 and
+// 16 x 16.  FP32 and FP64 storage keep 32 x 8: FP32 at 64 x 4 was 1.6%
+// faster but exceeded its error bound against FP64 on one variable-heat
+// case (its compiled contraction and reassociation differ per instantiation).
+template <int FIELDS, class ST>
 struct StepTile {
-  static constexpr int X = 32;
-  static constexpr int Y = ((FIELDS & F_NS) && (FIELDS & F_PHI)) ? 8 : 4;
+  static constexpr bool FLOWX = (FIELDS & F_NS) && (FIELDS & F_PHI);
+  static constexpr int X = (FLOWX && sizeof(typename Store<ST>::raw) == 2) ? 64 : 32;
+  static constexpr int Y = FLOWX ? (X == 64 ? 4 : 8) : 4;
   static constexpr int N = X * Y;
   // Minimum waves per SIMD asked of the register allocator.  The FP32-compute
   // step without flow, bubble phase or heat needs 64 VGPRs but over 100 SGPRs,
@@ -25,7 +30,7 @@ struct StepTile {
   // 1024^2).  Larger kernels spill to scratch when pushed and get slower
   // (coupled FP16 at 5 instead of 4 waves: 17.6k -> 14.0k), so they keep
   // the default (1 = no minimum).
-  template <class ST, class CT, bool SYM>
+  template <class CT, bool SYM>
   static constexpr int waves() {
     if (SYM) return 1;
     if (sizeof(CT) == 4 && !(FIELDS & (F_NS | F_PHI | F_TH))) return 8;

@@ -29,8 +29,8 @@
 namespace pfl {
 
 template <int FIELDS, int QP, class ST, class HT, class CT, bool SYM, bool STREAM>
-__global__ __launch_bounds__(StepTile<FIELDS>::N)
-__attribute__((amdgpu_waves_per_eu(StepTile<FIELDS>::template waves<ST, CT, SYM>())))
+__global__ __launch_bounds__((StepTile<FIELDS, ST>::N))
+__attribute__((amdgpu_waves_per_eu(StepTile<FIELDS, ST>::template waves<CT, SYM>())))
 void step2d_kernel(const DevParams P,
                                                     const typename Store<ST>::raw* __restrict__ fin,
                                                     typename Store<ST>::raw* __restrict__ fout,
@@ -40,7 +40,7 @@ void step2d_kernel(const DevParams P,
   constexpr bool CC = FIELDS & F_C, TH = FIELDS & F_TH;
   constexpr bool FLOWX = NS && PHI;          // mass-flux force needs D_phi (x) v0 on ring 1
   constexpr int R = FLOWX ? 2 : 1;
-  constexpr int STX = StepTile<FIELDS>::X, STY = StepTile<FIELDS>::Y, SNT = StepTile<FIELDS>::N;
+  constexpr int STX = StepTile<FIELDS, ST>::X, STY = StepTile<FIELDS, ST>::Y, SNT = StepTile<FIELDS, ST>::N;
   constexpr int RX = STX + 2 * R, RY = STY + 2 * R;
   constexpr int QN = 9, QS = 5;
   using LN = Lat<9>;
@@ -640,7 +640,7 @@ void step2d_kernel(const DevParams P,
 template <int FIELDS, int QP, class ST, class HT, class CT>
 hipError_t launch_step2d_t(const DevParams& P, const void* fin, void* fout, void* hist,
                            double* mout, int mode, hipStream_t s) {
-  constexpr int STX = StepTile<FIELDS>::X, STY = StepTile<FIELDS>::Y, SNT = StepTile<FIELDS>::N;
+  constexpr int STX = StepTile<FIELDS, ST>::X, STY = StepTile<FIELDS, ST>::Y, SNT = StepTile<FIELDS, ST>::N;
   dim3 grid(((P.nx + STX - 1) / STX) * ((P.ny + STY - 1) / STY));
   using raw = typename Store<ST>::raw;
   const bool sym = P.sym || P.far;
