@@ -75,11 +75,12 @@ enum { PFL_F64 = 0, PFL_F32 = 1, PFL_F16 = 2, PFL_BF16 = 3 };
  * (round to nearest, ties to even). */
 enum { PFL_ROUND_STOCHASTIC = 0, PFL_ROUND_NEAREST = 1 };
 /* Cache policy of the step's population and history stores.  AUTO streams
-   them past the last-level cache (non-temporal writes) in 2D with FP64 or
-   FP32 storage when the state read plus written per step exceeds its 256 MiB,
-   and caches them otherwise (16-bit storage and 3D tiles write partial
-   128-byte lines per wave, which streaming makes slower); the other two force
-   one policy.  Results are identical under every policy. */
+   them past the last-level cache (non-temporal writes) when the state read
+   plus written per step exceeds its 256 MiB and each wave's stores fill whole
+   128-byte lines: in 2D with FP64 or FP32 storage, and with 16-bit storage
+   when NS and phi are both active (64-node tile rows).  Otherwise it caches
+   them (partial lines per wave, as in 3D, are slower streamed).  The other
+   two force one policy.  Results are identical under every policy. */
 enum { PFL_WRITE_AUTO = 0, PFL_WRITE_CACHED = 1, PFL_WRITE_STREAM = 2 };
 
 /* Macro-field planes written by pfl_get_macros (node form, in this order). */

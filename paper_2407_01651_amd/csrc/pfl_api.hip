@@ -250,10 +250,14 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
     // Automatic write policy: stream the stores past the 256 MiB last-level
     // cache when the populations and history read plus written per step do
     // not fit it, and a wave's store row fills whole 128-byte lines (2D rows
-    // of 32 nodes in 4- or 8-byte storage).  Measured on 2048^2 coupled:
-    // FP32 +5.6%; 16-bit storage (64-byte rows) -4.7%; 3D FP16 (16-node
-    // rows) -25%; on a state that fits the cache, streaming loses a third.
-    const bool full_lines = p->dim == 2 && (p->store == PFL_F64 || p->store == PFL_F32);
+    // of 32 nodes in 4- or 8-byte storage, or of 64 nodes in 16-bit storage,
+    // the tile of the step with flow and bubble phase).  Measured on 2048^2
+    // coupled: FP32 +5.6%, FP16 +4.5%, BF16 +4.8%; with 64-byte rows (16-bit,
+    // 32-node rows) -4.7%; 3D FP16 with 16-node rows -25%; on a state that
+    // fits the cache, streaming loses a third.
+    const bool wide16 = (p->fields & PFL_NS) && (p->fields & PFL_PHI);
+    const bool full_lines = p->dim == 2 && (p->store == PFL_F64 || p->store == PFL_F32 ||
+                                            ((p->store == PFL_F16 || p->store == PFL_BF16) && wide16));
     d.nt = p->write_policy == PFL_WRITE_STREAM ||
            (p->write_policy == PFL_WRITE_AUTO && full_lines &&
             2 * (L.pops_bytes + L.hist_bytes) > ((size_t)256 << 20));

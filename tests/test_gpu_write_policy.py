@@ -5,8 +5,8 @@ give bit-identical states.
 * small grids with the policy forced, over storage forms, 2D and 3D, walls
   and symmetry / far-field sides (the streaming path on grids that would
   otherwise cache);
-* the full 2048 x 2048 coupled grid in FP32 storage, where the default
-  (automatic) policy streams, against forced cached writes.
+* the full 2048 x 2048 coupled grid in FP32 and FP16 storage, where the
+  default (automatic) policy streams, against forced cached writes.
 """
 import pytest
 import torch
@@ -44,10 +44,11 @@ def test_streaming_and_cached_writes_agree_bit_for_bit(dim, store, bc):
     assert torch.equal(a, b)
 
 
-def test_full_size_coupled_fp32_auto_policy_matches_cached():
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_full_size_coupled_auto_policy_matches_cached(store):
     w = workloads.get("coupled2d_2048")
-    a = _run(w, "f32", "auto", 10)
-    b = _run(w, "f32", "cached", 10)
-    log(f"[write policy] coupled2d_2048 f32 auto vs cached: max |diff| {float((a - b).abs().max()):.1e}")
+    a = _run(w, store, "auto", 10)
+    b = _run(w, store, "cached", 10)
+    log(f"[write policy] coupled2d_2048 {store} auto vs cached: max |diff| {float((a - b).abs().max()):.1e}")
     assert torch.equal(a, b)
 
