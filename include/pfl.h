@@ -77,10 +77,10 @@ enum { PFL_ROUND_STOCHASTIC = 0, PFL_ROUND_NEAREST = 1 };
 /* Cache policy of the step's population and history stores.  AUTO streams
    them past the last-level cache (non-temporal writes) when the state read
    plus written per step exceeds its 256 MiB and each wave's stores fill whole
-   128-byte lines: in 2D with FP64 or FP32 storage, and with 16-bit storage
+   128-byte lines: with FP64 or FP32 storage, and with 16-bit storage in 2D
    when NS and phi are both active (64-node tile rows).  Otherwise it caches
-   them (partial lines per wave, as in 3D, are slower streamed).  The other
-   two force one policy.  Results are identical under every policy. */
+   them (partial lines per wave are slower streamed).  The other two force
+   one policy.  Results are identical under every policy. */
 enum { PFL_WRITE_AUTO = 0, PFL_WRITE_CACHED = 1, PFL_WRITE_STREAM = 2 };
 
 /* Macro-field planes written by pfl_get_macros (node form, in this order). */

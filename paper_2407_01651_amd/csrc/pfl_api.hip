@@ -249,15 +249,17 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
     d.sr = ((p->store == PFL_F16 || p->store == PFL_BF16) && p->rounding == PFL_ROUND_STOCHASTIC) ? 1 : 0;
     // Automatic write policy: stream the stores past the 256 MiB last-level
     // cache when the populations and history read plus written per step do
-    // not fit it, and a wave's store row fills whole 128-byte lines (2D rows
-    // of 32 nodes in 4- or 8-byte storage, or of 64 nodes in 16-bit storage,
-    // the tile of the step with flow and bubble phase).  Measured on 2048^2
-    // coupled: FP32 +5.6%, FP16 +4.5%, BF16 +4.8%; with 64-byte rows (16-bit,
-    // 32-node rows) -4.7%; 3D FP16 with 16-node rows -25%; on a state that
-    // fits the cache, streaming loses a third.
-    const bool wide16 = (p->fields & PFL_NS) && (p->fields & PFL_PHI);
-    const bool full_lines = p->dim == 2 && (p->store == PFL_F64 || p->store == PFL_F32 ||
-                                            ((p->store == PFL_F16 || p->store == PFL_BF16) && wide16));
+    // not fit it, and a wave's store row fills whole 128-byte lines: 4- or
+    // 8-byte storage (2D rows of 32 nodes; 3D rows of 32 nodes in FP32, of
+    // 16 in FP64), or 16-bit storage in the 2D step with flow and bubble
+    // phase (64-node rows).  Measured, streaming against cached: 2048^2
+    // coupled FP32 +5.6%, FP16 +4.5%, BF16 +4.8%; 256^3 coupled FP32 +5.1%;
+    // with 64-byte rows, 2D 16-bit -4.7% and 3D FP16 -3.7%; on a state that
+    // fits the cache, streaming loses a third.  (3D FP64 follows the rule
+    // unmeasured.)
+    const bool wide16 = p->dim == 2 && (p->fields & PFL_NS) && (p->fields & PFL_PHI);
+    const bool full_lines = p->store == PFL_F64 || p->store == PFL_F32 ||
+                            ((p->store == PFL_F16 || p->store == PFL_BF16) && wide16);
     d.nt = p->write_policy == PFL_WRITE_STREAM ||
            (p->write_policy == PFL_WRITE_AUTO && full_lines &&
             2 * (L.pops_bytes + L.hist_bytes) > ((size_t)256 << 20));

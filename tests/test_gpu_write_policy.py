@@ -5,8 +5,10 @@ give bit-identical states.
 * small grids with the policy forced, over storage forms, 2D and 3D, walls
   and symmetry / far-field sides (the streaming path on grids that would
   otherwise cache);
-* the full 2048 x 2048 coupled grid in FP32 and FP16 storage, where the
-  default (automatic) policy streams, against forced cached writes.
+* states larger than the last-level cache, where the default (automatic)
+  policy streams (the full 2048 x 2048 coupled grid in FP32 and FP16
+  storage, a 128 x 128 x 64 coupled grid in FP32), against forced cached
+  writes.
 """
 import pytest
 import torch
@@ -44,11 +46,16 @@ def test_streaming_and_cached_writes_agree_bit_for_bit(dim, store, bc):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("store", ["f32", "f16"])
-def test_full_size_coupled_auto_policy_matches_cached(store):
-    w = workloads.get("coupled2d_2048")
+@pytest.mark.parametrize("name,store", [("coupled2d_2048", "f32"), ("coupled2d_2048", "f16"),
+                                        ("coupled3d_128x128x64", "f32")])
+def test_large_states_auto_policy_matches_cached(name, store):
+    # states larger than the last-level cache, where the automatic policy streams
+    if name == "coupled3d_128x128x64":
+        w = workloads.small(dim=3, nx=128, ny=128, nz=64, seed=53, periodic=(True, True, False))
+    else:
+        w = workloads.get(name)
     a = _run(w, store, "auto", 10)
     b = _run(w, store, "cached", 10)
-    log(f"[write policy] coupled2d_2048 {store} auto vs cached: max |diff| {float((a - b).abs().max()):.1e}")
+    log(f"[write policy] {name} {store} auto vs cached: max |diff| {float((a - b).abs().max()):.1e}")
     assert torch.equal(a, b)
 
