@@ -266,7 +266,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}[a.store],
         "data": "synthetic",
         "config": {"workload": w["name"], "grid": [w["nx"], w["ny"]] + ([w["nz"]] if w["dim"] == 3 else []),
-                   "fields": list(w["fields"]), "storage": a.store, "nodes": n},
+                   "fields": list(w["fields"]), "storage": a.store, "nodes": n, "write_policy": a.write_policy},
         "roofline": {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_run["achieved_gbs"] / PEAK_HBM_GBS, 4),
