@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpfl.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_01651_amd.build`"
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2407_01651_amd/build.py`"
                       " (or __graft_entry__.build())")
 _lib = ct.CDLL(LIB_PATH)
 
