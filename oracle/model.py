@@ -34,7 +34,15 @@ Paper:
 Readings (the paper defers the CAC, solute and NS schemes and the
 fluid-solid force to other works):
   * NS: pressure-based incompressible scheme, p recovered from the moving
-    populations, rho from phi; forcing with a v.grad(rho) zeroth moment.
+    populations, rho from phi.  The forcing carries the velocity-density
+    term w_i (c_i.v)(c_i.grad rho)/cs2: its zeroth moment v.grad(rho) makes
+    the recovered continuity equation div v = 0, and its second moment
+    cs2 (v grad rho + grad rho v + v.grad rho I) removes the error
+    nu div(v grad rho + grad rho v) that the momentum moment rho v leaves in
+    the viscous stress, so that the stress is mu (grad v + grad v^T) of
+    Sec. 2.2 with mu = rho nu (without it a uniform flow along a flat
+    interface at density ratio 10 is not preserved: errors of twice the
+    flow speed within 200 steps).
   * The mass-flux term enters as the force (drho/dphi) div(D_phi (x) v0).
   * Fluid-solid force rho f = -2 chi rho v*, chi = clamp(h(psi), 0, 1), so
     that v = (1 - chi) v*.
@@ -594,6 +602,91 @@ class OracleSim:
         self.n = 0
         self.first = True
 
+    # ------------------------------------------------------------ single terms
+    # Each term below is a method of its own, so that a test can substitute a
+    # plausible mistake for one of them and check that a pin catches it.
+
+    def ns_rate(self, nu):
+        """Stress-moment relaxation rate s_nu = 1/(nu/cs2 + 1/2) of the flow
+        LB at kinematic viscosity nu (Appendix B relaxation relation of the
+        CDE sets, D = (1/s - 1/2) cs2, read for the NS set with nu; MRT
+        collision of Sec. 3).  Pinned by the shear-wave decay rate nu k^2."""
+        return 1.0 / (nu / self.L_ns.cs2 + 0.5)
+
+    def ns_forcing(self, L, v, F, gradrho):
+        """Forcing distribution of the flow LB, w_i [(c_i.v)(c_i.grad rho)/cs2
+        + c_i.F/cs2 + (vF + Fv):(c_i c_i - cs2 I)/(2 cs4)] (Sec. 3 unified LB
+        equation, auxiliary term G).  Moments: zeroth v.grad rho, first F,
+        second vF + Fv + cs2 (v grad rho + grad rho v + v.grad rho I); the
+        grad-rho parts make the recovered equations div v = 0 and the viscous
+        stress mu (grad v + grad v^T) of Sec. 2.2 at variable density.
+        Pinned by a uniform flow along a flat interface at density ratio 10."""
+        cv = self.cdot(L, v)
+        cF = self.cdot(L, F)
+        vF = (v * F).sum(0)
+        w = self.wv(L, vF)
+        # (vF + Fv):(c c - cs2 I) / (2 cs4) = [2 (c.v)(c.F) - 2 cs2 v.F] / (2 cs4)
+        return w * (cv * self.cdot(L, gradrho) / L.cs2 + cF / L.cs2
+                    + (2 * cv * cF - 2 * L.cs2 * vF) / (2 * L.cs2 ** 2))
+
+    def buoyancy(self, rho):
+        """Body force F_b = -(rho - rho_l) g y^ (Sec. 2.2 momentum equation;
+        the liquid's hydrostatic head -rho_l g y^ is carried by the pressure).
+        Pinned by the momentum budget of a periodic box."""
+        Fb = torch.zeros((self.d,) + self.grid, dtype=DT)
+        Fb[1] = -(rho - self.p.rho_l) * self.p.g
+        return Fb
+
+    def mass_flux_force(self, Dphi, v0):
+        """Force of the mass-diffusion part of the momentum flux m v with
+        m = rho v - D_phi (rho_l - rho_g)/(phi_l - phi_g) (Sec. 2.2):
+        (rho_l - rho_g)/(phi_l - phi_g) div(D_phi (x) v0), v0 the velocity
+        without this force.  Pinned by the momentum budget (a pure divergence)
+        and by Galilean invariance of a uniform flow through a relaxing bubble."""
+        drho = (self.p.rho_l - self.p.rho_g) / (PHI_L - PHI_G)
+        X = Dphi.unsqueeze(1) * v0.unsqueeze(0)      # X_ab = D_a v0_b
+        return drho * self.div_tensor(X)
+
+    def solid_force(self, chi, rvs):
+        """Fluid-solid force rho f = -2 chi rho v* (Sec. 2.2 force f, limited
+        by the solid fraction chi = clamp(h(psi), 0, 1)), so that
+        rho v = (1 - chi) rho v*.  Pinned by the body-force-driven channel
+        between two solid slabs."""
+        return -2 * chi * rvs
+
+    def cac_equilibrium(self, L, phi, v):
+        """Equilibrium of the bubble-phase LB, w_i phi (1 + c_i.v/cs2): zeroth
+        moment phi, first moment phi v (the convective flux of Sec. 2.1's
+        conservative Allen-Cahn equation).  Pinned by the uniform-flow
+        advection of a bubble."""
+        w = self.wv(L, phi)
+        return w * phi * (1 + self.cdot(L, v) / L.cs2)
+
+    def antitrapping(self, q, psi_prev):
+        """Anti-trapping current J_at = -a W_psi [1 + (1-k) U] (dpsi/dt)
+        grad psi/|grad psi| (Sec. 2.1) with W_psi = W0 a_s, a = 1/(2 sqrt 2)
+        for beta_psi = 1/4 (Sec. 2.1 specialisation, Appendix A), dpsi/dt a
+        backward difference.  Pinned by the partition of a moving planar
+        front (no solute trapping)."""
+        P = self.p
+        return -A_AT * P.W0 * q["a_s"] * (1 + (1 - P.k) * q["U"]) * (q["psi"] - psi_prev) * q["epsi"]
+
+    def solute_drift(self, q):
+        """The part of (1-k) D q grad U not carried by the LB's diffusion
+        D q/m grad C, with m = 1 - (1-k) h: the drift -D q C (1-k) grad h/m^2
+        (Sec. 2.1 solute equation; (1-k) grad U = grad(C/m)).  Returns the
+        drift and m.  Pinned by the stationary partitioned profile
+        C = 1 - (1-k) h at U = 0."""
+        P = self.p
+        m = 1 - (1 - P.k) * q["h"]
+        gh = q["gpsi"] / (PSI_S - PSI_L)
+        return P.D * q["qf"] * q["C"] * (1 - P.k) * gh / (m * m), m
+
+    def solute_convection(self, C, v):
+        """Convective solute flux C v (Sec. 2.1 solute equation).  Pinned by
+        the uniform-flow advection of a solute Gaussian."""
+        return C * v
+
     # -------------------------------------------------------- node quantities
     def compute(self):
         """Steps S1-S9 of one time step at every node (moments, stencils,
@@ -668,14 +761,12 @@ class OracleSim:
             fns = st["f_ns"]
             j = torch.einsum("ia,i...->a...", Ln.c, fns)
             Fs = P.k_s * mu_phi * gphi
-            Fb = torch.zeros_like(gphi)
-            Fb[1] = -(rho - P.rho_l) * P.g      # liquid hydrostatic head carried by p
+            Fb = self.buoyancy(rho)
             v0 = (1 - chi) * (j + 0.5 * (Fs + Fb)) / rho
-            X = Dphi.unsqueeze(1) * v0.unsqueeze(0)      # X_ab = D_a v0_b
-            Fm = drho * self.div_tensor(X)
+            Fm = self.mass_flux_force(Dphi, v0)
             rvs = j + 0.5 * (Fs + Fb + Fm)
             v = (1 - chi) * rvs / rho
-            rf = -2 * chi * rvs
+            rf = self.solid_force(chi, rvs)
             Ftot = Fs + Fb + Fm + rf
             w0 = Ln.w[0]
             s0 = -w0 * (v * v).sum(0) / (2 * Ln.cs2)
@@ -712,13 +803,8 @@ class OracleSim:
             s_i = w * (cv / L.cs2 + cv * cv / (2 * L.cs2 ** 2) - vv / (2 * L.cs2))
             feq = w * q["p"] / L.cs2 + q["rho"] * s_i
             feq[0] = feq[0] - q["p"] / L.cs2
-            Fv = q["Ftot"]
-            cF = self.cdot(L, Fv)
-            vF = (v * Fv).sum(0)
-            # (vF + Fv):(c c - cs2 I) / (2 cs4) = [2 (c.v)(c.F) - 2 cs2 v.F] / (2 cs4)
-            Ft = w * ((v * q["gradrho"]).sum(0) + cF / L.cs2
-                      + (2 * cv * cF - 2 * L.cs2 * vF) / (2 * L.cs2 ** 2))
-            s_nu = 1.0 / (q["nu"] / L.cs2 + 0.5)
+            Ft = self.ns_forcing(L, v, q["Ftot"], q["gradrho"])
+            s_nu = self.ns_rate(q["nu"])
             rates = {r: s_nu for r in L.stress_rows}
             fstar = f - self.mrt(L, f, feq, rates) + Ft - 0.5 * self.lam_apply(L, Ft, rates)
             new["f_ns"] = self.stream(fstar, L)
@@ -728,7 +814,7 @@ class OracleSim:
             L = self.L_phi
             f = st["f_phi"]
             w = self.wv(L, q["phi"])
-            feq = w * q["phi"] * (1 + self.cdot(L, v) / L.cs2)
+            feq = self.cac_equilibrium(L, q["phi"], v)
             prev = phiv if first else st["phiv_prev"]
             flux = (phiv - prev) + L.cs2 * q["sharp"] * q["nphi"]
             G = w * self.cdot(L, flux) / L.cs2
@@ -761,13 +847,11 @@ class OracleSim:
             L = self.L_sc
             f = st["f_c"]
             psi_prev = q["psi"] if first else st["psi_prev"]
-            Jat = -A_AT * P.W0 * q["a_s"] * (1 + (1 - P.k) * q["U"]) * (q["psi"] - psi_prev) * q["epsi"]
+            Jat = self.antitrapping(q, psi_prev)
             Jv = (P.D * q["qf"] * q["C"] * math.sqrt(2 * BETA_PHI) / P.W_phi
                   * torch.clamp(PHI_L - q["phi"], min=0.0) * q["nphi"])
-            m = 1 - (1 - P.k) * q["h"]
-            gh = q["gpsi"] / (PSI_S - PSI_L)
-            drift = P.D * q["qf"] * q["C"] * (1 - P.k) * gh / (m * m)
-            B = q["C"] * v - drift + (1 - P.k) * (Jat + Jv)
+            drift, m = self.solute_drift(q)
+            B = self.solute_convection(q["C"], v) - drift + (1 - P.k) * (Jat + Jv)
             w = self.wv(L, q["C"])
             feq = w * q["C"] + w * self.cdot(L, B) / L.cs2
             Bprev = B if first else st["B_prev"]

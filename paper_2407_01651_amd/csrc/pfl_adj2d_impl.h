@@ -719,7 +719,6 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
     const CT nu = (K.mu_g + (K.mu_l - K.mu_g) * phi) / rho;
     const CT s_nu = 1 / (nu * 3 + CT(0.5));
     const CT vv = vx * vx + vy * vy;
-    const CT vgr = vx * grx + vy * gry;
     const CT vF = vx * Fx + vy * Fy;
     CT feq[QN], Ft[QN];
     CT m1 = 0, m2 = 0;
@@ -729,7 +728,8 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy;
       feq[i] = w * p * 3 + rho * w * (cv * 3 + cv * cv * CT(4.5) - vv * CT(1.5));
       if (i == 0) feq[i] -= p * 3;
-      Ft[i] = w * (vgr + cF * 3 + (cv * cF - vF * CT(1.0 / 3)) * 9);
+      const CT cg = cx * grx + cy * gry;
+      Ft[i] = w * (cv * cg * 3 + cF * 3 + (cv * cF - vF * CT(1.0 / 3)) * 9);
       const CT fneq = fns[i] - feq[i] + CT(0.5) * Ft[i];
       m1 += (cx * cx - cy * cy) * fneq;
       m2 += (cx * cy) * fneq;
@@ -753,18 +753,19 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_m1 += ao_[i] * r * CT(0.25) * (cx * cx - cy * cy);
       a_m2 += ao_[i] * r * CT(0.25) * (cx * cy);
     }
-    CT a_vgr = 0, a_vF = 0, a_vv = 0;
+    CT a_vF = 0, a_vv = 0;
 #pragma unroll
     for (int i = 0; i < QN; ++i) {
       const CT cx = LN::c[i][0], cy = LN::c[i][1], w = LN::w[i];
-      const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy;
+      const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy, cg = cx * grx + cy * gry;
       const CT a_fneq = (cx * cx - cy * cy) * a_m1 + (cx * cy) * a_m2;
       a_fns[i] += a_fneq;
       const CT a_feq = ao_[i] - a_fneq;
       const CT a_Ft = CT(0.5) * a_fneq + CT(0.5) * ao_[i];
-      a_vgr += a_Ft * w;
+      const CT a_cg = a_Ft * w * 3 * cv;
+      a_grx += a_cg * cx; a_gry += a_cg * cy;
       const CT a_cF = a_Ft * w * (3 + 9 * cv);
-      CT a_cv = a_Ft * 9 * w * cF;
+      CT a_cv = a_Ft * w * (9 * cF + 3 * cg);
       a_vF -= 3 * w * a_Ft;
       a_p += a_feq * (3 * w - (i == 0 ? CT(3.0) : CT(0.0)));
       a_rho += a_feq * w * (cv * 3 + cv * cv * CT(4.5) - vv * CT(1.5));
@@ -774,7 +775,6 @@ __global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
       a_Fx += a_cF * cx; a_Fy += a_cF * cy;
     }
     a_vx += a_vF * Fx; a_vy += a_vF * Fy; a_Fx += a_vF * vx; a_Fy += a_vF * vy;
-    a_vx += a_vgr * grx; a_vy += a_vgr * gry; a_grx += a_vgr * vx; a_gry += a_vgr * vy;
     a_vx += 2 * a_vv * vx; a_vy += 2 * a_vv * vy;
     const CT a_snu = -a_r;
     const CT a_nu = a_snu * (-3 * s_nu * s_nu);

@@ -436,16 +436,15 @@ void step2d_kernel(const DevParams P,
     const CT nu = (K.mu_g + (K.mu_l - K.mu_g) * phi) * rcp(rho);
     const CT s_nu = rcp(nu * CT(3) + CT(0.5));
     const CT vv = vx * vx + vy * vy;
-    const CT vgr = vx * grx + vy * gry;
     const CT vF = vx * Fx + vy * Fy;
     if constexpr (sizeof(CT) == 4) {
       // FP32 compute: the same collision in moment form.  On the 4th-order
       // isotropic lattice the traceless stress moments of f^eq and of F/2 are
-      // rho T:vv and T:(vF) (symmetrised), and for i > 0
-      // f_i^eq + F_i/2 = w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F)) + 1.5 c.F]
-      // with A = 3p - 1.5 rho v.v + v.grad(rho)/2 - 1.5 v.F; f_0^eq + F_0/2 = w_0 A - 3p.
+      // rho T:vv and T:(vF + cs2 v grad(rho)) (symmetrised), and for i > 0
+      // f_i^eq + F_i/2 = w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F) + 1.5 c.grad(rho)) + 1.5 c.F]
+      // with A = 3p - 1.5 rho v.v - 1.5 v.F; f_0^eq + F_0/2 = w_0 A - 3p.
       const CT r = CT(1) - s_nu;
-      const CT A = CT(3) * p - CT(1.5) * rho * vv + CT(0.5) * vgr - CT(1.5) * vF;
+      const CT A = CT(3) * p - CT(1.5) * rho * vv - CT(1.5) * vF;
       CT s1 = CT(0), s2 = CT(0);
 #pragma unroll
       for (int i = 1; i < QN; ++i) {
@@ -453,8 +452,8 @@ void step2d_kernel(const DevParams P,
         if (t1 > 0) s1 += fns[i]; else if (t1 < 0) s1 -= fns[i];
         if (t2 > 0) s2 += fns[i]; else if (t2 < 0) s2 -= fns[i];
       }
-      const CT m1 = s1 - rho * (vx * vx - vy * vy) + (vx * Fx - vy * Fy);
-      const CT m2 = s2 - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx);
+      const CT m1 = s1 - rho * (vx * vx - vy * vy) + (vx * Fx - vy * Fy) + CT(1.0 / 3) * (vx * grx - vy * gry);
+      const CT m2 = s2 - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx) + CT(1.0 / 6) * (vx * gry + vy * grx);
       const CT q1 = CT(0.25) * r * m1, q2 = CT(0.25) * r * m2;
       const CT rho3 = CT(3) * rho;
 #pragma unroll
@@ -465,8 +464,8 @@ void step2d_kernel(const DevParams P,
         if (i == 0) {
           fs = w * A - CT(3) * p;
         } else {
-          const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy;
-          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF)) + CT(1.5) * cF + A;
+          const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy, cg = cx * grx + cy * gry;
+          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
           fs = w * t + ((cx * cx - cy * cy) * q1 + (cx * cy) * q2);
         }
         st(P.o_ns, i, fs);
@@ -482,7 +481,8 @@ void step2d_kernel(const DevParams P,
       const CT w = CT(LN::w[i]);
       CT feq = w * p * CT(3) + rho * w * (cv * CT(3) + cv * cv * CT(4.5) - vv * CT(1.5));
       if (i == 0) feq -= p * CT(3);
-      const CT Ft = w * (vgr + cF * CT(3) + (cv * cF - vF * CT(1.0 / 3)) * CT(9));
+      const CT cg = cx * grx + cy * gry;
+      const CT Ft = w * (cv * cg * CT(3) + cF * CT(3) + (cv * cF - vF * CT(1.0 / 3)) * CT(9));
       fhalf[i] = feq + CT(0.5) * Ft;
       fneq[i] = fns[i] - feq + CT(0.5) * Ft;
       m1 += (cx * cx - cy * cy) * fneq[i];

@@ -617,16 +617,15 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
     const CT nu = (K.mu_g + (K.mu_l - K.mu_g) * phi) * rcp(rho);
     const CT s_nu = rcp(nu * CT(3) + CT(0.5));
     const CT vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const CT vgr = v[0] * gr[0] + v[1] * gr[1] + v[2] * gr[2];
     const CT vF = v[0] * Ft[0] + v[1] * Ft[1] + v[2] * Ft[2];
     if constexpr (sizeof(CT) == 4) {
       // FP32 compute: the same collision in moment form (D3Q19 is 4th-order
       // isotropic, so each traceless stress moment T of f^eq + F/2 is
-      // rho T:vv + T:(vF) symmetrised; for i > 0 f_i^eq + F_i/2 =
-      // w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F)) + 1.5 c.F] with
-      // A = 3p - 1.5 rho v.v + v.grad(rho)/2 - 1.5 v.F, and w_0 A - 3p at rest)
+      // rho T:vv + T:(vF + cs2 v grad(rho)) symmetrised; for i > 0
+      // f_i^eq + F_i/2 = w_i [A + c.v (3 rho + 4.5 (rho c.v + c.F) + 1.5 c.grad(rho)) + 1.5 c.F]
+      // with A = 3p - 1.5 rho v.v - 1.5 v.F, and w_0 A - 3p at rest)
       const CT r = CT(1) - s_nu;
-      const CT A = CT(3) * p - CT(1.5) * rho * vv + CT(0.5) * vgr - CT(1.5) * vF;
+      const CT A = CT(3) * p - CT(1.5) * rho * vv - CT(1.5) * vF;
       CT s9 = CT(0), s11 = CT(0), sxy = CT(0), syz = CT(0), sxz = CT(0);
 #pragma unroll
       for (int i = 1; i < QN; ++i) {
@@ -638,12 +637,16 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
         sxz += CT(cx * cz) * fns[i];
       }
       const CT vx = v[0], vy = v[1], vz = v[2], Fx = Ft[0], Fy = Ft[1], Fz = Ft[2];
+      const CT gx = gr[0], gy = gr[1], gz = gr[2];
+      constexpr CT c3 = CT(1.0 / 3), c6 = CT(1.0 / 6);
       const CT q9 = (r * CT(1.0 / 36)) * (s9 - rho * (CT(2) * vx * vx - vy * vy - vz * vz) +
-                                          (CT(2) * vx * Fx - vy * Fy - vz * Fz));
-      const CT q11 = (r * CT(1.0 / 12)) * (s11 - rho * (vy * vy - vz * vz) + (vy * Fy - vz * Fz));
-      const CT qxy = (r * CT(0.25)) * (sxy - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx));
-      const CT qyz = (r * CT(0.25)) * (syz - rho * vy * vz + CT(0.5) * (vy * Fz + vz * Fy));
-      const CT qxz = (r * CT(0.25)) * (sxz - rho * vx * vz + CT(0.5) * (vx * Fz + vz * Fx));
+                                          (CT(2) * vx * Fx - vy * Fy - vz * Fz) +
+                                          c3 * (CT(2) * vx * gx - vy * gy - vz * gz));
+      const CT q11 = (r * CT(1.0 / 12)) * (s11 - rho * (vy * vy - vz * vz) + (vy * Fy - vz * Fz) +
+                                           c3 * (vy * gy - vz * gz));
+      const CT qxy = (r * CT(0.25)) * (sxy - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx) + c6 * (vx * gy + vy * gx));
+      const CT qyz = (r * CT(0.25)) * (syz - rho * vy * vz + CT(0.5) * (vy * Fz + vz * Fy) + c6 * (vy * gz + vz * gy));
+      const CT qxz = (r * CT(0.25)) * (sxz - rho * vx * vz + CT(0.5) * (vx * Fz + vz * Fx) + c6 * (vx * gz + vz * gx));
       const CT rho3 = CT(3) * rho;
 #pragma unroll
       for (int i = 0; i < QN; ++i) {
@@ -655,7 +658,8 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
         } else {
           const CT cv = CT(cx) * vx + CT(cy) * vy + CT(cz) * vz;
           const CT cF = CT(cx) * Fx + CT(cy) * Fy + CT(cz) * Fz;
-          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF)) + CT(1.5) * cF + A;
+          const CT cg = CT(cx) * gx + CT(cy) * gy + CT(cz) * gz;
+          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
           fs = w * t + (CT(2 * cx * cx - cy * cy - cz * cz) * q9 + CT(cy * cy - cz * cz) * q11 +
                         CT(cx * cy) * qxy + CT(cy * cz) * qyz + CT(cx * cz) * qxz);
         }
@@ -672,7 +676,8 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
       const CT w = CT(LN::w[i]);
       CT feq = w * p * CT(3) + rho * w * (cv * CT(3) + cv * cv * CT(4.5) - vv * CT(1.5));
       if (i == 0) feq -= p * CT(3);
-      const CT Fi = w * (vgr + cF * CT(3) + (cv * cF - vF * CT(1.0 / 3)) * CT(9));
+      const CT cg = cx * gr[0] + cy * gr[1] + cz * gr[2];
+      const CT Fi = w * (cv * cg * CT(3) + cF * CT(3) + (cv * cF - vF * CT(1.0 / 3)) * CT(9));
       fhalf[i] = feq + CT(0.5) * Fi;
       const CT fneq = fns[i] - feq + CT(0.5) * Fi;
       m9 += (CT(2) * cx * cx - cy * cy - cz * cz) * fneq;

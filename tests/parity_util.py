@@ -74,3 +74,21 @@ def rel_err(a, b):
 
 def compare_macros(gm, om, keys=MACRO_KEYS):
     return {k: rel_err(gm[k], om[k]) for k in keys if k in om}
+
+
+def plane_err(a, b, floor=1e-6):
+    """Largest relative error over the planes of a node-form state, each plane
+    measured against its own maximum: max_p max|a_p - b_p| / max|b_p|.  A
+    plane whose maximum is below floor times the state's maximum (one that
+    holds rounding noise only, such as the flow of a quiescent start) is
+    measured against that floor instead."""
+    a = a.detach().double().cpu()
+    b = b.detach().double().cpu()
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    gmax = float(b.abs().max())
+    worst = 0.0
+    for p in range(b.shape[0]):
+        den = max(float(b[p].abs().max()), floor * gmax, 1e-300)
+        worst = max(worst, float((a[p] - b[p]).abs().max()) / den)
+    return worst

@@ -27,7 +27,7 @@ FIELDS = ("phi", "psi", "C", "theta", "p")
 # supersaturation U (a derived field: (C/C_l^eq - 1)/(1 - k) amplifies the
 # error of C), of velocity (None: not compared), solid-fraction and
 # gas-volume relative error, bubble centroid (nodes).  Measured maxima over
-# the three cases: FP32 2.2e-5 / 4.8e-5 / 1.4e-4 / 7.4e-6 / 1.5e-5 / 4e-7;
+# the first three cases: FP32 2.2e-5 / 4.8e-5 / 1.4e-4 / 7.4e-6 / 1.5e-5 / 4e-7;
 # FP16 5.5e-3 / 1.4e-2 / - / 7.6e-5 / 2.9e-4 / 1.5e-2; BF16 4.1e-2 / 0.16 / - /
 # 5.4e-4 / 2.3e-3 / 1.8e-2.
 BOUNDS = {
@@ -44,8 +44,12 @@ CASES = {
     # symmetry in x, far-field top (the set-up of Sec. 4)
     "farfield_44x36": (lambda: dict(workloads.small(nx=44, ny=36, seed=7, periodic=(False, False, True)),
                                     symmetric=(True, False, False), farfield=(False, "hi", False)), 300),
-    # heat properties varying between gas and liquid
-    "varheat_40x34": (lambda: dict(workloads.small(nx=40, ny=34, seed=8), th_rho_g=0.7, th_cp_g=0.9,
+    # heat properties varying between gas and liquid.  The geometry keeps the
+    # bubble clear of the seed: with a bubble inside the seed (seed 8 of the
+    # small grids) the oracle itself amplifies a perturbation of 6e-8 to
+    # 1.3e-5 within 300 steps, which no rounding bound survives; here a
+    # perturbation decays
+    "varheat_40x34": (lambda: dict(workloads.small(nx=40, ny=34, seed=13), th_rho_g=0.7, th_cp_g=0.9,
                                    th_k_g=0.5), 300),
 }
 

@@ -14,7 +14,7 @@ import torch
 
 import workloads
 from tests.parity_util import (compare_macros, gpu_run, log, oracle_macros, oracle_run,
-                               oracle_state, rel_err)
+                               oracle_state, plane_err, rel_err)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -104,10 +104,13 @@ def test_small_grids_fp64(name, over, steps):
     gsim = gpu_run(w, steps)
     errs = compare_macros(gsim.macros(), oracle_macros(osim))
     log(f"[parity] {name} macros {errs}")
-    st_err = rel_err(gsim.get_state(), oracle_state(osim, w["fields"]))
-    log(f"[parity] {name} state {st_err:.3e}")
+    gst, ost = gsim.get_state(), oracle_state(osim, w["fields"])
+    st_err = rel_err(gst, ost)
+    pl_err = plane_err(gst, ost)
+    log(f"[parity] {name} state {st_err:.3e} per plane {pl_err:.3e}")
     assert max(errs.values()) < TOL, errs
     assert st_err < TOL
+    assert pl_err < TOL, pl_err
 
 
 def test_initial_state_matches_oracle():
@@ -166,7 +169,10 @@ def test_coupled_128_full_500_steps():
     gsim = gpu_run(w, 500)
     errs = compare_macros(gsim.macros(), oracle_macros(osim))
     log(f"[parity] coupled2d_128 macros {errs}")
-    st_err = rel_err(gsim.get_state(), oracle_state(osim, w["fields"]))
-    log(f"[parity] coupled2d_128 state {st_err:.3e}")
+    gst, ost = gsim.get_state(), oracle_state(osim, w["fields"])
+    st_err = rel_err(gst, ost)
+    pl_err = plane_err(gst, ost)
+    log(f"[parity] coupled2d_128 state {st_err:.3e} per plane {pl_err:.3e}")
     assert max(errs.values()) < TOL, errs
     assert st_err < TOL
+    assert pl_err < TOL, pl_err

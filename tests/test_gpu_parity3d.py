@@ -14,7 +14,7 @@ import pytest
 
 import workloads
 from tests.parity_util import (compare_macros, gpu_run, log, oracle_macros, oracle_run,
-                               oracle_state, rel_err)
+                               oracle_state, plane_err, rel_err)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -77,10 +77,13 @@ def test_small_grids_3d_fp64(name, over, steps):
     gsim = gpu_run(w, steps)
     errs = compare_macros(gsim.macros(), oracle_macros(osim), KEYS)
     log(f"[parity3d] {name} macros {errs}")
-    st_err = rel_err(gsim.get_state(), oracle_state(osim, w["fields"]))
-    log(f"[parity3d] {name} state {st_err:.3e}")
+    gst, ost = gsim.get_state(), oracle_state(osim, w["fields"])
+    st_err = rel_err(gst, ost)
+    pl_err = plane_err(gst, ost)
+    log(f"[parity3d] {name} state {st_err:.3e} per plane {pl_err:.3e}")
     assert max(errs.values()) < TOL, errs
     assert st_err < TOL
+    assert pl_err < TOL, pl_err
 
 
 def test_3d_init_matches_oracle():

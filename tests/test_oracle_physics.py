@@ -220,7 +220,14 @@ def test_solute_vacuum_in_bubble():
     slope = np.polyfit(torch.log(m["phi"][sel]).numpy(), torch.log(m["C"][sel]).numpy(), 1)[0]
     assert abs(slope / (1 - w["k"]) - 1) < 0.03, slope
     # the core is emptied by more than two orders of magnitude, mass is kept,
-    # and the liquid far from the bubble gained the solute
+    # and the liquid far from the bubble gained the solute.  The discrete CAC
+    # steady state holds phi = 4.8e-4 at the core (6e-6 initially), so the
+    # vacuum reaches C_core / C_far = phi_core^(1-k) = 1.5e-3 there, not 0:
+    # the core follows the same power law (measured 1.7e-3, steady from
+    # 500 steps on)
+    core = float(m["C"][24, 24]) / float(m["C"][0, 0])
+    law = float(m["phi"][24, 24]) ** (1 - w["k"])
+    assert abs(core / law - 1) < 0.25, (core, law)
     assert float(m["C"][24, 24]) < 5e-3
     assert abs(float(m["C"].sum()) / c0 - 1) < 1e-12
     assert float(m["C"][0, 0]) > 1.0
