@@ -23,8 +23,9 @@
  *     pfl_query_sizes(); the library never allocates or frees device memory.
  *     A pfl_ctx holds host metadata only.
  *   - Every call enqueues work on the caller's HIP stream (hipStream_t passed
- *     as void*) and returns without synchronising, except pfl_reduce(), which
- *     synchronises that stream.
+ *     as void*) and returns without synchronising, except pfl_reduce() and
+ *     pfl_last_check(), and pfl_step() when in-step checks are on
+ *     (reduce_every > 0), which synchronise that stream.
  *   - Node (x, y, z) has linear index (z * ny + y) * nx + x.  Node-form
  *     arrays are plane-major: plane p of length n = nx*ny*nz.
  *   - Velocity ordering (node-form population export/import):
@@ -48,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PFL_ABI_VERSION 1
+#define PFL_ABI_VERSION 2
 
 enum {
   PFL_OK = 0,
@@ -83,9 +84,15 @@ enum { PFL_ROUND_STOCHASTIC = 0, PFL_ROUND_NEAREST = 1 };
    one policy.  Results are identical under every policy. */
 enum { PFL_WRITE_AUTO = 0, PFL_WRITE_CACHED = 1, PFL_WRITE_STREAM = 2 };
 
-/* Macro-field planes written by pfl_get_macros (node form, in this order). */
+/* Macro fields of pfl_get_macros: bit PFL_M_x of its field mask selects the
+ * plane; the selected planes are written packed, in this order. */
 enum { PFL_M_PHI = 0, PFL_M_PSI, PFL_M_C, PFL_M_THETA, PFL_M_U, PFL_M_P,
        PFL_M_VX, PFL_M_VY, PFL_M_VZ, PFL_M_COUNT };
+#define PFL_M_ALL ((1u << PFL_M_COUNT) - 1u)
+/* Element type of pfl_get_macros output. */
+enum { PFL_OUT_F64 = 0, PFL_OUT_F32 = 1 };
+/* Input planes given to pfl_init_from_macros (bit mask). */
+enum { PFL_IN_PHI = 1, PFL_IN_PSI = 2, PFL_IN_C = 4, PFL_IN_THETA = 8, PFL_IN_V = 16 };
 
 /*
  * Physical inputs, in lattice units (dx = dt = 1).  The library derives
@@ -129,6 +136,11 @@ typedef struct {
                                solid = liquid, Sec. 2.2); 1, 1, 1 = matched properties.  The
                                scheme is conditionally stable where rho c_p < 1. */
   int write_policy;         /* PFL_WRITE_AUTO (0, default), PFL_WRITE_CACHED, PFL_WRITE_STREAM */
+  int reduce_every;         /* K > 0: pfl_step checks the state every K steps (step count a
+                               multiple of K) with the FP64 reduction of pfl_reduce, and
+                               returns PFL_E_NONFINITE if a check found NaN or Inf; 0: no
+                               checks.  With checks, pfl_step synchronises its stream once
+                               at the end of the call. */
 } pfl_params;
 
 /* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */
@@ -142,7 +154,7 @@ typedef struct {
   size_t aux_bytes;         /* grain map and angle table */
   size_t macros_bytes;      /* PFL_M_COUNT FP64 planes for pfl_get_macros */
   size_t state_bytes;       /* node-form FP64 populations + history (get/set_state) */
-  size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce */
+  size_t reduce_bytes;      /* FP64 partial sums of pfl_reduce and of the in-step checks */
   size_t adj_bytes;         /* scratch of pfl_step_backward / pfl_init_backward */
   size_t raw_bytes;         /* raw image of the current state (pfl_save_raw) */
   size_t tape_bytes;        /* one step tape (pfl_step_raw_taped); 0 in 3D */
@@ -165,11 +177,17 @@ typedef struct {
 
 typedef struct pfl_ctx pfl_ctx;
 
-/* Buffer sizes for these parameters.  Errors: PFL_E_INVALID_ARG,
- * PFL_E_UNSUPPORTED (see pfl_create). */
+/* Buffer sizes for these parameters: populations of every active set on
+ * its lattice (Appendix B: D2Q9 flow, D2Q5 or D2Q9 bubble phase, D2Q5 for
+ * the other sets; D3Q19 and D3Q7 in 3D) plus the history of the time
+ * derivatives.  Errors: PFL_E_INVALID_ARG, PFL_E_UNSUPPORTED (see
+ * pfl_create). */
 int pfl_query_sizes(const pfl_params* p, pfl_sizes* out);
 
 /* Validate parameters, derive constants, bind caller buffers and a stream.
+ * The constants follow the paper: d_psi = W0^2/tau0 and the relaxation
+ * relations of Appendix B, D from Pe_D (Sec. 3.3), lambda = 1/(a2 Pe_D)
+ * (Sec. 3.3, Appendix A), the surface-tension prefactor of Sec. 2.2.
  * Errors: PFL_E_INVALID_ARG for bad sizes, null buffers, or a relaxation
  * rate outside (0, 2) anywhere in the admissible range of the fields;
  * PFL_E_UNSUPPORTED for isothermal runs with bubbles and solute (F(U) -> 0
@@ -184,46 +202,92 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
 int pfl_init_fields(pfl_ctx* c, const pfl_seed* seeds, int nseed,
                     const pfl_bubble* bubbles, int nbub);
 
-/* Rest-equilibrium populations of given FP64 node-form macro fields on the
- * device: planes phi, psi, C, theta, v_x, v_y[, v_z] (dev_macros holds
- * 4 + dim planes).  Seeds give the grain map.  Resets the step counter. */
-int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, const pfl_seed* seeds, int nseed);
+/* Rest-equilibrium populations (the equilibria of Appendix B and of the
+ * flow, CAC and solute schemes at the given macros, no non-equilibrium part)
+ * of FP64 node-form macro fields on the device: plane k of dev_macros
+ * (planes phi, psi, C, theta, v_x, v_y[, v_z]; 4 + dim planes of N) is read
+ * only if its bit is set in given (PFL_IN_PHI .. PFL_IN_THETA, PFL_IN_V for
+ * all velocity planes).  Planes not given take the bulk liquid at rest:
+ * phi = 1, psi = -1, theta = theta0, v = 0, and
+ * C = phi (1 + (1-k) U0)(1 - (1-k) h(psi)), the partitioned equilibrium
+ * profile (Sec. 3.3 case A initial condition).  Seeds give the grain map.
+ * Resets the step counter.  Errors: PFL_E_INVALID_ARG for a null
+ * dev_macros with given != 0 or unknown bits. */
+int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, uint32_t given, const pfl_seed* seeds,
+                         int nseed);
 
-/* Advance nsteps time steps: one fused kernel launch per step on the
- * context's stream.  Errors: PFL_E_STATE before init. */
+/* Advance nsteps time steps of the Sec. 3 unified LB equation for every
+ * active set (flow, CAC, AAC with the time stretch a_n of Appendix B,
+ * solute, heat), one fused kernel launch per step on the context's stream.
+ * With pfl_params.reduce_every = K > 0 the state is checked after every
+ * step whose count is a multiple of K and the call synchronises once at its
+ * end.  Errors: PFL_E_STATE before init; PFL_E_NONFINITE when a check found
+ * NaN or Inf (all nsteps steps were still taken; the message names the first
+ * failing check). */
 int pfl_step(pfl_ctx* c, int nsteps);
 
-/* Macro fields of the current state into dev_out (FP64, PFL_M_COUNT planes,
- * node form; unused planes are zero).  Errors: PFL_E_STATE before init. */
-int pfl_get_macros(pfl_ctx* c, void* dev_out);
+/* Macro fields of the current state: phi = sum f_i (CAC), psi = sum f_i
+ * (Appendix B AAC), C = sum f_i, theta from H = sum g_i / rho
+ * (Appendix B heat model, H = c_p theta - c_p^s h(psi)), U from C and psi
+ * (Sec. 2.1), the velocity and pressure of the flow scheme.  field_mask
+ * selects planes (bit PFL_M_x; 0 means PFL_M_ALL); they are written to
+ * dev_out packed in PFL_M order, node form, as FP64 (out_type PFL_OUT_F64) or
+ * FP32 (PFL_OUT_F32), popcount(field_mask) planes of N.  Planes of fields not
+ * solved hold their fixed value (v_z = 0 in 2D).  Errors: PFL_E_STATE before
+ * init; PFL_E_INVALID_ARG for unknown bits or output type. */
+int pfl_get_macros(pfl_ctx* c, uint32_t field_mask, void* dev_out, int out_type);
 
 /* Node-form FP64 copy of the pre-collision populations followed by the
- * history planes (state_bytes), and its inverse.  set_state marks the
- * history as valid (the next step is not a first step). */
+ * history planes (state_bytes), and its inverse.  The history holds the
+ * previous step's psi, S_psi, phi v, solute flux and H v, from which the
+ * time derivatives of Appendix B (dF_i/dt, the auxiliary terms G) are taken
+ * by backward differences.  set_state with step_count 0 marks the next step
+ * as a first step (time derivatives zero, history unused); any other count
+ * marks the history as valid. */
 int pfl_get_state(pfl_ctx* c, double* dev_out);
+/* Inverse of pfl_get_state (the history of the Appendix B time derivatives
+ * included); step_count 0 makes the next step a first step. */
 int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count);
 
-/* Global FP64 reductions; synchronises the stream.  Returns
- * PFL_E_NONFINITE (with *out filled) if the state holds NaN/Inf. */
+/* Global FP64 reductions of the current state, the quantities the paper
+ * conserves or reports: sum phi and the gas volume sum (phi_l - phi) (the
+ * CAC equation is conservative, Sec. 2.1), sum C (the solute equation is
+ * conservative), the solid fraction mean h(psi) and the gas centroid (Sec. 4
+ * bubble position), and a NaN/Inf flag over every population and history
+ * value.  Synchronises the stream.  Returns PFL_E_NONFINITE (with *out
+ * filled) if the state holds NaN/Inf. */
 int pfl_reduce(pfl_ctx* c, pfl_diag* out);
 
-/* Checkpoints.  save_raw copies the current state (populations in their
+/* The diagnostics of the last in-step check of pfl_step (reduce_every > 0),
+ * as pfl_reduce would have returned them at that step (the conserved sums of
+ * Sec. 2.1 and the NaN/Inf flag; the check itself is not in the paper: failure
+ * detection of this library); synchronises the stream.  Errors: PFL_E_STATE if no check has run since init;
+ * PFL_E_NONFINITE as pfl_reduce. */
+int pfl_last_check(pfl_ctx* c, pfl_diag* out);
+
+/* Checkpoints (the checkpoint-and-recompute of the adjoint, which the paper
+ * does not treat).  save_raw copies the current state (populations in their
  * storage type, then history) into dev_dst (raw_bytes, caller-owned device
  * memory) on the context's stream; load_raw makes such an image the current
  * state with its step count and first-step flag, so that stepping from it
  * repeats the original steps bit for bit (the stochastic rounding key is the
  * step count).  Errors: PFL_E_STATE before init. */
 int pfl_save_raw(pfl_ctx* c, void* dev_dst);
+/* Inverse of pfl_save_raw (checkpoint-and-recompute; not in the paper). */
 int pfl_load_raw(pfl_ctx* c, const void* dev_src, int64_t step_count, int first);
 
-/* One time step from the raw image raw_in into the raw image raw_out
+/* One time step (as pfl_step, Sec. 3 unified LB equation) from the raw image raw_in into the raw image raw_out
  * (distinct, raw_bytes each), as the step taken from a state with that step
  * count and first-step flag; the context's own state is not touched.  The
  * recompute of a checkpointed segment steps image to image this way instead
  * of copying states in and out.  Errors as pfl_step. */
 int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first);
 
-/* Adjoint of one time step (2D) at the current state x^n: given
+/* Adjoint of one time step (2D; not in the paper): the operation is
+ * the exact reverse-mode derivative of the discrete step of pfl_step (a
+ * hand-written transpose of each of its operations), for gradient-based
+ * calibration of eps4, k, the undercooling and the bubble radii.
+ * At the current state x^n: given
  * lambda^{n+1} = dL/dx^{n+1} (adj_in), writes lambda^n = (dx^{n+1}/dx^n)^T
  * lambda^{n+1} (adj_out) and adds lambda^{n+1} . dx^{n+1}/d(eps4, k) to
  * dparams[0], dparams[1].  x is the node-form state of pfl_get_state:
@@ -239,13 +303,13 @@ int pfl_step_raw(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_cou
  * property the 2D step runs, phi on either lattice). */
 int pfl_step_backward(pfl_ctx* c, const void* adj_in, void* adj_out, double* dparams);
 
-/* pfl_step_backward at the state held in a raw image (pfl_save_raw /
+/* As pfl_step_backward (adjoint of the discrete step; not in the paper), at the state held in a raw image (pfl_save_raw /
  * pfl_step_raw layout) with its step count and first-step flag, instead of
  * the context's current state.  Errors as pfl_step_backward. */
 int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count, int first,
                           const void* adj_in, void* adj_out, double* dparams);
 
-/* pfl_step_raw that also writes the step's tape (2D): the results of the
+/* pfl_step_raw (one step of the Sec. 3 unified LB equation) that also writes the step's tape (2D): the results of the
  * step's finite-difference stencils at every node, in the step's compute type
  * (FP64 for FP64 storage, FP32 otherwise), nine planes of N nodes: grad phi
  * (x, y), Laplacian of phi, grad psi (x, y), grad U (x, y) and the mass-flux
@@ -255,7 +319,7 @@ int pfl_step_backward_raw(pfl_ctx* c, const void* raw_state, int64_t step_count,
 int pfl_step_raw_taped(pfl_ctx* c, const void* raw_in, void* raw_out, int64_t step_count, int first,
                        void* tape);
 
-/* pfl_step_backward_raw with the step's stencil results taken from the tape
+/* pfl_step_backward_raw (adjoint of the discrete step; not in the paper) with the step's stencil results taken from the tape
  * that pfl_step_raw_taped wrote for the same step from the same image, instead
  * of recomputing them (the reverse then does no halo work).  Errors as
  * pfl_step_backward. */
@@ -266,7 +330,8 @@ int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_coun
 #define PFL_SWEEP_CONTINUE  1   /* carry on from the open sweep before (this context) */
 #define PFL_SWEEP_OPEN      2   /* leave this sweep open, to be continued */
 
-/* The reverse of the n steps step0 .. step0 + n - 1 in one call: for
+/* The reverse of the n steps step0 .. step0 + n - 1 in one call (adjoint of
+ * the discrete step; not in the paper): for
  * k = n - 1 down to 0, the adjoint of step step0 + k at the raw image
  * raw_states[k] (the state that step started from), with first-step flag
  * (first0 && k == 0) and the tape tapes[k] of pfl_step_raw_taped, or, with
@@ -293,7 +358,9 @@ int pfl_step_backward_taped(pfl_ctx* c, const void* raw_state, int64_t step_coun
 int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* const* tapes, int64_t n,
                        int64_t step0, int first0, void* adj, void* adj_tmp, double* dparams, int flags);
 
-/* Adjoint of pfl_init_fields: adds lambda^0 . dx^0/d(k, Omega, R_b) to
+/* Adjoint of pfl_init_fields (the Sec. 3.2 bubble profile, the psi
+ * equilibrium profile of Sec. 2.1, C and theta of the initial condition;
+ * the derivative itself is not in the paper): adds lambda^0 . dx^0/d(k, Omega, R_b) to
  * dparams[1], dparams[2], dparams[3 + b], where Omega is the undercooling
  * (theta0 = -Omega when the heat equation is solved, U0 = -Omega otherwise)
  * and R_b the radius of bubble b.  adj0 is lambda^0 in the adjoint type of
@@ -301,12 +368,29 @@ int pfl_backward_sweep(pfl_ctx* c, const void* const* raw_states, const void* co
  * last pfl_init_fields.  Errors as pfl_step_backward. */
 int pfl_init_backward(pfl_ctx* c, const void* adj0, double* dparams);
 
-/* Steps taken since the last init. */
+/* Adjoint of the macro fields of pfl_get_macros with respect to the state
+ * (not in the paper; it starts the reverse of a loss of the final fields):
+ * adj_out = (d macros / d x)^T dL, x the node-form state of pfl_get_state.
+ * phi, psi and C are the sums of their sets' populations (Sec. 2.1,
+ * Appendix B), so every population of a set receives dL/d(its sum); history
+ * entries and the other sets receive zero.  dL holds popcount(field_mask)
+ * FP64 node-form planes of N, packed in PFL_M order; field_mask may hold
+ * PFL_M_PHI, PFL_M_PSI and PFL_M_C.  adj_out is in the adjoint type of
+ * pfl_step_backward (state_bytes / 8 elements).  Errors: PFL_E_STATE before
+ * init; PFL_E_INVALID_ARG for other bits, bits of sets not solved or null
+ * pointers. */
+int pfl_adjoint_seed(pfl_ctx* c, const double* dL, uint32_t field_mask, void* adj_out);
+
+/* Steps taken since the last init (the time n of the Sec. 3 LB equation,
+ * t = n dt). */
 int64_t pfl_step_count(const pfl_ctx* c);
 
+/* Releases the host metadata of a context (no device memory is owned).
+ * There is no paper passage: resource handling of this library. */
 int pfl_destroy(pfl_ctx* c);
 
-/* Thread-local message of the last error ("" if none). */
+/* Thread-local message of the last error ("" if none); no paper passage:
+ * error reporting of this library. */
 const char* pfl_last_error(void);
 
 #ifdef __cplusplus

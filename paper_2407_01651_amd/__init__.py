@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
                       " (or __graft_entry__.build())")
 _lib = ct.CDLL(LIB_PATH)
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
 SWEEP_CONTINUE, SWEEP_OPEN = 1, 2
 NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
@@ -31,6 +31,8 @@ ROUNDINGS = {"stochastic": 0, "nearest": 1}
 WRITE_POLICIES = {"auto": 0, "cached": 1, "stream": 2}
 FIELD_BITS = {"ns": NS, "phi": PHI, "psi": PSI, "c": CONC, "theta": THETA}
 MACROS = ("phi", "psi", "C", "theta", "U", "p", "vx", "vy", "vz")
+OUT_F64, OUT_F32 = 0, 1
+INPUTS = {"phi": 1, "psi": 2, "C": 4, "theta": 8, "v": 16}
 
 
 class PflError(RuntimeError):
@@ -47,7 +49,7 @@ class Params(ct.Structure):
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
                                           "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")] + \
-               [("write_policy", ct.c_int)]
+               [("write_policy", ct.c_int), ("reduce_every", ct.c_int)]
 
 
 class Seed(ct.Structure):
@@ -78,12 +80,14 @@ _sig = {
     "pfl_query_sizes": ([_P(Params), _P(Sizes)], ct.c_int),
     "pfl_create": ([_P(ct.c_void_p), _P(Params), _P(Buffers), ct.c_void_p], ct.c_int),
     "pfl_init_fields": ([ct.c_void_p, _P(Seed), ct.c_int, _P(Bubble), ct.c_int], ct.c_int),
-    "pfl_init_from_macros": ([ct.c_void_p, ct.c_void_p, _P(Seed), ct.c_int], ct.c_int),
+    "pfl_init_from_macros": ([ct.c_void_p, ct.c_void_p, ct.c_uint32, _P(Seed), ct.c_int], ct.c_int),
     "pfl_step": ([ct.c_void_p, ct.c_int], ct.c_int),
-    "pfl_get_macros": ([ct.c_void_p, ct.c_void_p], ct.c_int),
+    "pfl_get_macros": ([ct.c_void_p, ct.c_uint32, ct.c_void_p, ct.c_int], ct.c_int),
     "pfl_get_state": ([ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_set_state": ([ct.c_void_p, ct.c_void_p, ct.c_int64], ct.c_int),
     "pfl_reduce": ([ct.c_void_p, _P(Diag)], ct.c_int),
+    "pfl_last_check": ([ct.c_void_p, _P(Diag)], ct.c_int),
+    "pfl_adjoint_seed": ([ct.c_void_p, ct.c_void_p, ct.c_uint32, ct.c_void_p], ct.c_int),
     "pfl_step_count": ([ct.c_void_p], ct.c_int64),
     "pfl_save_raw": ([ct.c_void_p, ct.c_void_p], ct.c_int),
     "pfl_load_raw": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int], ct.c_int),
@@ -114,11 +118,12 @@ def _check(rc):
     return rc
 
 
-def make_params(w, store=None, rounding=None, write_policy=None):
+def make_params(w, store=None, rounding=None, write_policy=None, reduce_every=None):
     """pfl_params from a workload description (primary inputs only).
     rounding: "stochastic" (default) or "nearest", for 16-bit storage;
     write_policy: "auto" (default), "cached" or "stream" (cache policy of the
-    step's stores, no effect on results)."""
+    step's stores, no effect on results); reduce_every: in-step NaN/Inf
+    check every K steps (0: none)."""
     p = Params()
     p.abi_version = ABI_VERSION
     p.struct_size = ct.sizeof(Params)
@@ -149,6 +154,7 @@ def make_params(w, store=None, rounding=None, write_policy=None):
     for n in ("th_rho_g", "th_cp_g", "th_k_g"):
         setattr(p, n, float(w.get(n, 1.0)))
     p.write_policy = WRITE_POLICIES[write_policy or w.get("write_policy", "auto")]
+    p.reduce_every = int(w.get("reduce_every", 0) if reduce_every is None else reduce_every)
     return p
 
 
@@ -161,10 +167,11 @@ def query_sizes(p):
 class Sim:
     """One simulation on one GPU; buffers are torch tensors owned here."""
 
-    def __init__(self, w, store=None, device="cuda:0", stream=None, rounding=None, adjoint=False):
+    def __init__(self, w, store=None, device="cuda:0", stream=None, rounding=None, adjoint=False,
+                 reduce_every=None):
         self.w = w
         self.device = torch.device(device)
-        self.p = make_params(w, store, rounding)
+        self.p = make_params(w, store, rounding, reduce_every=reduce_every)
         self.dim = w["dim"]
         self.shape = (w["nz"], w["ny"], w["nx"]) if self.dim == 3 else (w["ny"], w["nx"])
         self.N = w["nx"] * w["ny"] * (w["nz"] if self.dim == 3 else 1)
@@ -201,20 +208,20 @@ class Sim:
         _check(_lib.pfl_init_fields(self.ctx, sa, ns, ba, len(bubbles)))
 
     def init_from_macros(self, phi=None, psi=None, C=None, theta=None, v=None, seeds=None):
-        """Rest-equilibrium start from node-form macro fields (CPU or GPU tensors)."""
+        """Rest-equilibrium start from node-form macro fields (CPU or GPU
+        tensors); fields not given take the library's bulk-liquid defaults."""
         n = 4 + self.dim
         m = torch.zeros((n,) + self.shape, dtype=torch.float64, device=self.device)
-        m[0] = 1.0
-        m[1] = -1.0
-        m[2] = (1 + (1 - self.w["k"]) * self.w["U0"])
-        m[3] = self.w["theta0"]
-        for i, t in enumerate((phi, psi, C, theta)):
+        given = 0
+        for i, (name, t) in enumerate((("phi", phi), ("psi", psi), ("C", C), ("theta", theta))):
             if t is not None:
                 m[i] = t.to(self.device, torch.float64)
+                given |= INPUTS[name]
         if v is not None:
             m[4:4 + self.dim] = v.to(self.device, torch.float64)
+            given |= INPUTS["v"]
         sa, ns = self._seeds(seeds)
-        _check(_lib.pfl_init_from_macros(self.ctx, ct.c_void_p(m.data_ptr()), sa, ns))
+        _check(_lib.pfl_init_from_macros(self.ctx, ct.c_void_p(m.data_ptr()), given, sa, ns))
         self._keep = m
 
     # stepping ---------------------------------------------------------------
@@ -225,10 +232,17 @@ class Sim:
     def steps(self):
         return int(_lib.pfl_step_count(self.ctx))
 
-    def macros(self):
-        out = torch.empty((len(MACROS),) + self.shape, dtype=torch.float64, device=self.device)
-        _check(_lib.pfl_get_macros(self.ctx, ct.c_void_p(out.data_ptr())))
-        return {k: out[i] for i, k in enumerate(MACROS)}
+    def macros(self, fields=None, dtype=torch.float64):
+        """Macro fields as a dict of device tensors: all of them, or the names
+        in fields (of MACROS); dtype float64 or float32."""
+        names = MACROS if fields is None else [k for k in MACROS if k in set(fields)]
+        mask = 0
+        for k in names:
+            mask |= 1 << MACROS.index(k)
+        out_type = {torch.float64: OUT_F64, torch.float32: OUT_F32}[dtype]
+        out = torch.empty((len(names),) + self.shape, dtype=dtype, device=self.device)
+        _check(_lib.pfl_get_macros(self.ctx, mask, ct.c_void_p(out.data_ptr()), out_type))
+        return {k: out[i] for i, k in enumerate(names)}
 
     def get_state(self):
         nplanes = self.sizes.state_bytes // (8 * self.N)
@@ -328,6 +342,35 @@ class Sim:
     def init_backward(self, lam0, dparams):
         self._adj(lam0)
         _check(_lib.pfl_init_backward(self.ctx, ct.c_void_p(lam0.data_ptr()), ct.c_void_p(dparams.data_ptr())))
+
+    def adjoint_seed(self, phi=None, psi=None, C=None):
+        """Node-form adjoint (adj_dtype) of a loss of the final phi, psi, C
+        from its derivatives with respect to them (pfl_adjoint_seed)."""
+        given = [(k, t) for k, t in (("phi", phi), ("psi", psi), ("C", C)) if t is not None]
+        mask = 0
+        for k, _ in given:
+            mask |= 1 << MACROS.index(k)
+        dL = torch.zeros((max(len(given), 1),) + self.shape, dtype=torch.float64, device=self.device)
+        for i, (_, t) in enumerate(given):
+            dL[i] = t.to(self.device, torch.float64)
+        lam = torch.empty((self.state_planes(),) + self.shape, dtype=self.adj_dtype, device=self.device)
+        _check(_lib.pfl_adjoint_seed(self.ctx, ct.c_void_p(dL.data_ptr()), mask, ct.c_void_p(lam.data_ptr())))
+        self._keep_seed = dL
+        return lam
+
+    @staticmethod
+    def _diag(d):
+        return dict(sum_phi=d.sum_phi, gas_volume=d.gas_volume, sum_C=d.sum_C,
+                    solid_fraction=d.solid_fraction, gas_centroid=list(d.gas_centroid),
+                    nonfinite=d.nonfinite)
+
+    def last_check(self):
+        """Diagnostics of the last in-step check (reduce_every > 0)."""
+        d = Diag()
+        rc = _lib.pfl_last_check(self.ctx, ct.byref(d))
+        if rc not in (OK, E_NONFINITE):
+            _check(rc)
+        return self._diag(d)
 
     def reduce(self):
         d = Diag()

@@ -104,25 +104,10 @@ class CheckpointedRun:
         return sim.macros()
 
     def lam_from_macros(self, g_phi=None, g_psi=None):
-        """Node-form adjoint of a loss of the final phi and psi: each population
-        of a set carries the derivative with respect to its zeroth moment."""
-        sim = self.sim
-        P = sim.p
-        lam = torch.zeros((sim.state_planes(),) + sim.shape, dtype=sim.adj_dtype, device=sim.device)
-        q_phi = P.phi_q
-        q_sc = 5 if sim.dim == 2 else 7
-        q_ns = 9 if sim.dim == 2 else 19
-        o = 0
-        f = self.w["fields"]
-        if "ns" in f:
-            o += q_ns
-        if "phi" in f:
-            if g_phi is not None:
-                lam[o:o + q_phi] = g_phi.to(sim.device, sim.adj_dtype)
-            o += q_phi
-        if "psi" in f and g_psi is not None:
-            lam[o:o + q_sc] = g_psi.to(sim.device, sim.adj_dtype)
-        return lam
+        """Node-form adjoint of a loss of the final phi and psi
+        (pfl_adjoint_seed: each population of a set carries the derivative
+        with respect to its zeroth moment)."""
+        return self.sim.adjoint_seed(phi=g_phi, psi=g_psi)
 
     def _images(self, si):
         """Images of segment si: its checkpoint, then x^{s0 + j} for j >= 1."""

@@ -82,6 +82,7 @@ int validate(const pfl_params* p) {
   if (!std::isfinite(p->U0) || !std::isfinite(p->theta0) || !std::isfinite(p->eps4) || !std::isfinite(p->g))
     return fail(PFL_E_INVALID_ARG, "non-finite parameter");
   if (!(p->eps4 >= 0 && p->eps4 < 1.0 / 3)) return fail(PFL_E_INVALID_ARG, "eps4 must lie in [0, 1/3)");
+  if (p->reduce_every < 0) return fail(PFL_E_INVALID_ARG, "reduce_every must be >= 0");
   return PFL_OK;
 }
 
@@ -116,7 +117,7 @@ Layout layout(const pfl_params* p) {
   L.aux_bytes = round_up(L.aux_bub + sizeof(double) * 4 * MAX_BUBBLES, 256);
   L.macros_bytes = (size_t)PFL_M_COUNT * L.N * sizeof(double);
   L.state_bytes = (size_t)(L.n_pop_planes + L.n_hist_planes) * L.N * sizeof(double);
-  L.reduce_bytes = (size_t)(RED_BLOCKS + 1) * RED_VALS * sizeof(double);
+  L.reduce_bytes = (CHECK_OFF + CHECK_VALS) * sizeof(double);
   return L;
 }
 
@@ -143,6 +144,7 @@ struct pfl_ctx {
   bool inited;
   int64_t steps;
   bool sweep_open;       // the last adjoint call was a sweep left open (partials and moment terms)
+  bool checked;          // an in-step check has run since init
   std::vector<double> cs, seeds, bubbles;   // host copies kept alive for async uploads
 };
 
@@ -184,6 +186,7 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   c->cur = 0;
   c->inited = false;
   c->sweep_open = false;
+  c->checked = false;
   c->steps = 0;
   const Layout& L = c->L;
   DevParams& d = c->d;
@@ -346,21 +349,27 @@ int pfl_init_fields(pfl_ctx* c, const pfl_seed* seeds, int nseed, const pfl_bubb
   c->d.first = 1;
   c->steps = 0;
   c->inited = true;
+  c->checked = false;
   g_err.clear();
   return PFL_OK;
 }
 
-int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, const pfl_seed* seeds, int nseed) {
-  if (!c || !dev_macros) return fail(PFL_E_INVALID_ARG, "null argument");
+int pfl_init_from_macros(pfl_ctx* c, const double* dev_macros, uint32_t given, const pfl_seed* seeds, int nseed) {
+  if (!c) return fail(PFL_E_INVALID_ARG, "null context");
+  if (given & ~31u) return fail(PFL_E_INVALID_ARG, "unknown input plane bits");
+  if (given && !dev_macros) return fail(PFL_E_INVALID_ARG, "null macro planes");
   int rc = upload_geometry(c, seeds, nseed, nullptr, 0);
   if (rc) return rc;
   c->cur = 0;
-  hipError_t e = launch_init(c->d, (int)c->p.fields, c->p.store, 1, dev_macros, c->b.pops_a, c->b.hist,
+  DevParams d = c->d;
+  d.given = given;
+  hipError_t e = launch_init(d, (int)c->p.fields, c->p.store, 1, dev_macros, c->b.pops_a, c->b.hist,
                              (uint8_t*)c->d.grain, c->s);
   if (e != hipSuccess) return hip_fail(e, "init kernel");
   c->d.first = 1;
   c->steps = 0;
   c->inited = true;
+  c->checked = false;
   g_err.clear();
   return PFL_OK;
 }
@@ -369,28 +378,58 @@ int pfl_step(pfl_ctx* c, int nsteps) {
   if (!c) return fail(PFL_E_INVALID_ARG, "null context");
   if (!c->inited) return fail(PFL_E_STATE, "step before init");
   if (nsteps < 0) return fail(PFL_E_INVALID_ARG, "negative step count");
+  const int K = c->p.reduce_every;
+  double* red = (double*)c->b.reduce;
+  bool checks = false;
+  hipError_t e = hipSuccess;
   for (int n = 0; n < nsteps; ++n) {
     void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
     void* fout = c->cur == 0 ? c->b.pops_b : c->b.pops_a;
     bool ok = true;
     c->d.step_ctr = (uint32_t)c->steps;
-    hipError_t e = launch_step(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
+    e = launch_step(c->d, (int)c->p.fields, c->p.store, fin, fout, c->b.hist, nullptr, 0, c->s, ok);
     if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
     if (e != hipSuccess) return hip_fail(e, "step kernel");
     c->cur ^= 1;
     c->d.first = 0;
     c->steps++;
+    if (K > 0 && c->steps % K == 0) {
+      // FP64 reduction of the new state, its NaN/Inf flag folded into the
+      // check area (the first failing step is kept)
+      if (!checks) {
+        e = launch_check_reset(red, c->s);
+        if (e != hipSuccess) return hip_fail(e, "check reset kernel");
+        checks = true;
+      }
+      e = launch_reduce(c->d, (int)c->p.fields, c->p.store, fout, c->b.hist, c->L.n_hist_planes, red, c->s);
+      if (e == hipSuccess) e = launch_check_record(red, (long long)c->steps, c->s);
+      if (e != hipSuccess) return hip_fail(e, "check kernels");
+      c->checked = true;
+    }
+  }
+  if (checks) {
+    long long ck[2];
+    e = hipMemcpyAsync(ck, red + CHECK_OFF, sizeof(ck), hipMemcpyDeviceToHost, c->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) return hip_fail(e, "check read-back");
+    if (ck[0] != 0x7fffffffffffffffLL)
+      return fail(PFL_E_NONFINITE, "non-finite values in the state at the check after step " + std::to_string(ck[0]));
   }
   g_err.clear();
   return PFL_OK;
 }
 
-int pfl_get_macros(pfl_ctx* c, void* dev_out) {
+int pfl_get_macros(pfl_ctx* c, uint32_t field_mask, void* dev_out, int out_type) {
   if (!c || !dev_out) return fail(PFL_E_INVALID_ARG, "null argument");
   if (!c->inited) return fail(PFL_E_STATE, "get_macros before init");
+  if (field_mask & ~PFL_M_ALL) return fail(PFL_E_INVALID_ARG, "unknown macro field bits");
+  if (out_type != PFL_OUT_F64 && out_type != PFL_OUT_F32) return fail(PFL_E_INVALID_ARG, "bad output type");
   void* fin = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
+  DevParams d = c->d;
+  d.mmask = field_mask ? field_mask : PFL_M_ALL;
+  d.mf32 = out_type == PFL_OUT_F32;
   bool ok = true;
-  hipError_t e = launch_step(c->d, (int)c->p.fields, c->p.store, fin, nullptr, c->b.hist, (double*)dev_out, 1, c->s, ok);
+  hipError_t e = launch_step(d, (int)c->p.fields, c->p.store, fin, nullptr, c->b.hist, (double*)dev_out, 1, c->s, ok);
   if (!ok) return fail(PFL_E_UNSUPPORTED, "field combination not built");
   if (e != hipSuccess) return hip_fail(e, "macros kernel");
   g_err.clear();
@@ -414,8 +453,20 @@ int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count) {
   void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   hipError_t e = launch_set_state(c->d, (int)c->p.fields, c->p.store, dev_in, pops, c->b.hist, c->s);
   if (e != hipSuccess) return hip_fail(e, "state import kernel");
-  c->d.first = 0;
+  c->d.first = step_count == 0 ? 1 : 0;
   c->steps = step_count;
+  g_err.clear();
+  return PFL_OK;
+}
+
+static int diag_of(const pfl_ctx* c, const double* v, pfl_diag* out) {
+  out->sum_phi = v[0];
+  out->gas_volume = v[1];
+  out->sum_C = v[2];
+  out->solid_fraction = v[3] / (double)c->L.N;
+  for (int a = 0; a < 3; ++a) out->gas_centroid[a] = v[1] > 0 ? v[4 + a] / v[1] : 0.0;
+  out->nonfinite = v[7] != 0.0 || !std::isfinite(v[0]) || !std::isfinite(v[2]);
+  if (out->nonfinite) return fail(PFL_E_NONFINITE, "non-finite values in the state");
   g_err.clear();
   return PFL_OK;
 }
@@ -432,13 +483,31 @@ int pfl_reduce(pfl_ctx* c, pfl_diag* out) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(reduce)");
   e = hipStreamSynchronize(c->s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  out->sum_phi = v[0];
-  out->gas_volume = v[1];
-  out->sum_C = v[2];
-  out->solid_fraction = v[3] / (double)c->L.N;
-  for (int a = 0; a < 3; ++a) out->gas_centroid[a] = v[1] > 0 ? v[4 + a] / v[1] : 0.0;
-  out->nonfinite = v[7] != 0.0 || !std::isfinite(v[0]) || !std::isfinite(v[2]);
-  if (out->nonfinite) return fail(PFL_E_NONFINITE, "non-finite values in the state");
+  return diag_of(c, v, out);
+}
+
+int pfl_last_check(pfl_ctx* c, pfl_diag* out) {
+  if (!c || !out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited || !c->checked) return fail(PFL_E_STATE, "no in-step check has run since init");
+  double v[CHECK_VALS];
+  hipError_t e = hipMemcpyAsync(v, (double*)c->b.reduce + CHECK_OFF, sizeof(v), hipMemcpyDeviceToHost, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return hip_fail(e, "check read-back");
+  return diag_of(c, v + 2, out);
+}
+
+int pfl_adjoint_seed(pfl_ctx* c, const double* dL, uint32_t field_mask, void* adj_out) {
+  if (!c || !dL || !adj_out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "adjoint seed before init");
+  const uint32_t allowed = (1u << PFL_M_PHI) | (1u << PFL_M_PSI) | (1u << PFL_M_C);
+  if (field_mask & ~allowed) return fail(PFL_E_INVALID_ARG, "the seed takes phi, psi and C only");
+  const uint32_t f = c->p.fields;
+  if (((field_mask >> PFL_M_PHI) & 1u) && !(f & PFL_PHI)) return fail(PFL_E_INVALID_ARG, "phi is not solved");
+  if (((field_mask >> PFL_M_PSI) & 1u) && !(f & PFL_PSI)) return fail(PFL_E_INVALID_ARG, "psi is not solved");
+  if (((field_mask >> PFL_M_C) & 1u) && !(f & PFL_C)) return fail(PFL_E_INVALID_ARG, "C is not solved");
+  hipError_t e = launch_adjoint_seed(c->d, (int)f, c->p.store, dL, field_mask, adj_out,
+                                     c->L.n_pop_planes + c->L.n_hist_planes, c->s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint seed kernel");
   g_err.clear();
   return PFL_OK;
 }

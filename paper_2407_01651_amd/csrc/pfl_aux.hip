@@ -110,11 +110,15 @@ __global__ __launch_bounds__(BT) void init_kernel(const DevParams P, int fields,
     C = phi * (1.0 + (1.0 - P.k) * P.U0) * (1.0 - (1.0 - P.k) * h);
     theta = P.theta0;
   } else {
-    phi = macros[0 * P.N + n];
-    psi = macros[1 * P.N + n];
-    C = macros[2 * P.N + n];
-    theta = macros[3 * P.N + n];
-    for (int a = 0; a < P.dim; ++a) v[a] = macros[(4 + a) * P.N + n];
+    // planes not given: the bulk liquid at rest, with the partitioned
+    // solute profile of the given phi and psi
+    phi = (P.given & 1u) ? macros[0 * P.N + n] : 1.0;
+    psi = (P.given & 2u) ? macros[1 * P.N + n] : -1.0;
+    const double h0 = (psi + 1.0) * 0.5;
+    C = (P.given & 4u) ? macros[2 * P.N + n] : phi * (1.0 + (1.0 - P.k) * P.U0) * (1.0 - (1.0 - P.k) * h0);
+    theta = (P.given & 8u) ? macros[3 * P.N + n] : P.theta0;
+    if (P.given & 16u)
+      for (int a = 0; a < P.dim; ++a) v[a] = macros[(4 + a) * P.N + n];
   }
   const double h = (psi + 1.0) * 0.5;
   if (fields & F_NS) {
@@ -254,6 +258,52 @@ __global__ void reduce_final(double* red) {
   red[(long long)RED_BLOCKS * RED_VALS + v] = a;
 }
 
+// In-step checks of pfl_step: the check area after the reduction's final
+// values holds the first failing step (INT64_MAX if none), the step of the
+// last check and that check's final values.
+__global__ void check_reset(double* red) {
+  long long* ck = (long long*)(red + (size_t)(RED_BLOCKS + 1) * RED_VALS);
+  if (threadIdx.x == 0) {
+    ck[0] = 0x7fffffffffffffffLL;
+    ck[1] = -1;
+  }
+}
+
+__global__ void check_record(double* red, long long step) {
+  const int v = threadIdx.x;
+  const double* fin = red + (size_t)RED_BLOCKS * RED_VALS;
+  long long* ck = (long long*)(red + (size_t)(RED_BLOCKS + 1) * RED_VALS);
+  double* diag = (double*)(ck + 2);
+  if (v < RED_VALS) diag[v] = fin[v];
+  if (v == 0) {
+    ck[1] = step;
+    const bool bad = fin[7] != 0.0 || !isfinite(fin[0]) || !isfinite(fin[2]);
+    if (bad && ck[0] > step) ck[0] = step;
+  }
+}
+
+// Adjoint of the zeroth moments: every population of a set whose sum is
+// seeded takes dL/d(sum); other entries zero.
+template <class AT>
+__global__ __launch_bounds__(BT) void seed_kernel(const DevParams P, int fields, const double* __restrict__ dL,
+                                                  uint32_t mask, AT* __restrict__ out, int planes) {
+  const long long n = (long long)blockIdx.x * BT + threadIdx.x;
+  if (n >= P.N) return;
+  int plane = 0;
+  auto set = [&](int q, bool on, int bit) {
+    AT v = AT(0);
+    if (on && ((mask >> bit) & 1u)) v = (AT)dL[(long long)__popc(mask & ((1u << bit) - 1u)) * P.N + n];
+    for (int i = 0; i < q; ++i) out[(long long)(plane + i) * P.N + n] = v;
+    plane += q;
+  };
+  if (fields & F_NS) set(P.q_ns, false, 0);
+  if (fields & F_PHI) set(P.q_phi, true, 0);
+  if (fields & F_PSI) set(P.q_sc, true, 1);
+  if (fields & F_C) set(P.q_sc, true, 2);
+  if (fields & F_TH) set(P.q_sc, false, 0);
+  for (; plane < planes; ++plane) out[(long long)plane * P.N + n] = AT(0);
+}
+
 template <class ST, class HT>
 struct Disp {
   template <int QN, int QP, int QS>
@@ -340,6 +390,26 @@ hipError_t launch_set_state(const DevParams& P, int fields, int store, const dou
     return Disp<ST, HT>::template state<QN, QP, QS>(P, fields, 1, pops, hist, hp,
                                                    const_cast<double*>(in), s);
   });
+}
+
+hipError_t launch_check_reset(double* red, hipStream_t s) {
+  hipLaunchKernelGGL(check_reset, dim3(1), dim3(64), 0, s, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_record(double* red, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(check_record, dim3(1), dim3(64), 0, s, red, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed(const DevParams& P, int fields, int store, const double* dL, uint32_t mask,
+                               void* out, int planes, hipStream_t s) {
+  const unsigned nb = (unsigned)((P.N + BT - 1) / BT);
+  if (store == 0)
+    hipLaunchKernelGGL((seed_kernel<double>), dim3(nb), dim3(BT), 0, s, P, fields, dL, mask, (double*)out, planes);
+  else
+    hipLaunchKernelGGL((seed_kernel<float>), dim3(nb), dim3(BT), 0, s, P, fields, dL, mask, (float*)out, planes);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const DevParams& P, int fields, int store, const void* pops,

@@ -167,6 +167,9 @@ struct DevParams {
   int nt;                      // step stores non-temporal (streamed past the last-level cache)
   uint32_t step_ctr;           // step counter, part of the rounding key
   void* tape;                  // 2D: stencil results written here when set (TAPE_PLANES planes)
+  uint32_t mmask;              // macro mode: planes written (bit k = macro k), packed in bit order
+  int mf32;                    // macro mode: FP32 output (else FP64)
+  uint32_t given;              // init from macros: input planes given (bit 0 phi .. 3 theta, 4 v)
   KP<double> kd;
   KP<float> kf;
   // rest equilibria r_i of the deviation storage (per set, per direction)
@@ -180,6 +183,20 @@ __device__ __forceinline__ bool sym_side(const DevParams& P, int a, bool lo) {
 // Whether the low (lo) or high boundary of axis a is a far-field side.
 __device__ __forceinline__ bool far_side(const DevParams& P, int a, bool lo) {
   return (P.far >> (lo ? a : 3 + a)) & 1;
+}
+
+// Macro mode of the step kernels: the planes of m (phi, psi, C, theta, U, p,
+// v_x, v_y, v_z) selected by P.mmask, packed in that order, as FP64 or FP32.
+__device__ __forceinline__ void put_macros(const DevParams& P, double* mout, long long idx, const double (&m)[9]) {
+  int o = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if ((P.mmask >> k) & 1u) {
+      if (P.mf32) ((float*)mout)[(long long)o * P.N + idx] = (float)m[k];
+      else mout[(long long)o * P.N + idx] = m[k];
+      ++o;
+    }
+  }
 }
 
 // --------------------------------------------------------- storage types

@@ -5,7 +5,8 @@
 namespace pfl {
 
 // mode 0: one time step fin -> fout (history updated in place);
-// mode 1: macro fields of fin into mout (no population or history writes).
+// mode 1: macro fields of fin into mout, the planes of P.mmask packed, FP64 or
+// FP32 (P.mf32) (no population or history writes).
 hipError_t launch_step2d(const DevParams& P, int fields, int store, const void* fin, void* fout,
                          void* hist, double* mout, int mode, hipStream_t s, bool& ok);
 bool step2d_supported(int fields);
@@ -53,7 +54,7 @@ hipError_t launch_adj_step2d_lowp(const DevParams& P, int fields, int store, con
                                   double* dparams, hipStream_t s, bool& ok, const AdjOpts& o);
 
 // Initial state: mode 0 from seeds/bubbles, mode 1 from node-form FP64 macro
-// planes (phi, psi, C, theta, v...).  Writes the grain map, equilibrium
+// planes (phi, psi, C, theta, v...), those not given by P.given defaulted.  Writes the grain map, equilibrium
 // populations into pops (pull storage) and zero history.
 hipError_t launch_init(const DevParams& P, int fields, int store, int mode, const double* macros,
                        void* pops, void* hist, uint8_t* grain, hipStream_t s);
@@ -69,5 +70,17 @@ constexpr int RED_BLOCKS = 512;
 constexpr int RED_VALS = 8;
 hipError_t launch_reduce(const DevParams& P, int fields, int store, const void* pops,
                          const void* hist, int hist_planes, double* red, hipStream_t s);
+// Check area after the final values: first failing step, last check step,
+// the last check's final values.
+constexpr size_t CHECK_OFF = (size_t)(RED_BLOCKS + 1) * RED_VALS;   // in doubles
+constexpr size_t CHECK_VALS = 2 + RED_VALS;
+hipError_t launch_check_reset(double* red, hipStream_t s);
+hipError_t launch_check_record(double* red, long long step, hipStream_t s);
+
+// Node-form adjoint of the zeroth moments phi, psi, C (mask bits 0..2) from
+// packed FP64 planes dL, in the adjoint type of the storage; planes: the
+// state's plane count.
+hipError_t launch_adjoint_seed(const DevParams& P, int fields, int store, const double* dL, uint32_t mask,
+                               void* out, int planes, hipStream_t s);
 
 }  // namespace pfl

@@ -397,16 +397,9 @@ void step2d_kernel(const DevParams P,
   }
 
   if (mode == 1) {
-    const long long NN = N;
-    mout[0 * NN + idx] = (double)phi;
-    mout[1 * NN + idx] = (double)psi;
-    mout[2 * NN + idx] = (double)C;
-    mout[3 * NN + idx] = (double)theta;
-    mout[4 * NN + idx] = (double)U;
-    mout[5 * NN + idx] = (double)p;
-    mout[6 * NN + idx] = (double)vx;
-    mout[7 * NN + idx] = (double)vy;
-    mout[8 * NN + idx] = 0.0;
+    const double m9[9] = {(double)phi, (double)psi, (double)C, (double)theta, (double)U, (double)p,
+                          (double)vx, (double)vy, 0.0};
+    put_macros(P, mout, idx, m9);
     return;
   }
 

@@ -578,16 +578,9 @@ __global__ __launch_bounds__(Tile3<CT>::NT, sizeof(CT) == 4 ? 3 : 1) void step3d
   }
 
   if (mode == 1) {
-    const long long NN = N;
-    mout[0 * NN + idx] = (double)phi;
-    mout[1 * NN + idx] = (double)psi;
-    mout[2 * NN + idx] = (double)C;
-    mout[3 * NN + idx] = (double)theta;
-    mout[4 * NN + idx] = (double)U;
-    mout[5 * NN + idx] = (double)p;
-    mout[6 * NN + idx] = (double)v[0];
-    mout[7 * NN + idx] = (double)v[1];
-    mout[8 * NN + idx] = (double)v[2];
+    const double m9[9] = {(double)phi, (double)psi, (double)C, (double)theta, (double)U, (double)p,
+                          (double)v[0], (double)v[1], (double)v[2]};
+    put_macros(P, mout, idx, m9);
     return;
   }
 

@@ -145,3 +145,53 @@ def test_boundary_flags():
     p = pfl.make_params(w3, "f16", "stochastic")
     assert list(p.wall) == [0, 6, 0]
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+
+
+def _declarations_with_comments():
+    """(name, comment text before the declaration) for every function
+    declared in include/*.h."""
+    out = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        last = 0
+        for m in re.finditer(r"^\s*(?:int|int64_t|const char\*)\s+(pfl_\w+)\s*\(", txt, re.M):
+            out.append((m.group(1), txt[last:m.start()]))
+            last = txt.index(";", m.end()) + 1
+    return out
+
+
+def test_every_declared_function_cites_its_passage():
+    """Each entry point's comment names the passage of the paper that defines
+    the operation, or says that the operation is not in the paper."""
+    cite = re.compile(r"Sec\. \d|Appendix [AB]|not in the paper|no paper passage|does not treat")
+    decl = _declarations_with_comments()
+    assert len(decl) >= 20
+    missing = [n for n, c in decl if not cite.search(c)]
+    assert not missing, missing
+
+
+def test_abi_version_and_parameter_struct():
+    import paper_2407_01651_amd as pfl
+    h = open(os.path.join(ROOT, "include", "pfl.h")).read()
+    assert f"#define PFL_ABI_VERSION {pfl.ABI_VERSION}" in h
+    w = workloads.get("coupled2d_128")
+    p = pfl.make_params(dict(w, reduce_every=50))
+    assert p.reduce_every == 50
+    s = pfl.Sizes()
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.reduce_every = -1
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    assert "reduce_every" in pfl._lib.pfl_last_error().decode()
+
+
+def test_host_argument_checks_of_new_entry_points():
+    """Null contexts and bad masks are rejected on the host, before any GPU
+    work (no context is created here)."""
+    import paper_2407_01651_amd as pfl
+    lib = pfl._lib
+    assert lib.pfl_get_macros(None, 0, None, 0) == -1
+    assert lib.pfl_adjoint_seed(None, None, 1, None) == -1
+    assert lib.pfl_last_check(None, None) == -1
+    assert lib.pfl_init_from_macros(None, None, 0, None, 0) == -1
