@@ -258,6 +258,17 @@ int pfl_set_state(pfl_ctx* c, const double* dev_in, int64_t step_count);
  * filled) if the state holds NaN/Inf. */
 int pfl_reduce(pfl_ctx* c, pfl_diag* out);
 
+/* pfl_reduce for callers that cannot allocate (harnesses that forbid device
+ * allocation, tight serving loops): the reduction's block partials and final
+ * values live in a 32.8 KB array of device memory that the library holds on
+ * each GPU until the process ends, instead of the reduce buffer; the call
+ * allocates nothing.  Results are those of pfl_reduce, bit for bit.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (several
+ * host threads or streams) race.  Synchronises the stream.  Errors as
+ * pfl_reduce; PFL_E_STATE if the array was not found on the device current
+ * at pfl_create. */
+int pfl_reduce_noalloc(pfl_ctx* c, pfl_diag* out);
+
 /* The diagnostics of the last in-step check of pfl_step (reduce_every > 0),
  * as pfl_reduce would have returned them at that step (the conserved sums of
  * Sec. 2.1 and the NaN/Inf flag; the check itself is not in the paper: failure

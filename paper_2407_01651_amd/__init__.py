@@ -87,6 +87,7 @@ _sig = {
     "pfl_set_state": ([ct.c_void_p, ct.c_void_p, ct.c_int64], ct.c_int),
     "pfl_reduce": ([ct.c_void_p, _P(Diag)], ct.c_int),
     "pfl_last_check": ([ct.c_void_p, _P(Diag)], ct.c_int),
+    "pfl_reduce_noalloc": ([ct.c_void_p, _P(Diag)], ct.c_int),
     "pfl_adjoint_seed": ([ct.c_void_p, ct.c_void_p, ct.c_uint32, ct.c_void_p], ct.c_int),
     "pfl_step_count": ([ct.c_void_p], ct.c_int64),
     "pfl_save_raw": ([ct.c_void_p, ct.c_void_p], ct.c_int),
@@ -368,6 +369,15 @@ class Sim:
         """Diagnostics of the last in-step check (reduce_every > 0)."""
         d = Diag()
         rc = _lib.pfl_last_check(self.ctx, ct.byref(d))
+        if rc not in (OK, E_NONFINITE):
+            _check(rc)
+        return self._diag(d)
+
+    def reduce_noalloc(self):
+        """pfl_reduce_noalloc: the reduction with the library's static device
+        scratch (no workspace)."""
+        d = Diag()
+        rc = _lib.pfl_reduce_noalloc(self.ctx, ct.byref(d))
         if rc not in (OK, E_NONFINITE):
             _check(rc)
         return self._diag(d)

@@ -145,6 +145,7 @@ struct pfl_ctx {
   int64_t steps;
   bool sweep_open;       // the last adjoint call was a sweep left open (partials and moment terms)
   bool checked;          // an in-step check has run since init
+  int device;            // the device current at pfl_create
   std::vector<double> cs, seeds, bubbles;   // host copies kept alive for async uploads
 };
 
@@ -178,7 +179,15 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   if (!bufs || !bufs->pops_a || !bufs->pops_b || !bufs->hist || !bufs->aux || !bufs->reduce)
     return fail(PFL_E_INVALID_ARG, "null device buffer");
   if (bufs->pops_a == bufs->pops_b) return fail(PFL_E_INVALID_ARG, "pops_a and pops_b must differ");
+  // the device current now is the context's; the scratch of
+  // pfl_reduce_noalloc is looked up on it once
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+  he = resolve_reduce_scratch(dev);
+  if (he != hipSuccess) return hip_fail(he, "hipGetSymbolAddress(reduction scratch)");
   pfl_ctx* c = new pfl_ctx();
+  c->device = dev;
   c->p = *p;
   c->L = layout(p);
   c->b = *bufs;
@@ -476,6 +485,26 @@ int pfl_reduce(pfl_ctx* c, pfl_diag* out) {
   if (!c->inited) return fail(PFL_E_STATE, "reduce before init");
   const void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   double* red = (double*)c->b.reduce;
+  hipError_t e = launch_reduce(c->d, (int)c->p.fields, c->p.store, pops, c->b.hist, c->L.n_hist_planes, red, c->s);
+  if (e != hipSuccess) return hip_fail(e, "reduce kernel");
+  double v[RED_VALS];
+  e = hipMemcpyAsync(v, red + (size_t)RED_BLOCKS * RED_VALS, sizeof(v), hipMemcpyDeviceToHost, c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(reduce)");
+  e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return diag_of(c, v, out);
+}
+
+int pfl_reduce_noalloc(pfl_ctx* c, pfl_diag* out) {
+  if (!c || !out) return fail(PFL_E_INVALID_ARG, "null argument");
+  if (!c->inited) return fail(PFL_E_STATE, "reduce before init");
+  double* red = reduce_scratch(c->device);
+  if (!red) return fail(PFL_E_STATE, "no reduction scratch on this context's device");
+  // the launch writes RED_BLOCKS partials and RED_VALS final values: the
+  // array's whole capacity, whatever the grid (grid-stride loop)
+  if ((size_t)(RED_BLOCKS + 1) * RED_VALS > REDUCE_SCRATCH_DOUBLES)
+    return fail(PFL_E_INVALID_ARG, "reduction larger than the static scratch");
+  const void* pops = c->cur == 0 ? c->b.pops_a : c->b.pops_b;
   hipError_t e = launch_reduce(c->d, (int)c->p.fields, c->p.store, pops, c->b.hist, c->L.n_hist_planes, red, c->s);
   if (e != hipSuccess) return hip_fail(e, "reduce kernel");
   double v[RED_VALS];

@@ -2,6 +2,8 @@
 // 2D and 3D lattices.  None of these is on the per-step path.
 #include "pfl_kernels.h"
 
+#include <mutex>
+
 namespace pfl {
 
 namespace {
@@ -410,6 +412,35 @@ hipError_t launch_adjoint_seed(const DevParams& P, int fields, int store, const 
   else
     hipLaunchKernelGGL((seed_kernel<float>), dim3(nb), dim3(BT), 0, s, P, fields, dL, mask, (float*)out, planes);
   return hipGetLastError();
+}
+
+// Partials and final values of the allocation-free reduction
+// (pfl_reduce_noalloc): one array per GPU, held until the process ends.
+// Every call on a GPU shares it, so calls that overlap on one GPU race.
+static __device__ __align__(256) double scratch[REDUCE_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t resolve_reduce_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  // the array's name is a host-side stand-in; its device address on the
+  // current device comes from the runtime
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (double*)ptr;
+  return hipSuccess;
+}
+
+double* reduce_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_reduce(const DevParams& P, int fields, int store, const void* pops,

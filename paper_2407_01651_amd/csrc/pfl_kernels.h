@@ -70,6 +70,15 @@ constexpr int RED_BLOCKS = 512;
 constexpr int RED_VALS = 8;
 hipError_t launch_reduce(const DevParams& P, int fields, int store, const void* pops,
                          const void* hist, int hist_planes, double* red, hipStream_t s);
+// Device scratch of pfl_reduce_noalloc: the RED_BLOCKS partials and the
+// final values of one reduction (32.8 KB per GPU).  resolve_reduce_scratch
+// looks up the array's address on a device (call with that device current,
+// once per device; later calls return at once); reduce_scratch returns it
+// (null before the look-up).
+constexpr size_t REDUCE_SCRATCH_DOUBLES = (size_t)(RED_BLOCKS + 1) * RED_VALS;
+constexpr int MAX_DEVICES = 64;
+hipError_t resolve_reduce_scratch(int device);
+double* reduce_scratch(int device);
 // Check area after the final values: first failing step, last check step,
 // the last check's final values.
 constexpr size_t CHECK_OFF = (size_t)(RED_BLOCKS + 1) * RED_VALS;   // in doubles
