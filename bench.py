@@ -1,13 +1,19 @@
 """Throughput of the fused phase-field LB step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--store f64|f32|f16|bf16]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps R] [--config NAME] [--store f64|f32|f16|bf16]
 
 A step is one fused time step of every active field over the whole grid
-(one kernel launch).  Default workload: the isothermal binary-alloy
-dendrite run, 1024 x 1024, four rotated seeds, FP64, timed over K steps after
-W warm-up steps with the inputs resident in HBM.  The same run in FP32 is
-timed beside it.  Prints ONE JSON line with MLUPS, the HBM roofline fraction
-of the step kernel and the CPU oracle timed on a bounded sample.
+(one kernel launch).  Headline: the coupled 3D workload, 256^3 nodes
+(D3Q19 flow, D3Q7 bubble phase, order parameter, solute and heat; 8 seeds,
+12 bubbles, density ratio 100), in FP64, the largest single-GPU
+configuration; after W warm-up steps, R repetitions of K timed steps each,
+inputs resident in HBM, the median repetition reported.  The same workload
+in FP32, FP16 and BF16 storage, the coupled 2D 2048^2 workload in every
+storage type and the alloy 1024^2 workload are timed beside it as variants
+(configurations whose state fits the 256 MiB last-level cache are flagged).
+Prints ONE JSON line with MLUPS, the HBM roofline fraction of the step kernel,
+the adjoint/forward cost ratio and the CPU oracle timed on a bounded sample of
+the headline workload.
 """
 from __future__ import annotations
 
@@ -15,6 +21,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -22,53 +29,72 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "step2d_alloy2d_1024.md")
-KERNEL_SOURCES = ("paper_2407_01651_amd/csrc/pfl_step2d.hip", "paper_2407_01651_amd/csrc/pfl_step2d_impl.h",
-                  "paper_2407_01651_amd/csrc/pfl_step2d_lowp.hip", "paper_2407_01651_amd/csrc/pfl_step2d.h",
-                  "paper_2407_01651_amd/csrc/pfl_util.h", "paper_2407_01651_amd/csrc/pfl_dev.h",
-                  "paper_2407_01651_amd/build.py")
+LLC_BYTES = 256 << 20
+CSRC = "paper_2407_01651_amd/csrc/"
+# committed rocprofv3 summaries of the step kernels, by dimension, and the
+# sources whose hash they were taken on
+PROFILES = {
+    3: ("profiles/step3d_coupled3d_256.md",
+        (CSRC + "pfl_step3d.hip", CSRC + "pfl_step3d_lowp.hip", CSRC + "pfl_step3d_impl.h",
+         CSRC + "pfl_util.h", CSRC + "pfl_dev.h", "paper_2407_01651_amd/build.py")),
+    2: ("profiles/step2d_coupled2d_2048.md",
+        (CSRC + "pfl_step2d.hip", CSRC + "pfl_step2d_lowp.hip", CSRC + "pfl_step2d_impl.h",
+         CSRC + "pfl_step2d.h", CSRC + "pfl_util.h", CSRC + "pfl_dev.h", "paper_2407_01651_amd/build.py")),
+}
+DEFAULT_VARIANTS = ("coupled3d_256:f32,coupled3d_256:f16,coupled3d_256:bf16,"
+                    "coupled2d_2048:f64,coupled2d_2048:f32,coupled2d_2048:f16,coupled2d_2048:bf16,"
+                    "coupled2d_2048_q9:f16,alloy2d_1024:f64,alloy2d_1024:f32")
 
 
-def measured_traffic(store):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
-    or None when the step kernel changed since those counters were taken."""
+def source_hash(files):
     import hashlib
-    try:
-        txt = open(PROFILE).read()
-    except OSError:
-        return None
-    kv = dict(l.strip().split(": ", 1) for l in txt.splitlines() if ": " in l and l.startswith("    "))
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if kv.get("source_sha256") != h.hexdigest():
-        return None
-    v = kv.get(f"traffic_bytes_per_launch_{store}")
-    return float(v) if v else None
+    return h.hexdigest()
+
+
+def profile_figures(dim, workload, store):
+    """(calibrated HBM bytes per launch, average kernel duration in ns) of the
+    step kernel from the committed rocprofv3 summary, each None when the
+    summary is missing, is for another workload, or the kernel's sources
+    changed since it was taken."""
+    path, files = PROFILES[dim]
+    try:
+        txt = open(os.path.join(ROOT, path)).read()
+    except OSError:
+        return None, None
+    kv = dict(l.strip().split(": ", 1) for l in txt.splitlines() if ": " in l and l.startswith("    "))
+    if kv.get("workload") != workload or kv.get("source_sha256") != source_hash(files):
+        return None, None
+    t = kv.get(f"traffic_bytes_per_launch_{store}")
+    a = kv.get(f"avg_duration_ns_{store}")
+    return (float(t) if t else None), (float(a) if a else None)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--config", default="alloy2d_1024")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps per repetition")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions; the median is reported")
+    ap.add_argument("--config", default="coupled3d_256")
     ap.add_argument("--store", default="f64")
-    ap.add_argument("--also", default="f32", help="comma list of extra storage types timed beside")
-    ap.add_argument("--extra", default="coupled2d_2048:f16,coupled2d_2048:bf16,coupled2d_2048:f32,"
-                                       "coupled2d_2048_q9:f16,coupled3d_256:f16",
-                    help="comma list of config:storage pairs timed beside (variants)")
+    ap.add_argument("--variants", default=DEFAULT_VARIANTS,
+                    help="comma list of config:storage pairs timed beside the headline ('' for none)")
     ap.add_argument("--rounding", default="stochastic", choices=("stochastic", "nearest"),
                     help="rounding into 16-bit storage")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward cost ratio on the 512^2 adjoint workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--write-policy", default="auto", choices=("auto", "cached", "stream"),
-                    help="cache policy of the step's stores (auto: streaming in 2D FP64/FP32 when the state exceeds the "
-                         "256 MiB last-level cache)")
+                    help="cache policy of the step's stores (auto: streaming when the state exceeds the "
+                         "256 MiB last-level cache and a wave writes whole lines)")
     ap.add_argument("--adjoint-steps", type=int, default=None,
                     help="shorten the adjoint workload (profiling runs); default its 2000 steps")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-window", type=int, default=64,
+                    help="edge of the window of the headline workload the CPU oracle steps")
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--calib", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -102,7 +128,13 @@ def algorithmic_bytes(w, store):
     return 2 * q * sp + 2 * nh * sh
 
 
-def time_gpu(w, store, steps, warmup, rounding=None, write_policy="auto"):
+def nodes(w):
+    return w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
+
+
+def time_gpu(w, store, steps, warmup, reps, rounding=None, write_policy="auto"):
+    """Warm-up, then reps timed repetitions of steps steps each, HIP events on
+    the stream the library launches on (torch's current stream)."""
     import torch
     import paper_2407_01651_amd as pfl
     sim = pfl.Sim(dict(w, write_policy=write_policy), store=store, rounding=rounding)
@@ -110,21 +142,26 @@ def time_gpu(w, store, steps, warmup, rounding=None, write_policy="auto"):
     sim.step(warmup)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    rep_ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rep_ms.append(e0.elapsed_time(e1))
     r = sim.reduce()
-    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
-    mlups = n * steps / (ms * 1e-3) / 1e6
-    bpn = algorithmic_bytes(w, store)
-    gbs = n * bpn / (ms * 1e-3 / steps) / 1e9
+    state = 2 * (int(sim.sizes.pops_bytes) + int(sim.sizes.hist_bytes))
     sim.close()
-    return dict(ms=ms, ms_per_step=ms / steps, mlups=mlups, bytes_per_node=bpn,
-                achieved_gbs=gbs, nonfinite=r["nonfinite"], solid_fraction=r["solid_fraction"])
+    del sim
+    torch.cuda.empty_cache()
+    ms = statistics.median(rep_ms)
+    n = nodes(w)
+    bpn = algorithmic_bytes(w, store)
+    return dict(ms=ms, ms_per_step=ms / steps, mlups=n * steps / (ms * 1e-3) / 1e6, bytes_per_node=bpn,
+                achieved_gbs=n * bpn / (ms * 1e-3 / steps) / 1e9, rep_ms=[round(x, 4) for x in rep_ms],
+                nonfinite=r["nonfinite"], state_bytes=state, cache_resident=state <= LLC_BYTES)
 
 
 def time_adjoint(name="adjoint2d_512", store="f32", K=100, steps=None):
@@ -208,19 +245,26 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100, steps=None):
             "grad": [round(v, 8) for v in grad]}
 
 
-def time_cpu(w, steps):
+def time_cpu(w, n, steps):
+    """The CPU oracle (float64 PyTorch, as it stands) on an n-node window of
+    workload w around its first bubble (or its centre), steps steps."""
     import torch
+    import workloads
     from oracle import OracleParams, OracleSim
-    sim = OracleSim(OracleParams.from_workload(w))
+    d = w["dim"]
+    c = ([w["bubbles"][0][k] for k in "xyz"[:d]] if w["bubbles"]
+         else [w[k] / 2 for k in ("nx", "ny", "nz")[:d]])
+    ww = workloads.window(w, n, c)
+    sim = OracleSim(OracleParams.from_workload(ww))
     sim.init_fields()
     t = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t
-    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
-    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
-                kind="oracle",
-                sample=f"{w['name']} full grid {w['nx']}x{w['ny']}, {steps} steps from init, "
-                       f"float64 PyTorch CPU, {dt:.1f} s")
+    return dict(value=round(nodes(ww) * steps / dt / 1e6, 4), unit="MLUPS", cores=torch.get_num_threads(),
+                host_cpus=os.cpu_count(), kind="oracle",
+                sample=f"{ww['name']}: a {'x'.join([str(n)] * d)} window of {w['name']} (its parameters, "
+                       f"{len(ww['seeds'])} seeds and {len(ww['bubbles'])} bubbles inside), {steps} steps "
+                       f"from init, float64 PyTorch CPU, {dt:.1f} s")
 
 
 def main():
@@ -242,16 +286,19 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_run = time_gpu(w, a.store, a.steps, a.warmup, a.rounding, a.write_policy)
+    main_run = time_gpu(w, a.store, a.steps, a.warmup, a.reps, a.rounding, a.write_policy)
+    print(f"bench: {a.config} {a.store} {main_run['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     variants = {}
-    for st in [s for s in a.also.split(",") if s and s != a.store]:
-        variants[st] = time_gpu(w, st, a.steps, a.warmup, a.rounding, a.write_policy)
-    for item in [s for s in a.extra.split(",") if s]:
+    for item in [x for x in a.variants.split(",") if x]:
         cfg, st = item.split(":")
-        variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.rounding, a.write_policy)
+        if (cfg, st) == (a.config, a.store):
+            continue
+        variants[item] = time_gpu(workloads.get(cfg), st, a.steps, a.warmup, a.reps, a.rounding, a.write_policy)
+        print(f"bench: {item} {variants[item]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     adj = None if a.no_adjoint else time_adjoint(steps=a.adjoint_steps)
-    cpu = None if a.no_cpu else time_cpu(w, a.cpu_steps)
-    n = w["nx"] * w["ny"] * (w["nz"] if w["dim"] == 3 else 1)
+    cpu = None if a.no_cpu else time_cpu(w, a.cpu_window, a.cpu_steps)
+    n = nodes(w)
+    traffic, prof_ns = profile_figures(w["dim"], w["name"], a.store)
     out = {
         "metric": "MLUPS (all fields fused) FP64 vs FP32/FP16-store; adjoint/forward cost ratio",
         "value": round(main_run["mlups"], 2),
@@ -266,16 +313,20 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}[a.store],
         "data": "synthetic",
         "config": {"workload": w["name"], "grid": [w["nx"], w["ny"]] + ([w["nz"]] if w["dim"] == 3 else []),
-                   "fields": list(w["fields"]), "storage": a.store, "nodes": n, "write_policy": a.write_policy},
+                   "fields": list(w["fields"]), "storage": a.store, "nodes": n, "write_policy": a.write_policy,
+                   "state_bytes": main_run["state_bytes"], "cache_resident": main_run["cache_resident"]},
+        "timing": {"reps": a.reps, "statistic": "median", "rep_ms": main_run["rep_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_run["achieved_gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(a.store) if a.config == "alloy2d_1024" else None,
-                     "bytes_per_node": main_run["bytes_per_node"]},
+                     "traffic": traffic,
+                     "bytes_per_node": main_run["bytes_per_node"],
+                     "profile_avg_ns": prof_ns},
         "variants": {k: {"mlups": round(v["mlups"], 2), "ms_per_step": round(v["ms_per_step"], 6),
                          "achieved_gbs": round(v["achieved_gbs"], 1),
                          "frac": round(v["achieved_gbs"] / PEAK_HBM_GBS, 4),
-                         "bytes_per_node": v["bytes_per_node"]} for k, v in variants.items()},
+                         "bytes_per_node": v["bytes_per_node"], "state_bytes": v["state_bytes"],
+                         "cache_resident": v["cache_resident"]} for k, v in variants.items()},
         "adjoint": adj,
         "cpu_baseline": cpu,
     }

@@ -162,6 +162,8 @@ struct DevParams {
   const double* seeds;         // x, y, z, r, angle per seed
   const double* bubbles;       // x, y, z, r per bubble
   int fast;                    // byte offsets of every buffer fit in 32 bits
+  int plane32;                 // byte offsets within one plane fit in 32 bits
+  int zc;                      // 3D: z planes per workgroup chunk
   const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
   int nt;                      // step stores non-temporal (streamed past the last-level cache)

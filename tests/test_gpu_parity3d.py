@@ -3,9 +3,9 @@ through the C ABI.
 
 Bar: 1e-12 normwise relative error per field after N steps, on every macro
 field (velocity with its z component) and on the full node-form state.
-Grids span several 16 x 4 x 2 FP64 tiles with ragged tails on every axis, and
-one grid is large enough for interior tiles to take the 32-bit-offset fast
-path; walls on one and on two axes, periodic boxes, and every 3D field
+Grids span several 32 x 4 FP64 column tiles with ragged tails on every axis
+and whole z chunks, and one grid is large enough for interior tiles to take
+the fast addressing path; walls on one and on two axes, periodic boxes, and every 3D field
 combination the library builds are covered.
 """
 import math

@@ -307,6 +307,28 @@ def small(dim=2, nx=12, ny=10, nz=1, fields=FIELDS_ALL, seed=0, periodic=None,
     return c
 
 
+def window(w, n, centre):
+    """A cube (square in 2D) of n nodes per axis cut from workload w around
+    the point centre: the same parameters and boundary types, the seeds and
+    bubbles whose centres fall inside it, moved into its coordinates.  Used as
+    a bounded sample of a workload too large for the CPU oracle."""
+    c = copy.deepcopy(w)
+    d = w["dim"]
+    o = [int(round(centre[a] - n / 2)) for a in range(d)] + [0] * (3 - d)
+    keys = ("x", "y", "z")
+
+    def inside(obj):
+        return all(0 <= obj[keys[a]] - o[a] < n for a in range(d))
+
+    def moved(obj):
+        return dict(obj, **{keys[a]: obj[keys[a]] - o[a] for a in range(d)})
+
+    c.update(name=f"{w['name']}_window{n}", nx=n, ny=n, nz=n if d == 3 else 1,
+             seeds=[moved(s) for s in w["seeds"] if inside(s)],
+             bubbles=[moved(b) for b in w["bubbles"] if inside(b)])
+    return c
+
+
 CONFIGS = {
     "coupled2d_128": coupled2d_128,
     "corner_thermal2d_256": corner_thermal2d_256,
