@@ -25,6 +25,8 @@ Paper:
     functions (Sec. 3, boundary paragraph);
   * far-field Dirichlet values psi = psi_l, C = 1, theta = -Omega on chosen
     sides (Sec. 3.4 thermosolutal validation, Sec. 4 set-up);
+  * the AAC form for Le = O(1), a_n = a_s^2 F(U) (Appendix B, first
+    paragraph), beside the rewritten form;
   * the heat LB with variable properties (Appendix B heat model, Sec. 2.2
     property rule): H = c_p theta - c_p^s h(psi), H = sum g / rho,
     g_eq,0 = rho H + (w_0 - 1) theta, g_eq,i = w_i theta + w_i c_i.rho H v/cs2,
@@ -181,6 +183,10 @@ class OracleParams:
     th_rho_g: float = 1.0
     th_cp_g: float = 1.0
     th_k_g: float = 1.0
+    # form of the AAC scheme (Appendix B): "rewritten" (a_n = a_s^2, the
+    # kinetic factor F(U) in the diffusivity and the source) or "le1" (the
+    # form for Le = O(1): a_n = a_s^2 F(U))
+    aac_form: str = "rewritten"
 
     @classmethod
     def from_workload(cls, w):
@@ -198,7 +204,7 @@ class OracleParams:
                    symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]),
                    farfield=tuple(w.get("farfield", (False, False, False))[:dim]),
                    th_rho_g=w.get("th_rho_g", 1.0), th_cp_g=w.get("th_cp_g", 1.0),
-                   th_k_g=w.get("th_k_g", 1.0))
+                   th_k_g=w.get("th_k_g", 1.0), aac_form=w.get("aac_form", "rewritten"))
 
     # --- derived constants -------------------------------------------------
     @property
@@ -613,6 +619,21 @@ class OracleSim:
         collision of Sec. 3).  Pinned by the shear-wave decay rate nu k^2."""
         return 1.0 / (nu / self.L_ns.cs2 + 0.5)
 
+    def aac_source(self, F, gF, a2, gpsi, N, Qpsi):
+        """Source S_psi and diffusivity D_psi of the AAC LB (Appendix B).
+        Rewritten form: S_psi = (W0^2/(tau0 F^2)) grad F.(a_s^2 grad psi + N)
+        + Q_psi/(tau0 F), D_psi = W0^2 a_s^2/(tau0 F), with a_n = a_s^2.  Form
+        for Le = O(1) (Appendix B, first paragraph): F(U) multiplies the time
+        derivative through a_n = a_s^2 F(U), so D_psi = W0^2 a_s^2/tau0,
+        S_psi = Q_psi/tau0 and no grad F term.  Pinned by the shrinkage rate
+        2 W0^2/(tau0 F) of a circle at F != 1 in both forms and by the two
+        forms' agreement on a front moving through a U gradient."""
+        P = self.p
+        if P.aac_form == "le1":
+            return Qpsi / P.tau0, P.d_psi * a2
+        return (P.d_psi / (F * F) * (gF * (a2 * gpsi + N)).sum(0) + Qpsi / (P.tau0 * F),
+                P.d_psi * a2 / F)
+
     def ns_forcing(self, L, v, F, gradrho):
         """Forcing distribution of the flow LB, w_i [(c_i.v)(c_i.grad rho)/cs2
         + c_i.F/cs2 + (vF + Fv):(c_i c_i - cs2 I)/(2 cs4)] (Sec. 3 unified LB
@@ -737,10 +758,9 @@ class OracleSim:
         pprime = 30.0 / (PSI_S - PSI_L) ** 5 * (PSI_S - psi) ** 2 * (psi - PSI_L) ** 2
         Qpsi = -(f2p + f3psi + P.lam * pprime * (theta + P.Mcinf * U))
         a2 = a_s * a_s
-        S_psi = P.d_psi / (F * F) * (gF * (a2 * gpsi + N)).sum(0) + Qpsi / (P.tau0 * F)
+        S_psi, D_psi = self.aac_source(F, gF, a2, gpsi, N, Qpsi)
         if self.S_override is not None:
             S_psi = one * self.S_override
-        D_psi = P.d_psi * a2 / F
         s_psi = 1.0 / (D_psi / self.L_sc.cs2 + 0.5)
         # S8 chemical potential, surface tension (potential form), CAC flux
         f1p = 2 * BETA_PHI * (PHI_L - phi) * (phi - PHI_G) * (PHI_L + PHI_G - 2 * phi)
@@ -835,6 +855,8 @@ class OracleSim:
             rates = {r: q["s_psi"] for r in L.flux_rows}
             fstar = f - self.mrt(L, f, feq, rates) + Fi + dFi + G - 0.5 * self.lam_apply(L, G, rates)
             an = q["a_s"] * q["a_s"]
+            if P.aac_form == "le1":
+                an = an * q["F"]
             if self.an_override is not None:
                 an = torch.ones_like(an) * self.an_override
             fs_str = self.stream(fstar, L, dval=PSI_L)
