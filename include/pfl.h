@@ -49,7 +49,10 @@
 extern "C" {
 #endif
 
-#define PFL_ABI_VERSION 2
+#define PFL_ABI_VERSION 3
+
+/* pfl_params.aac_form */
+enum { PFL_AAC_REWRITTEN = 0, PFL_AAC_LE1 = 1 };
 
 enum {
   PFL_OK = 0,
@@ -141,6 +144,17 @@ typedef struct {
                                returns PFL_E_NONFINITE if a check found NaN or Inf; 0: no
                                checks.  With checks, pfl_step synchronises its stream once
                                at the end of the call. */
+  int aac_form;             /* LB form of the anisotropic Allen-Cahn equation (Appendix B):
+                               PFL_AAC_REWRITTEN (0, default): time stretch a_n = a_s^2, the
+                               kinetic factor F(U) in the diffusivity W0^2 a_s^2/(tau0 F) and
+                               the source, with its grad F term; PFL_AAC_LE1: the form for
+                               Le = O(1), a_n = a_s^2 F(U), diffusivity W0^2 a_s^2/tau0, source
+                               Q_psi/tau0.  The Le = O(1) form is stable only where the AAC
+                               relaxation rate s_psi <= 2 a_s^2 F(U) (a_n < 1 amplifies a
+                               relaxed mode by 1 - s_psi/a_n); the library cannot bound F(U)
+                               beforehand: use reduce_every to catch a divergence.  No adjoint
+                               for PFL_AAC_LE1 (the adjoint entry points return
+                               PFL_E_UNSUPPORTED). */
 } pfl_params;
 
 /* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */

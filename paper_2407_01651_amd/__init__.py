@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
                       " (or __graft_entry__.build())")
 _lib = ct.CDLL(LIB_PATH)
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
 SWEEP_CONTINUE, SWEEP_OPEN = 1, 2
 NS, PHI, PSI, CONC, THETA = 1, 2, 4, 8, 16
@@ -29,6 +29,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 STORES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 ROUNDINGS = {"stochastic": 0, "nearest": 1}
 WRITE_POLICIES = {"auto": 0, "cached": 1, "stream": 2}
+AAC_FORMS = {"rewritten": 0, "le1": 1}
 FIELD_BITS = {"ns": NS, "phi": PHI, "psi": PSI, "c": CONC, "theta": THETA}
 MACROS = ("phi", "psi", "C", "theta", "U", "p", "vx", "vy", "vz")
 OUT_F64, OUT_F32 = 0, 1
@@ -49,7 +50,7 @@ class Params(ct.Structure):
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
                                           "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")] + \
-               [("write_policy", ct.c_int), ("reduce_every", ct.c_int)]
+               [("write_policy", ct.c_int), ("reduce_every", ct.c_int), ("aac_form", ct.c_int)]
 
 
 class Seed(ct.Structure):
@@ -156,6 +157,7 @@ def make_params(w, store=None, rounding=None, write_policy=None, reduce_every=No
         setattr(p, n, float(w.get(n, 1.0)))
     p.write_policy = WRITE_POLICIES[write_policy or w.get("write_policy", "auto")]
     p.reduce_every = int(w.get("reduce_every", 0) if reduce_every is None else reduce_every)
+    p.aac_form = AAC_FORMS[w.get("aac_form", "rewritten")]
     return p
 
 

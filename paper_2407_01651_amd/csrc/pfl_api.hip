@@ -84,6 +84,7 @@ int validate(const pfl_params* p) {
     return fail(PFL_E_INVALID_ARG, "non-finite parameter");
   if (!(p->eps4 >= 0 && p->eps4 < 1.0 / 3)) return fail(PFL_E_INVALID_ARG, "eps4 must lie in [0, 1/3)");
   if (p->reduce_every < 0) return fail(PFL_E_INVALID_ARG, "reduce_every must be >= 0");
+  if (p->aac_form != PFL_AAC_REWRITTEN && p->aac_form != PFL_AAC_LE1) return fail(PFL_E_INVALID_ARG, "bad AAC form");
   return PFL_OK;
 }
 
@@ -214,6 +215,7 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
   d.q_ns = L.q_ns; d.q_phi = L.q_phi; d.q_sc = L.q_sc;
   d.h_psi = L.h_psi; d.h_S = L.h_S; d.h_phiv = L.h_phiv; d.h_B = L.h_B; d.h_Hv = L.h_Hv;
   d.first = 1;
+  d.le1 = p->aac_form == PFL_AAC_LE1;
   const bool th = p->fields & PFL_THETA;
   const double cs2_sc = p->dim == 2 ? 1.0 / 3 : 0.25;
   const double cs2_phi = p->dim == 2 ? 1.0 / 3 : 0.25;
@@ -617,6 +619,7 @@ static int adj_check(pfl_ctx* c) {
   if (!c->b.adj) return fail(PFL_E_STATE, "no adjoint scratch buffer (pfl_buffers.adj)");
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
+  if (c->p.aac_form != PFL_AAC_REWRITTEN) return fail(PFL_E_UNSUPPORTED, "no adjoint for the Le = O(1) AAC form");
   return PFL_OK;
 }
 

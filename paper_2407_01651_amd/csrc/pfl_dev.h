@@ -164,6 +164,7 @@ struct DevParams {
   int fast;                    // byte offsets of every buffer fit in 32 bits
   int plane32;                 // byte offsets within one plane fit in 32 bits
   int zc;                      // 3D: z planes per workgroup chunk
+  int le1;                     // AAC form for Le = O(1): a_n = a_s^2 F(U), no F in D_psi and S_psi
   const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
   int nt;                      // step stores non-temporal (streamed past the last-level cache)

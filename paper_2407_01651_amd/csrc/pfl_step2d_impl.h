@@ -330,7 +330,7 @@ void step2d_kernel(const DevParams P,
     Nx = cth * Nrx - sth * Nry;
     Ny = sth * Nrx + cth * Nry;
   }
-  const CT an = a_s * a_s;
+  const CT as2 = a_s * a_s;
 
   // kinetics F(U)
   const CT lin = CT(1) + k1 * U;
@@ -346,10 +346,19 @@ void step2d_kernel(const DevParams P,
   const CT s1m = (CT(1) - psi) * ps1;
   const CT pprime = CT(30.0 / 32.0) * s1m * s1m;
   const CT Qpsi = -(f2p + f3psi + K.lam * pprime * (theta + K.Mcinf * U));
-  const CT invF = rcp(F);
-  const CT S_psi = K.d_psi * invF * invF * (gFx * (an * gpx + Nx) + gFy * (an * gpy + Ny)) +
-                   Qpsi * invF * K.inv_tau0;
-  const CT D_psi = K.d_psi * an * invF;
+  // rewritten form: a_n = a_s^2, F(U) in D_psi and S_psi with the grad F
+  // term; form for Le = O(1): a_n = a_s^2 F(U) (Appendix B)
+  CT S_psi, D_psi;
+  if (P.le1) {
+    S_psi = Qpsi * K.inv_tau0;
+    D_psi = K.d_psi * as2;
+  } else {
+    const CT invF = rcp(F);
+    S_psi = K.d_psi * invF * invF * (gFx * (as2 * gpx + Nx) + gFy * (as2 * gpy + Ny)) +
+            Qpsi * invF * K.inv_tau0;
+    D_psi = K.d_psi * as2 * invF;
+  }
+  const CT an = P.le1 ? as2 * F : as2;
   const CT rate_psi = rcp(D_psi * CT(3) + CT(0.5));
 
   // velocity, forces, pressure (pressure recovered in FP64 in every mode)
@@ -536,7 +545,8 @@ void step2d_kernel(const DevParams P,
       const CT d = fps[i] - CT(LS::w[i]) * dpsi;
       jx_ += CT(LS::c[i][0]) * d; jy_ += CT(LS::c[i][1]) * d;
     }
-    const CT gNx = -Nx * inv_an, gNy = -Ny * inv_an;    // G_i = -w_i c_i.N / a_s^2
+    const CT inv_as2 = P.le1 ? rcp(as2) : inv_an;
+    const CT gNx = -Nx * inv_as2, gNy = -Ny * inv_as2;  // G_i = -w_i c_i.N / a_s^2
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const CT cx = CT(LS::c[i][0]), cy = CT(LS::c[i][1]);

@@ -542,7 +542,7 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
             Nv[1] = sth * Nr[0] + cth * Nr[1];
             Nv[2] = Nr[2];
           }
-          const CT an = a_s * a_s;
+          const CT as2 = a_s * a_s;
 
           const CT lin = CT(1) + k1 * U;
           const CT F = K.inv_Le + K.Mcinf * (lin > CT(0) ? lin : CT(0));
@@ -555,12 +555,21 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           const CT s1m = (CT(1) - psi) * ps1;
           const CT pprime = CT(30.0 / 32.0) * s1m * s1m;
           const CT Qpsi = -(f2p + f3psi + K.lam * pprime * (theta + K.Mcinf * U));
-          const CT invF = rcp(F);
-          CT gdot = CT(0);
+          // rewritten form: a_n = a_s^2, F(U) in D_psi and S_psi with the
+          // grad F term; form for Le = O(1): a_n = a_s^2 F(U) (Appendix B)
+          CT S_psi, D_psi;
+          if (P.le1) {
+            S_psi = Qpsi * K.inv_tau0;
+            D_psi = K.d_psi * as2;
+          } else {
+            const CT invF = rcp(F);
+            CT gdot = CT(0);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) gdot += gFs * gU[a] * (an * gp[a] + Nv[a]);
-          const CT S_psi = K.d_psi * invF * invF * gdot + Qpsi * invF * K.inv_tau0;
-          const CT D_psi = K.d_psi * an * invF;
+            for (int a = 0; a < 3; ++a) gdot += gFs * gU[a] * (as2 * gp[a] + Nv[a]);
+            S_psi = K.d_psi * invF * invF * gdot + Qpsi * invF * K.inv_tau0;
+            D_psi = K.d_psi * as2 * invF;
+          }
+          const CT an = P.le1 ? as2 * F : as2;
           const CT rate_psi = rcp(D_psi * CT(1.0 / LS::cs2) + CT(0.5));
 
           // velocity, forces, pressure (pressure recovered in FP64 in every mode)
@@ -738,7 +747,8 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
               if (LS::c[i][1]) jf[1] += CT(LS::c[i][1]) * d;
               if (LS::c[i][2]) jf[2] += CT(LS::c[i][2]) * d;
             }
-            const CT gN[3] = {-Nv[0] * inv_an, -Nv[1] * inv_an, -Nv[2] * inv_an};
+            const CT inv_as2 = P.le1 ? rcp(as2) : inv_an;
+            const CT gN[3] = {-Nv[0] * inv_as2, -Nv[1] * inv_as2, -Nv[2] * inv_as2};
             const raw* own_psi = fin_psi + idx;
             const int n3[3] = {P.nx, P.ny, P.nz};
             const int xyz[3] = {x, y, z};

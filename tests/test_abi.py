@@ -197,3 +197,16 @@ def test_host_argument_checks_of_new_entry_points():
     assert lib.pfl_adjoint_seed(None, None, 1, None) == -1
     assert lib.pfl_last_check(None, None) == -1
     assert lib.pfl_init_from_macros(None, None, 0, None, 0) == -1
+
+
+def test_aac_form_parameter():
+    import paper_2407_01651_amd as pfl
+    w = workloads.get("coupled2d_128")
+    s = pfl.Sizes()
+    assert pfl.make_params(w).aac_form == 0
+    p = pfl.make_params(dict(w, aac_form="le1"))
+    assert p.aac_form == 1
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    p.aac_form = 2
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    assert "AAC form" in pfl._lib.pfl_last_error().decode()

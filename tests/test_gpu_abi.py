@@ -141,3 +141,18 @@ def test_adjoint_seed(store):
     ref[19:24] = gpsi.to(lam.dtype)
     assert torch.equal(lam_c, ref)
     g.close()
+
+
+def test_no_adjoint_for_the_le_form():
+    import paper_2407_01651_amd as pfl
+    w = dict(workloads.small(nx=20, ny=16, seed=46), aac_form="le1", Le=1.0, tau0=50.0)
+    g = _sim(w, adjoint=True)
+    g.init_fields()
+    g.step(2)
+    lam = g.adjoint_seed(phi=torch.ones(16, 20, dtype=torch.float64, device="cuda"))
+    out = torch.empty_like(lam)
+    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
+    with pytest.raises(pfl.PflError) as e:
+        g.step_backward(lam, out, dp)
+    assert e.value.code == pfl.E_UNSUPPORTED and "Le = O(1)" in str(e.value)
+    g.close()

@@ -51,6 +51,8 @@ CASES = {
     # perturbation decays
     "varheat_40x34": (lambda: dict(workloads.small(nx=40, ny=34, seed=13), th_rho_g=0.7, th_cp_g=0.9,
                                    th_k_g=0.5), 300),
+    # the AAC form for Le = O(1) (Appendix B)
+    "le1_42x34": (lambda: dict(workloads.small(nx=42, ny=34, seed=9), aac_form="le1", Le=1.0, tau0=50.0), 300),
 }
 
 _oracle_cache = {}

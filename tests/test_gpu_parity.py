@@ -77,6 +77,13 @@ CASES = [
     # heat properties varying between gas and liquid (Appendix B heat model, Sec. 2.2 rule)
     ("all_varheat_30x24", dict(nx=30, ny=24, seed=28, g=2e-4, rho_g=0.01,
                                th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 30),
+    # the AAC form for Le = O(1) (Appendix B): a_n = a_s^2 F(U); Le = 1 and
+    # tau0 = 50 keep F >= 1 above its stability bound s_psi / (2 a_s^2)
+    ("all_le1_30x22", dict(nx=30, ny=22, seed=30, aac_form="le1", Le=1.0, tau0=50.0), 30),
+    ("alloy_theta_le1_far_corner_34x30", dict(nx=34, ny=30, seed=31, fields=("psi", "c", "theta"),
+                                              periodic=(False, False, True), symmetric=("lo", "lo", False),
+                                              farfield=("hi", "hi", False), aac_form="le1", Le=1.0, tau0=50.0,
+                                              seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=6.0, angle=0.0)]), 40),
     ("noflow_varheat_far_28x26", dict(nx=28, ny=26, seed=29, fields=("phi", "psi", "c", "theta"),
                                       periodic=(False, False, True), symmetric=(True, False, False),
                                       farfield=(False, "hi", False), th_rho_g=0.7, th_cp_g=0.6, th_k_g=2.0), 40),

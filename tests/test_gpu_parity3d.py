@@ -55,6 +55,10 @@ CASES = [
                                     seeds=[dict(x=7.0, y=9.5, z=4.0, r=3.5, angle=0.3)]), 25),
     # heat properties varying between gas and liquid
     ("all_varheat_16x14x10", dict(nx=16, ny=14, nz=10, seed=37, th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 20),
+    # the AAC form for Le = O(1) (Appendix B), F >= 1 above its stability bound
+    ("all_le1_18x12x8", dict(nx=18, ny=12, nz=8, seed=38, aac_form="le1", Le=1.0, tau0=50.0), 20),
+    ("alloy_theta_le1_16x12x9", dict(nx=16, ny=12, nz=9, seed=39, fields=("psi", "c", "theta"),
+                                     aac_form="le1", Le=1.0, tau0=50.0), 20),
 ]
 
 
