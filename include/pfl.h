@@ -118,13 +118,25 @@ typedef struct {
                                coordinate -1/2) and a wall on the high side, 4 the reverse,
                                5 a wall on the low side and a far-field side on the high side,
                                6 a symmetry plane on the low side and a far-field side on the
-                               high side.
+                               high side, 7 velocity sides on both ends, 8 a wall on the low
+                               side and a velocity side on the high side, 9 the reverse,
+                               10 a velocity side on the low side and a pressure side on the
+                               high side, 11 the reverse.
                                Symmetry planes lie half-way; a population crossing one comes
                                back as its mirror image, stencil ghosts are mirror images
                                (Sec. 3).  A far-field side (half-way) holds psi = psi_l,
                                C = 1 and theta = theta0 (Sec. 3.4, Sec. 4): populations of
                                those sets crossing it come back by anti-bounce-back,
-                               -f*_i + 2 w_i value; NS and phi see a wall there. */
+                               -f*_i + 2 w_i value; NS and phi see a wall there.
+                               A velocity side (2D, flow without the gas phase) prescribes
+                               the velocity v_in by non-equilibrium extrapolation (Sec. 3,
+                               boundary paragraph): the flow population entering node x
+                               from the ghost node x - c_i is f*_i(x) + f^eq_i(p, rho, v_in)
+                               - f^eq_i(p, rho, v) with p, rho, v of x (the ghost lies one
+                               node outside).  A pressure side holds p = 0 by the same
+                               extrapolation: f*_i(x) + f^eq_i(0, rho, v) - f^eq_i(p, rho, v).
+                               psi, C and theta take their far-field values on both kinds of
+                               side, as at a far-field side. */
   uint32_t fields;          /* PFL_NS | PFL_PHI | PFL_PSI | PFL_C | PFL_THETA */
   int phi_q;                /* lattice of phi: 5 or 9 in 2D, 7 in 3D */
   int store;                /* PFL_F64, PFL_F32, PFL_F16, PFL_BF16 */
@@ -155,6 +167,7 @@ typedef struct {
                                beforehand: use reduce_every to catch a divergence.  No adjoint
                                for PFL_AAC_LE1 (the adjoint entry points return
                                PFL_E_UNSUPPORTED). */
+  double v_in[3];           /* velocity of the velocity sides (wall codes 7-9), lattice units */
 } pfl_params;
 
 /* A solid seed (centre, radius, crystal rotation about z) and a gas bubble. */

@@ -179,6 +179,15 @@ class OracleParams:
     # non-periodic axes: far-field Dirichlet sides, True (both), "lo", "hi" or
     # False; a side is a symmetry plane, a far-field side or a wall
     farfield: tuple = (False, False, False)
+    # velocity sides per axis (True: both ends, "lo", "hi"): the flow takes the Dirichlet
+    # velocity v_in there by non-equilibrium extrapolation; psi, C and theta
+    # take their far-field values as at a far-field side
+    velocity: tuple = (False, False, False)
+    v_in: tuple = (0.0, 0.0, 0.0)
+    # pressure sides per axis ("lo", "hi"): the flow leaves at the pressure
+    # p = 0 with its own velocity, by the same extrapolation; psi, C and
+    # theta take their far-field values there
+    outflow: tuple = (False, False, False)
     # gas-to-liquid ratios of rho, c_p and k_T in the heat equation
     th_rho_g: float = 1.0
     th_cp_g: float = 1.0
@@ -203,6 +212,9 @@ class OracleParams:
                    bubbles=[dict(b) for b in w["bubbles"]],
                    symmetric=tuple(w.get("symmetric", (False, False, False))[:dim]),
                    farfield=tuple(w.get("farfield", (False, False, False))[:dim]),
+                   velocity=tuple(w.get("velocity", (False, False, False))[:dim]),
+                   v_in=tuple(float(u) for u in w.get("v_in", (0.0, 0.0, 0.0))[:dim]),
+                   outflow=tuple(w.get("outflow", (False, False, False))[:dim]),
                    th_rho_g=w.get("th_rho_g", 1.0), th_cp_g=w.get("th_cp_g", 1.0),
                    th_k_g=w.get("th_k_g", 1.0), aac_form=w.get("aac_form", "rewritten"))
 
@@ -270,6 +282,13 @@ class OracleSim:
             for lo in (True, False):
                 if not P.periodic[a] and self.sym(a, lo) and self.far(a, lo):
                     raise ValueError("a side is a symmetry plane or a far-field side, not both")
+        for a in range(P.dim):
+            for lo in (True, False):
+                if self.vel(a, lo) and self.pres(a, lo):
+                    raise ValueError("a side is a velocity side or a pressure side, not both")
+        if any(self.vel(a, lo) or self.pres(a, lo) for a in range(P.dim) for lo in (True, False)):
+            if "ns" not in P.fields or "phi" in P.fields:
+                raise ValueError("velocity and pressure sides need the flow and no gas phase")
         self.grid = tuple(reversed(P.shape))          # tensor shape: [z][y][x]
         self.n = 0
         self.first = True
@@ -314,10 +333,35 @@ class OracleSim:
             return not lo
         return bool(v)
 
-    def far(self, a, lo):
-        """Whether the low (lo) or high boundary of axis a is a far-field side."""
+    def vel(self, a, lo):
+        """Whether the low (lo) or high boundary of axis a is a velocity side."""
         if self.p.periodic[a]:
             return False
+        v = self.p.velocity[a]
+        if v == "lo":
+            return lo
+        if v == "hi":
+            return not lo
+        return bool(v)
+
+    def pres(self, a, lo):
+        """Whether the low (lo) or high boundary of axis a is a pressure side."""
+        if self.p.periodic[a]:
+            return False
+        v = self.p.outflow[a]
+        if v == "lo":
+            return lo
+        if v == "hi":
+            return not lo
+        return bool(v)
+
+    def far(self, a, lo):
+        """Whether the low (lo) or high boundary of axis a holds the far-field
+        values of psi, C and theta (a far-field, velocity or pressure side)."""
+        if self.p.periodic[a]:
+            return False
+        if self.vel(a, lo) or self.pres(a, lo):
+            return True
         v = self.p.farfield[a]
         if v == "lo":
             return lo
@@ -411,16 +455,61 @@ class OracleSim:
                 return j
         raise ValueError("velocity set not closed under reflection")
 
-    def stream(self, fs, L, dval=None):
+    def ns_equilibrium(self, L, p, rho, v):
+        """Equilibrium of the pressure-based flow LB (Sec. 3): w_i p/cs2 +
+        rho s_i(v) for i > 0 and (w_0 - 1) p/cs2 + rho s_0(v), with
+        s_i(v) = w_i [c_i.v/cs2 + (c_i.v)^2/(2 cs4) - v.v/(2 cs2)]."""
+        cv = self.cdot(L, v)
+        vv = (v * v).sum(0)
+        w = self.wv(L, vv)
+        feq = w * p / L.cs2 + rho * w * (cv / L.cs2 + cv * cv / (2 * L.cs2 ** 2) - vv / (2 * L.cs2))
+        feq[0] = feq[0] - p / L.cs2
+        return feq
+
+    def nee(self, L, fs, p, rho, v):
+        """Non-equilibrium extrapolation at a velocity side (Sec. 3, boundary
+        paragraph): the population entering node y along c_i from the ghost
+        node y - c_i is the ghost's equilibrium at the prescribed velocity
+        v_in, with the pressure and density of y, plus the non-equilibrium
+        part of the post-collision population f*_i(y):
+        f*_i(y) + f^eq_i(p, rho, v_in) - f^eq_i(p, rho, v) (every direction,
+        the caller picks those crossing a velocity side).  Pinned by the exact
+        linear Couette profile between a wall and a velocity side, by a
+        uniform oblique flow that stays exact, and by the flux and Poiseuille
+        profile of a channel fed through velocity sides."""
+        vb = torch.stack([torch.full(self.grid, float(u), dtype=DT) for u in self.p.v_in])
+        return fs + self.ns_equilibrium(L, p, rho, vb) - self.ns_equilibrium(L, p, rho, v)
+
+    def nee_outflow(self, L, fs, p, rho, v):
+        """The same extrapolation at a pressure side: the ghost's equilibrium
+        at the pressure p = 0 with the density and velocity of y,
+        f*_i(y) + f^eq_i(0, rho, v) - f^eq_i(p, rho, v).  Pinned by a uniform
+        flow whose pressure offset relaxes to the side's pressure and by the
+        flux of a channel fed by a velocity side and drained by a pressure
+        side."""
+        return fs + self.ns_equilibrium(L, torch.zeros_like(p), rho, v) - self.ns_equilibrium(L, p, rho, v)
+
+    def stream(self, fs, L, dval=None, flow=None):
         """out_i(y) = fs_i(y - c_i).  Across a wall, out_i(y) = fs_opp(i)(y);
         across a symmetry plane on axis a (and no wall), the source is the
         mirror node and the population the one with c_a reversed.  Across a
         far-field side: -fs_opp(i)(y) + 2 w_i dval for a scalar set with
-        far-field value dval, a wall for the others (dval None)."""
+        far-field value dval, a wall for the others (dval None).  Across a
+        velocity side (taking precedence over the other sides crossed):
+        nee(...)_i(y) for the flow set (flow = (p, rho, v)), the far-field
+        rule for a scalar set; across a pressure side (precedence after a
+        velocity side) nee_outflow(...)_i(y), the far-field rule for scalars."""
         out = torch.empty_like(fs)
+        ent = out_ent = None
+        if flow is not None and any(self.vel(a, lo) for a in range(self.d) for lo in (True, False)):
+            ent = self.nee(L, fs, *flow)
+        if flow is not None and any(self.pres(a, lo) for a in range(self.d) for lo in (True, False)):
+            out_ent = self.nee_outflow(L, fs, *flow)
         for i in range(L.Q):
             wall = torch.zeros(self.grid, dtype=torch.bool)
             farm = torch.zeros(self.grid, dtype=torch.bool)
+            velm = torch.zeros(self.grid, dtype=torch.bool)
+            presm = torch.zeros(self.grid, dtype=torch.bool)
             crossed = []                          # symmetry planes crossed: (axis, mask)
             for a in range(self.d):
                 ca = int(L.c[i, a])
@@ -439,6 +528,10 @@ class OracleSim:
                     wall = wall | m
                     if dval is not None and self.far(a, ca > 0):
                         farm = farm | m
+                    if self.vel(a, ca > 0):
+                        velm = velm | m
+                    if self.pres(a, ca > 0):
+                        presm = presm | m
             # every combination of crossed symmetry planes: reflect c on those
             # axes, take the source with the other components streamed
             res = torch.zeros(self.grid, dtype=DT)
@@ -464,6 +557,10 @@ class OracleSim:
                 # the scalar sets' velocities are axis-aligned: a population
                 # crosses one side at most
                 out[i] = torch.where(farm, -fs[L.opp[i]] + 2.0 * L.w[i] * dval, out[i])
+            if out_ent is not None:
+                out[i] = torch.where(presm, out_ent[i], out[i])
+            if ent is not None:
+                out[i] = torch.where(velm, ent[i], out[i])
         return out
 
     # ------------------------------------------------------------- collision
@@ -817,17 +914,12 @@ class OracleSim:
         if "ns" in P.fields:
             L = self.L_ns
             f = st["f_ns"]
-            cv = self.cdot(L, v)
-            vv = (v * v).sum(0)
-            w = self.wv(L, vv)
-            s_i = w * (cv / L.cs2 + cv * cv / (2 * L.cs2 ** 2) - vv / (2 * L.cs2))
-            feq = w * q["p"] / L.cs2 + q["rho"] * s_i
-            feq[0] = feq[0] - q["p"] / L.cs2
+            feq = self.ns_equilibrium(L, q["p"], q["rho"], v)
             Ft = self.ns_forcing(L, v, q["Ftot"], q["gradrho"])
             s_nu = self.ns_rate(q["nu"])
             rates = {r: s_nu for r in L.stress_rows}
             fstar = f - self.mrt(L, f, feq, rates) + Ft - 0.5 * self.lam_apply(L, Ft, rates)
-            new["f_ns"] = self.stream(fstar, L)
+            new["f_ns"] = self.stream(fstar, L, flow=(q["p"], q["rho"], v))
         # CAC
         phiv = q["phi"] * v
         if "phi" in P.fields:

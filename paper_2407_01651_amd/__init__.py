@@ -50,7 +50,7 @@ class Params(ct.Structure):
                [(n, ct.c_double) for n in ("W0", "tau0", "eps4", "k", "PeD", "Le", "Mcinf", "U0", "theta0",
                                           "rho_l", "rho_g", "nu_l", "nu_g", "sigma", "M_phi", "xi",
                                           "beta_inter", "g", "delta_n2", "th_rho_g", "th_cp_g", "th_k_g")] + \
-               [("write_policy", ct.c_int), ("reduce_every", ct.c_int), ("aac_form", ct.c_int)]
+               [("write_policy", ct.c_int), ("reduce_every", ct.c_int), ("aac_form", ct.c_int), ("v_in", ct.c_double * 3)]
 
 
 class Seed(ct.Structure):
@@ -136,7 +136,19 @@ def make_params(w, store=None, rounding=None, write_policy=None, reduce_every=No
         # "hi" (far-field high side, with a wall or a symmetry plane low) or False
         sym = w.get("symmetric", (False, False, False))
         far = w.get("farfield", (False, False, False))
-        if far[a]:
+        vel = w.get("velocity", (False, False, False))
+        out = w.get("outflow", (False, False, False))
+        if out[a]:
+            # a pressure side: the end opposite a velocity side
+            if sym[a] or far[a] or (vel[a], out[a]) not in (("lo", "hi"), ("hi", "lo")):
+                raise ValueError("a pressure side lies opposite a velocity side")
+            code = 10 if out[a] == "hi" else 11
+        elif vel[a]:
+            # velocity sides: True (both ends), "hi" or "lo" (a wall on the other side)
+            if sym[a] or far[a] or vel[a] not in (True, "hi", "lo"):
+                raise ValueError("velocity sides: both ends, or one end with a wall on the other")
+            code = {True: 7, "hi": 8, "lo": 9}[vel[a]]
+        elif far[a]:
             if far[a] != "hi" or sym[a] not in (False, "lo"):
                 raise ValueError("far-field sides: the high side, with a wall or a symmetry plane on the low side")
             code = 6 if sym[a] == "lo" else 5
@@ -158,6 +170,8 @@ def make_params(w, store=None, rounding=None, write_policy=None, reduce_every=No
     p.write_policy = WRITE_POLICIES[write_policy or w.get("write_policy", "auto")]
     p.reduce_every = int(w.get("reduce_every", 0) if reduce_every is None else reduce_every)
     p.aac_form = AAC_FORMS[w.get("aac_form", "rewritten")]
+    for a, u in enumerate(w.get("v_in", (0.0, 0.0, 0.0))):
+        p.v_in[a] = float(u)
     return p
 
 

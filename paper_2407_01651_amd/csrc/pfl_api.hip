@@ -50,7 +50,7 @@ int validate(const pfl_params* p) {
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31))
     return fail(PFL_E_INVALID_ARG, "grid larger than 2^31 nodes");
   for (int a = 0; a < 3; ++a)
-    if (p->wall[a] < 0 || p->wall[a] > 6) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 6");
+    if (p->wall[a] < 0 || p->wall[a] > 11) return fail(PFL_E_INVALID_ARG, "boundary flags must be 0 to 11");
   const uint32_t f = p->fields;
   if (f == 0 || (f & ~31u)) return fail(PFL_E_INVALID_ARG, "bad field mask");
   if (p->dim == 2 && p->phi_q != 5 && p->phi_q != 9) return fail(PFL_E_INVALID_ARG, "phi_q must be 5 or 9 in 2D");
@@ -85,6 +85,15 @@ int validate(const pfl_params* p) {
   if (!(p->eps4 >= 0 && p->eps4 < 1.0 / 3)) return fail(PFL_E_INVALID_ARG, "eps4 must lie in [0, 1/3)");
   if (p->reduce_every < 0) return fail(PFL_E_INVALID_ARG, "reduce_every must be >= 0");
   if (p->aac_form != PFL_AAC_REWRITTEN && p->aac_form != PFL_AAC_LE1) return fail(PFL_E_INVALID_ARG, "bad AAC form");
+  bool vel = false;
+  for (int a = 0; a < 3; ++a) vel = vel || (p->wall[a] >= 7 && p->wall[a] <= 11);
+  if (vel) {
+    if (p->dim != 2) return fail(PFL_E_UNSUPPORTED, "velocity and pressure sides are built for 2D");
+    if (!(f & PFL_NS) || (f & PFL_PHI))
+      return fail(PFL_E_UNSUPPORTED, "velocity and pressure sides need the flow and no gas phase");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->v_in[a])) return fail(PFL_E_INVALID_ARG, "non-finite v_in");
+  }
   return PFL_OK;
 }
 
@@ -209,7 +218,13 @@ int pfl_create(pfl_ctx** out, const pfl_params* p, const pfl_buffers* bufs, void
     if (p->wall[a] == 2 || p->wall[a] == 4) d.sym |= 1 << (3 + a);
     if (p->wall[a] == 6) d.sym |= 1 << a;
     if (p->wall[a] == 5 || p->wall[a] == 6) d.far |= 1 << (3 + a);
+    if (p->wall[a] == 7 || p->wall[a] == 9 || p->wall[a] == 10) d.vel |= 1 << a;
+    if (p->wall[a] == 7 || p->wall[a] == 8 || p->wall[a] == 11) d.vel |= 1 << (3 + a);
+    if (p->wall[a] == 10) d.pres |= 1 << (3 + a);
+    if (p->wall[a] == 11) d.pres |= 1 << a;
   }
+  d.far |= d.vel | d.pres;
+  for (int a = 0; a < 3; ++a) d.vin[a] = p->v_in[a];
   d.N = L.N;
   d.o_ns = L.o_ns; d.o_phi = L.o_phi; d.o_psi = L.o_psi; d.o_c = L.o_c; d.o_th = L.o_th;
   d.q_ns = L.q_ns; d.q_phi = L.q_phi; d.q_sc = L.q_sc;
@@ -620,6 +635,7 @@ static int adj_check(pfl_ctx* c) {
   if (c->p.dim != 2) return fail(PFL_E_UNSUPPORTED, "the adjoint is built for 2D");
   if (!adj2d_supported((int)c->p.fields)) return fail(PFL_E_UNSUPPORTED, "no adjoint for this field combination");
   if (c->p.aac_form != PFL_AAC_REWRITTEN) return fail(PFL_E_UNSUPPORTED, "no adjoint for the Le = O(1) AAC form");
+  if (c->d.vel || c->d.pres) return fail(PFL_E_UNSUPPORTED, "no adjoint with velocity or pressure sides");
   return PFL_OK;
 }
 

@@ -165,6 +165,9 @@ struct DevParams {
   int plane32;                 // byte offsets within one plane fit in 32 bits
   int zc;                      // 3D: z planes per workgroup chunk
   int le1;                     // AAC form for Le = O(1): a_n = a_s^2 F(U), no F in D_psi and S_psi
+  int vel;                     // velocity sides, bits as sym (also set in far: psi, C, theta see a far-field side)
+  double vin[3];               // velocity of the velocity sides
+  int pres;                    // pressure sides (p = 0), bits as sym (also set in far)
   const void* hist_src;        // history read from here (null: the written buffer)
   int sr;                      // stochastic rounding of 16-bit stores
   int nt;                      // step stores non-temporal (streamed past the last-level cache)

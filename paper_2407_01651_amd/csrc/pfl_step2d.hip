@@ -24,6 +24,7 @@ bool step2d_supported(int fields) {
     case F_PSI:
     case F_PHI:
     case F_NS | F_PSI | F_TH:
+    case F_NS | F_PSI | F_C | F_TH:
     case F_PSI | F_TH:
       return true;
     default:

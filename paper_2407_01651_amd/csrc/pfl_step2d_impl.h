@@ -439,6 +439,30 @@ void step2d_kernel(const DevParams P,
     const CT s_nu = rcp(nu * CT(3) + CT(0.5));
     const CT vv = vx * vx + vy * vy;
     const CT vF = vx * Fx + vy * Fy;
+    // Velocity and pressure sides (non-equilibrium extrapolation, Sec. 3
+    // boundary paragraph): the slot of population i leaving across one holds
+    // what the node pulls back along j = opp(i) on the next step, its own f*_j
+    // plus f^eq_j(p, rho, v_in) - f^eq_j(p, rho, v) (velocity side) or
+    // f^eq_j(0, rho, v) - f^eq_j(p, rho, v) = -w_j p / cs2 (pressure side);
+    // a velocity side takes precedence where both are crossed.
+    // nee_out: 0 none, 1 velocity side, 2 pressure side.
+    auto nee_out = [&](int i) -> int {
+      if constexpr (!SYM) return 0;
+      if (fast || !(P.vel | P.pres)) return 0;
+      const int dx = LN::c[i][0], dy = LN::c[i][1];
+      auto across = [&](int m) {
+        return (dx > 0 && x == P.nx - 1 && ((m >> 3) & 1)) || (dx < 0 && x == 0 && (m & 1)) ||
+               (dy > 0 && y == P.ny - 1 && ((m >> 4) & 1)) || (dy < 0 && y == 0 && ((m >> 1) & 1));
+      };
+      return across(P.vel) ? 1 : (across(P.pres) ? 2 : 0);
+    };
+    auto nee = [&](int j, int kind) -> CT {
+      if (kind == 2) return -CT(LN::w[j]) * p * CT(3);
+      const CT cx = CT(LN::c[j][0]), cy = CT(LN::c[j][1]);
+      const CT bx = CT(P.vin[0]), by = CT(P.vin[1]);
+      const CT cb = cx * bx + cy * by, cv = cx * vx + cy * vy;
+      return rho * CT(LN::w[j]) * ((cb - cv) * CT(3) + (cb * cb - cv * cv) * CT(4.5) - (bx * bx + by * by - vv) * CT(1.5));
+    };
     if constexpr (sizeof(CT) == 4) {
       // FP32 compute: the same collision in moment form.  On the 4th-order
       // isotropic lattice the traceless stress moments of f^eq and of F/2 are
@@ -458,18 +482,18 @@ void step2d_kernel(const DevParams P,
       const CT m2 = s2 - rho * vx * vy + CT(0.5) * (vx * Fy + vy * Fx) + CT(1.0 / 6) * (vx * gry + vy * grx);
       const CT q1 = CT(0.25) * r * m1, q2 = CT(0.25) * r * m2;
       const CT rho3 = CT(3) * rho;
-#pragma unroll
-      for (int i = 0; i < QN; ++i) {
+      auto post = [&](int i) -> CT {
         const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
         const CT w = CT(LN::w[i]);
-        CT fs;
-        if (i == 0) {
-          fs = w * A - CT(3) * p;
-        } else {
-          const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy, cg = cx * grx + cy * gry;
-          const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
-          fs = w * t + ((cx * cx - cy * cy) * q1 + (cx * cy) * q2);
-        }
+        if (i == 0) return w * A - CT(3) * p;
+        const CT cv = cx * vx + cy * vy, cF = cx * Fx + cy * Fy, cg = cx * grx + cy * gry;
+        const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
+        return w * t + ((cx * cx - cy * cy) * q1 + (cx * cy) * q2);
+      };
+#pragma unroll
+      for (int i = 0; i < QN; ++i) {
+        CT fs = post(i);
+        if (const int kind = nee_out(i)) fs = post(LN::opp[i]) + nee(LN::opp[i], kind);
         st(P.o_ns, i, fs);
       }
     } else {
@@ -491,10 +515,14 @@ void step2d_kernel(const DevParams P,
       m2 += (cx * cy) * fneq[i];
     }
     const CT r = CT(1) - s_nu;
+    auto post = [&](int i) -> CT {
+      const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
+      return fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
+    };
 #pragma unroll
     for (int i = 0; i < QN; ++i) {
-      const CT cx = CT(LN::c[i][0]), cy = CT(LN::c[i][1]);
-      const CT fs = fhalf[i] + r * ((cx * cx - cy * cy) * m1 * CT(0.25) + (cx * cy) * m2 * CT(0.25));
+      CT fs = post(i);
+      if (const int kind = nee_out(i)) fs = post(LN::opp[i]) + nee(LN::opp[i], kind);
       st(P.o_ns, i, fs);
     }
     }
@@ -676,6 +704,7 @@ static hipError_t dispatch_fields(const DevParams& P, int fields, const void* fi
     PFL_CASE(F_PSI)
     PFL_CASE(F_PHI)
     PFL_CASE(F_NS | F_PSI | F_TH)
+    PFL_CASE(F_NS | F_PSI | F_C | F_TH)
     PFL_CASE(F_PSI | F_TH)
     default:
       ok = false;

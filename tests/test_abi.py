@@ -114,7 +114,10 @@ def test_write_policy_values():
 def test_boundary_flags():
     """wall[a]: 0 periodic, 1 walls, 2 symmetry planes, 3 / 4 a symmetry plane
     on the low / high side only, 5 / 6 a far-field high side with a wall /
-    symmetry plane low; anything else is rejected."""
+    symmetry plane low, 7 velocity sides on both ends, 8 / 9 a velocity side
+    on the high / low side with a wall on the other, 10 / 11 a velocity side
+    on the low / high side with a pressure side on the other (2D flow without
+    the gas phase); anything else is rejected."""
     import paper_2407_01651_amd as pfl
     w = workloads.get("coupled2d_128")
     w["symmetric"] = (True, True, False)
@@ -132,9 +135,36 @@ def test_boundary_flags():
     p = pfl.make_params(w, "f64", "nearest")
     assert list(p.wall) == [6, 5, 0]
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
-    p.wall[0] = 7
+    p.wall[0] = 12
     assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
     assert "boundary" in pfl._lib.pfl_last_error().decode()
+    p.wall[0] = 7                    # velocity sides with the gas phase active
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == pfl.E_UNSUPPORTED
+    assert "gas phase" in pfl._lib.pfl_last_error().decode()
+    wv = workloads.small(nx=20, ny=30, fields=("ns", "psi", "theta"), periodic=(False, False, True))
+    wv.update(symmetric=(True, False, False), velocity=(False, True, False), v_in=(0.0, 0.01, 0.0))
+    p = pfl.make_params(wv, "f64", "nearest")
+    assert list(p.wall) == [2, 7, 0] and list(p.v_in) == [0.0, 0.01, 0.0]
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == 0
+    wv.update(symmetric=(False, False, False), velocity=(False, "hi", False))
+    assert list(pfl.make_params(wv).wall) == [1, 8, 0]
+    wv["velocity"] = (False, "lo", False)
+    assert list(pfl.make_params(wv).wall) == [1, 9, 0]
+    wv["outflow"] = (False, "hi", False)
+    assert list(pfl.make_params(wv).wall) == [1, 10, 0]
+    wv.update(velocity=(False, "hi", False), outflow=(False, "lo", False))
+    p11 = pfl.make_params(wv)
+    assert list(p11.wall) == [1, 11, 0]
+    assert pfl._lib.pfl_query_sizes(C.byref(p11), C.byref(s)) == 0
+    wv["outflow"] = (False, "hi", False)
+    with pytest.raises(ValueError):
+        pfl.make_params(wv)
+    wv["outflow"] = (False, False, False)
+    p.v_in[1] = float("nan")
+    assert pfl._lib.pfl_query_sizes(C.byref(p), C.byref(s)) == -1
+    wv["symmetric"] = (False, True, False)
+    with pytest.raises(ValueError):
+        pfl.make_params(wv)
     w["farfield"] = ("lo", False, False)
     with pytest.raises(ValueError):
         pfl.make_params(w, "f64", "nearest")

@@ -51,6 +51,13 @@ CASES = {
     # perturbation decays
     "varheat_40x34": (lambda: dict(workloads.small(nx=40, ny=34, seed=13), th_rho_g=0.7, th_cp_g=0.9,
                                    th_k_g=0.5), 300),
+    # velocity sides: the inflow set-up of Sec. 3.3
+    "inlet_36x44": (lambda: dict(workloads.small(nx=36, ny=44, seed=11, fields=("ns", "psi", "theta"),
+                                                 periodic=(False, False, True)),
+                                 symmetric=(True, False, False), velocity=(False, "lo", False),
+                                 outflow=(False, "hi", False), v_in=(0.0, 0.01, 0.0),
+                                 seeds=[dict(x=-0.5, y=22.0, z=0.0, r=6.0, angle=0.0)]),
+                    300),
     # the AAC form for Le = O(1) (Appendix B)
     "le1_42x34": (lambda: dict(workloads.small(nx=42, ny=34, seed=9), aac_form="le1", Le=1.0, tau0=50.0), 300),
 }

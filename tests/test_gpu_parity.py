@@ -84,6 +84,25 @@ CASES = [
                                               periodic=(False, False, True), symmetric=("lo", "lo", False),
                                               farfield=("hi", "hi", False), aac_form="le1", Le=1.0, tau0=50.0,
                                               seeds=[dict(x=-0.5, y=-0.5, z=0.0, r=6.0, angle=0.0)]), 40),
+    # velocity sides (Sec. 3, boundary paragraph): non-equilibrium extrapolation
+    ("couette_vel_hi_seed_20x14", dict(nx=20, ny=14, seed=32, fields=("ns", "psi", "theta"),
+                                       periodic=(True, False, True), velocity=(False, "hi", False),
+                                       v_in=(0.02, 0.0, 0.0)), 40),
+    # the inflow set-up of Sec. 3.3: symmetry planes in x, flow in through the bottom, out through the top
+    ("inlet_xsym_vel_30x40", dict(nx=30, ny=40, seed=33, fields=("ns", "psi", "theta"),
+                                  periodic=(False, False, True), symmetric=(True, False, False),
+                                  velocity=(False, True, False), v_in=(0.0, 0.01, 0.0),
+                                  seeds=[dict(x=-0.5, y=20.0, z=0.0, r=6.0, angle=0.0)]), 40),
+    # a velocity side at the bottom, a pressure side at the top (the inflow workload's sides)
+    ("inlet_xsym_vel_pres_28x36", dict(nx=28, ny=36, seed=35, fields=("ns", "psi", "theta"),
+                                       periodic=(False, False, True), symmetric=(True, False, False),
+                                       velocity=(False, "lo", False), outflow=(False, "hi", False),
+                                       v_in=(0.003, 0.01, 0.0),
+                                       seeds=[dict(x=-0.5, y=18.0, z=0.0, r=5.0, angle=0.0)]), 40),
+    # a sliding velocity side between walls (corners with walls), solute and heat
+    ("alloy_vel_lo_walls_26x30", dict(nx=26, ny=30, seed=34, fields=("ns", "psi", "c", "theta"),
+                                      periodic=(False, False, True), velocity=(False, "lo", False),
+                                      v_in=(0.01, 0.0, 0.0)), 40),
     ("noflow_varheat_far_28x26", dict(nx=28, ny=26, seed=29, fields=("phi", "psi", "c", "theta"),
                                       periodic=(False, False, True), symmetric=(True, False, False),
                                       farfield=(False, "hi", False), th_rho_g=0.7, th_cp_g=0.6, th_k_g=2.0), 40),

@@ -1,0 +1,216 @@
+"""Velocity sides of the oracle: the Dirichlet velocity boundary by
+non-equilibrium extrapolation (Sec. 3, boundary paragraph), and the flow
+equilibrium it is built from.
+
+* The flow equilibrium has the moments of the pressure-based scheme (Sec. 3):
+  sum f^eq = 0, sum c f^eq = rho v, sum c c f^eq = p I + rho v v.
+* A uniform oblique flow through a box fed by velocity sides stays uniform to
+  rounding.
+* Between a half-way bounce-back wall (at y = -1/2) and a velocity side (the
+  ghost node at y = n), plane Couette flow is an exact steady state of the LB:
+  the shear's non-equilibrium part is the same at every node, so extrapolating
+  it is exact, and u(y) = U (y + 1/2) / (n + 1/2) to rounding.  The
+  non-equilibrium part, the density factor and the velocity of the ghost's
+  equilibrium are each caught by this pin.
+* A channel between walls fed through velocity sides carries the prescribed
+  flux through every row and develops the Poiseuille profile mid-way.
+* A pressure side (the same extrapolation with p = 0 at the ghost and the
+  node's own velocity) opposite a velocity side: a pressure offset on a
+  uniform flow relaxes to the side's pressure, and a channel drained by it
+  carries the prescribed flux through every row.
+"""
+import pytest
+import torch
+
+import workloads
+from oracle import OracleParams, OracleSim
+
+DT = torch.float64
+
+
+def make(w, cls=OracleSim):
+    return cls(OracleParams.from_workload(w))
+
+
+class NoQuadEquilibrium(OracleSim):
+    """Planted: the equilibrium without its (c.v)^2 term."""
+
+    def ns_equilibrium(self, L, p, rho, v):
+        cv = self.cdot(L, v)
+        vv = (v * v).sum(0)
+        w = self.wv(L, vv)
+        feq = w * p / L.cs2 + rho * w * (cv / L.cs2 - vv / (2 * L.cs2))
+        feq[0] = feq[0] - p / L.cs2
+        return feq
+
+
+class EquilibriumOnly(OracleSim):
+    """Planted: the ghost's equilibrium without the non-equilibrium part."""
+
+    def nee(self, L, fs, p, rho, v):
+        vb = torch.stack([torch.full(self.grid, float(u), dtype=DT) for u in self.p.v_in])
+        return self.ns_equilibrium(L, p, rho, vb)
+
+
+class ZeroGradient(OracleSim):
+    """Planted: the entering population copied from the node (no velocity imposed)."""
+
+    def nee(self, L, fs, p, rho, v):
+        return fs
+
+
+class NoDensity(OracleSim):
+    """Planted: the equilibrium difference taken at unit density."""
+
+    def nee(self, L, fs, p, rho, v):
+        return super().nee(L, fs, p, torch.ones_like(rho), v)
+
+
+class ReversedVelocity(OracleSim):
+    """Planted: the ghost's equilibrium at -v_in."""
+
+    def nee(self, L, fs, p, rho, v):
+        vb = torch.stack([torch.full(self.grid, -float(u), dtype=DT) for u in self.p.v_in])
+        return fs + self.ns_equilibrium(L, p, rho, vb) - self.ns_equilibrium(L, p, rho, v)
+
+
+def flow_workload(nx, ny, periodic_x, **kw):
+    w = workloads.small(nx=nx, ny=ny, fields=("ns", "psi", "theta"), periodic=(periodic_x, False, True),
+                        Le=1.0, theta0=-0.3)
+    w.update(seeds=[], **kw)
+    return w
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_flow_equilibrium_moments(dim):
+    for cls, ok in ((OracleSim, True), (NoQuadEquilibrium, False)):
+        w = workloads.small(dim=dim, nx=5, ny=4, nz=3, seed=3)
+        s = make(w, cls)
+        g = torch.Generator().manual_seed(dim)
+        shape = s.grid
+        p = 0.01 * torch.randn(shape, generator=g, dtype=DT)
+        rho = 1 + torch.rand(shape, generator=g, dtype=DT)
+        v = 0.05 * torch.randn((s.d,) + shape, generator=g, dtype=DT)
+        L = s.L_ns
+        feq = s.ns_equilibrium(L, p, rho, v)
+        c = L.c.to(DT)
+        m0 = feq.sum(0)
+        m1 = torch.einsum("ia,i...->a...", c, feq)
+        m2 = torch.einsum("ia,ib,i...->ab...", c, c, feq)
+        eye = torch.eye(s.d, dtype=DT).view(s.d, s.d, *([1] * len(shape)))
+        ref2 = eye * p + rho * v.unsqueeze(1) * v.unsqueeze(0)
+        good = (m0.abs().max() < 1e-15 and (m1 - rho * v).abs().max() < 1e-15
+                and (m2 - ref2).abs().max() < 1e-15)
+        assert bool(good) == ok, cls.__name__
+
+
+def test_uniform_oblique_flow_through_velocity_sides_stays_exact():
+    for cls, ok in ((OracleSim, True), (ReversedVelocity, False)):
+        vin = (0.02, 0.05)
+        w = flow_workload(8, 10, True, rho_l=2.0, velocity=(False, True, False), v_in=vin + (0.0,))
+        s = make(w, cls)
+        one = torch.ones(s.grid, dtype=DT)
+        s.init_from_macros(v=torch.stack([vin[0] * one, vin[1] * one]))
+        s.step(60)
+        m = s.macros()
+        err = max(float((m["v"][a] - vin[a]).abs().max()) for a in range(2))
+        assert (err < 1e-14) == ok, (cls.__name__, err)
+
+
+def couette_error(cls, ny=12, U=0.02, steps=1000):
+    """max |u - U (y + 1/2) / (ny + 1/2)| / U after the start-up decays
+    (viscosity 0.5: the slowest mode decays by e^-29)."""
+    w = flow_workload(4, ny, True, nu_l=0.5, rho_l=2.0, velocity=(False, "hi", False), v_in=(U, 0.0, 0.0))
+    s = make(w, cls)
+    s.init_fields()
+    s.step(steps)
+    m = s.macros()
+    y = torch.arange(ny, dtype=DT)
+    return float((m["v"][0][:, 0] - U * (y + 0.5) / (ny + 0.5)).abs().max()) / U
+
+
+def test_couette_between_a_wall_and_a_velocity_side_is_exact():
+    assert couette_error(OracleSim) < 1e-10            # measured 4e-12
+
+
+@pytest.mark.parametrize("cls", [EquilibriumOnly, ZeroGradient, NoDensity, ReversedVelocity])
+def test_couette_catches(cls):
+    assert couette_error(cls, steps=400) > 1e-2          # measured 0.068, 0.92, 0.068, 1.84
+
+
+def channel(cls, nx=10, ny=40, u=0.01, steps=800):
+    w = flow_workload(nx, ny, False, nu_l=0.25, rho_l=2.0, velocity=(False, True, False), v_in=(0.0, u, 0.0))
+    s = make(w, cls)
+    one = torch.ones(s.grid, dtype=DT)
+    s.init_from_macros(v=torch.stack([0 * one, u * one]))
+    s.step(steps)
+    m = s.macros()
+    flux = m["v"][1].sum(1) / (nx * u)
+    sx = torch.arange(nx, dtype=DT) + 0.5
+    mid = m["v"][1][ny // 2] / u
+    return flux, float((mid - 6 * sx * (nx - sx) / nx ** 2).abs().max())
+
+
+def test_channel_carries_the_prescribed_flux_and_develops_poiseuille():
+    flux, dev = channel(OracleSim)
+    assert float((flux - 1).abs().max()) < 5e-4, flux    # measured 1.0e-4
+    assert dev < 2e-2, dev                               # measured 0.014 (0.002 once steady)
+
+
+def test_channel_flux_catches_a_zero_gradient_side():
+    flux, _ = channel(ZeroGradient, steps=300)
+    assert float((flux - 1).abs().max()) > 0.1
+
+
+class ZeroGradientOutflow(OracleSim):
+    """Planted: the outflow copies the node's population (no pressure held)."""
+
+    def nee_outflow(self, L, fs, p, rho, v):
+        return fs
+
+
+class FlippedOutflow(OracleSim):
+    """Planted: the pressure correction with the wrong sign."""
+
+    def nee_outflow(self, L, fs, p, rho, v):
+        return fs - self.ns_equilibrium(L, torch.zeros_like(p), rho, v) + self.ns_equilibrium(L, p, rho, v)
+
+
+def pressure_offset_left(cls, steps=1200, p0=0.01):
+    """|p| / p0 after a uniform flow from a velocity side to a pressure side
+    started with the pressure p0 everywhere."""
+    vin = (0.01, 0.03)
+    w = flow_workload(4, 16, True, rho_l=2.0, nu_l=0.5, velocity=(False, "lo", False),
+                      outflow=(False, "hi", False), v_in=vin + (0.0,))
+    s = make(w, cls)
+    one = torch.ones(s.grid, dtype=DT)
+    s.init_from_macros(v=torch.stack([vin[0] * one, vin[1] * one]))
+    L = s.L_ns
+    add = s.wv(L, one) * p0 / L.cs2 * one
+    add[0] = add[0] - p0 / L.cs2
+    s.state["f_ns"] = s.state["f_ns"] + add
+    assert abs(float(s.macros()["p"].mean()) - p0) < 1e-15
+    s.step(steps)
+    left = float(s.macros()["p"].abs().max()) / p0
+    return left if left == left else float("inf")
+
+
+def test_pressure_offset_relaxes_to_the_outflow_pressure():
+    assert pressure_offset_left(OracleSim) < 1e-2      # measured 1.8e-4
+
+
+@pytest.mark.parametrize("cls", [ZeroGradientOutflow, FlippedOutflow])
+def test_pressure_offset_catches(cls):
+    assert pressure_offset_left(cls, steps=300) > 0.5   # measured 1.0, non-finite
+
+
+def test_channel_drained_by_a_pressure_side_carries_the_flux():
+    nx, ny, u = 10, 40, 0.01
+    w = flow_workload(nx, ny, False, nu_l=0.25, rho_l=2.0, velocity=(False, "lo", False),
+                      outflow=(False, "hi", False), v_in=(0.0, u, 0.0))
+    s = make(w)
+    one = torch.ones(s.grid, dtype=DT)
+    s.init_from_macros(v=torch.stack([0 * one, u * one]))
+    s.step(800)
+    flux = s.macros()["v"][1].sum(1) / (nx * u)
+    assert float((flux - 1).abs().max()) < 5e-4, flux  # measured 1.4e-4

@@ -284,6 +284,46 @@ def bubble_dendrites2d_200x400():
     return c
 
 
+def rising_bubble2d_120x480():
+    """The rising bubble of Sec. 3.2 (Re = 35, Bo = 10, density and viscosity
+    ratios 10) on the right half of [-D, D] x [0, 4D]: D = 120 nodes
+    (dx = 1/240 with D = 0.5), symmetry planes on both x sides (the periodic
+    full domain is symmetric about x = 0 and hence about x = D), walls at the
+    bottom and top, the bubble centred on the left plane at y = D.  With
+    dt = dx^2 and the liquid density scaled to 1: nu_l = nu_g = mu/rho = 0.01
+    in lattice units, g = 0.98 dx^3 = 7.09e-8, sigma = 24.5 / 1000 * dx =
+    1.021e-4 (so Re = D sqrt(g D) / nu_l = 35 and Bo = g D^2 / sigma = 10);
+    interface width xi = 4 sqrt(2) W_phi with W_phi = 0.004 / dx = 0.96
+    nodes.  The paper does not state the mobility; M_phi = 0.1.  No solid,
+    solute or heat: the flow and the bubble phase field only."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="rising_bubble2d_120x480", nx=120, ny=480, periodic=(False, False, True),
+             symmetric=(True, False, False), fields=("ns", "phi"),
+             rho_l=1.0, rho_g=0.1, nu_l=0.01, nu_g=0.01, g=0.98 / 240.0 ** 3,
+             sigma=24.5 / 1000.0 / 240.0, xi=4.0 * math.sqrt(2.0) * 0.96, M_phi=0.1,
+             seeds=[], bubbles=[dict(x=-0.5, y=119.5, z=0.0, r=60.0)], steps=172800)
+    return c
+
+
+def inlet_thermal2d_256x512():
+    """The thermal dendrite in an inflow of Sec. 3.3: the domain [0, L] x
+    [-L, L] with L = 256 nodes, the parameters of corner_thermal2d_256 (dx =
+    0.4 W0, dt = 0.008 tau0, undercooling 0.55, eps4 0.05, Pe_D = 0.25,
+    Le = 1), a seed of radius 10 dx on the left side at y = L, the inflow
+    v_in = (0, W0 / tau0) = 0.02 nodes per step through the bottom, and
+    Pr = nu / alpha = 23.1 with alpha = W0^2 / (Pe_D tau0) = 0.2: nu_l = 4.62.
+    Readings where the paper is silent: the top is a pressure side (p = 0),
+    psi and theta take the melt's values on the bottom and top, both x sides
+    are symmetry planes, and the melt starts at rest."""
+    c = copy.deepcopy(_BASE)
+    c.update(name="inlet_thermal2d_256x512", nx=256, ny=512, periodic=(False, False, True),
+             symmetric=(True, False, False), velocity=(False, "lo", False), outflow=(False, "hi", False),
+             v_in=(0.0, 0.02, 0.0), fields=("ns", "psi", "theta"), tau0=125.0, eps4=0.05, PeD=0.25, Le=1.0, Mcinf=0.0,
+             U0=0.0, theta0=-0.55, rho_l=1.0, nu_l=23.1 * 0.2,
+             seeds=[dict(x=-0.5, y=255.5, z=0.0, r=10.0, angle=0.0)], bubbles=[], steps=16000)
+    return c
+
+
 def small(dim=2, nx=12, ny=10, nz=1, fields=FIELDS_ALL, seed=0, periodic=None,
           **over):
     """Tiny grids for brute-force parity: one seed and one bubble placed at
@@ -342,6 +382,8 @@ CONFIGS = {
     "adjoint2d_512": adjoint2d_512,
     "adjoint2d_64": adjoint2d_64,
     "coupled3d_256": coupled3d_256,
+    "rising_bubble2d_120x480": rising_bubble2d_120x480,
+    "inlet_thermal2d_256x512": inlet_thermal2d_256x512,
 }
 
 
