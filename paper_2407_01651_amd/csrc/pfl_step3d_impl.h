@@ -216,8 +216,9 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
   __shared__ CT s_psi[3 * P1::N];
   __shared__ CT s_U[CC ? 3 * P1::N : 1];
   __shared__ CT s_j[NS ? 3 * P1::N : 1];
-  __shared__ CT s_D[FLOWX ? 9 * P1::N : 1];     // [slot][component][position]
-  __shared__ CT s_v0[FLOWX ? 9 * P1::N : 1];
+  // D_phi and v0 of the plane formed last, tile + ring 1: [component][position]
+  __shared__ CT s_D[FLOWX ? 3 * P1::N : 1];
+  __shared__ CT s_v0[FLOWX ? 3 * P1::N : 1];
 
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
@@ -272,12 +273,41 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
       dst[k] = hphi;
     }
   };
+  // FP64 with flow and bubble phase: a thread keeps the flow, psi and C
+  // populations it pulls for its own node in phase A, for the plane's phase C
+  // one step later (two planes in registers: that kernel runs one wave per
+  // SIMD, with room to spare), so that phase C pulls only phi and theta.  The
+  // other kernels would lose a wave per SIMD to it.
+  constexpr bool KEEP = sizeof(CT) == 8 && FLOWX;
+  constexpr int KN = KEEP && NS ? QN : 1, KS = KEEP && PSI ? QS : 1, KC = KEEP && CC ? QS : 1;
+  CT kA_ns[KN], kA_ps[KS], kA_c[KC];       // plane t (phase C of this step)
+  CT kB_ns[KN], kB_ps[KS], kB_c[KC];       // plane t + 1 (pulled in this step's phase A)
   // ---- phase A: psi, U and the momentum of plane p on the tile and one ring
   auto load_rest = [&](int p) {
     const bool fast = fast_at(p);
     CT* dpsi_ = s_psi + ring_slot(p, 3) * P1::N;
     CT* dU = s_U + (CC ? ring_slot(p, 3) * P1::N : 0);
-    for (int k = tid; k < P1::N; k += NT) {
+    // KEEP: the own interior position first, then the ring positions
+    // (top row, bottom row, then the two side columns)
+    constexpr int NPOS = KEEP ? 1 + (P1::N - NT + NT - 1) / NT : (P1::N + NT - 1) / NT;
+#pragma unroll 1
+    for (int it = 0; it < NPOS; ++it) {
+      int k;
+      const bool keep = KEEP && it == 0;
+      if constexpr (KEEP) {
+        if (it == 0) {
+          k = P1::at(ly + 1, lx + 1);
+        } else {
+          const int r = tid + (it - 1) * NT;
+          if (r >= P1::N - NT) break;
+          if (r < P1::X) k = r;
+          else if (r < 2 * P1::X) k = (P1::Y - 1) * P1::X + (r - P1::X);
+          else k = (1 + (r - 2 * P1::X) / 2) * P1::X + ((r - 2 * P1::X) % 2 ? P1::X - 1 : 0);
+        }
+      } else {
+        k = tid + it * NT;
+        if (k >= P1::N) break;
+      }
       const int tx = k % P1::X - 1, ty = k / P1::X - 1;
       const int gx0 = bx0 + tx, gy0 = by0 + ty;
       int gx = gx0, gy = gy0, gz = p;
@@ -294,6 +324,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
 #pragma unroll
         for (int i = 0; i < QS; ++i) d += f[i];
         hpsi = r_psi + d;
+        if constexpr (KEEP) {
+          if (keep) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) kB_ps[i] = f[i];
+          }
+        }
       }
       if constexpr (CC) {
         CT f[QS];
@@ -301,6 +337,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
         CT d = CT(0);
 #pragma unroll
         for (int i = 0; i < QS; ++i) d += f[i];
+        if constexpr (KEEP) {
+          if (keep) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) kB_c[i] = f[i];
+          }
+        }
         const CT hC = r_C + d;
         const CT h = (hpsi + CT(1)) * CT(0.5);
         hU = (hC * rcp(CT(1) - k1 * h) - CT(1)) * K.inv_k1;
@@ -313,6 +355,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           if (LN::c[i][0]) hj[0] += CT(LN::c[i][0]) * f[i];
           if (LN::c[i][1]) hj[1] += CT(LN::c[i][1]) * f[i];
           if (LN::c[i][2]) hj[2] += CT(LN::c[i][2]) * f[i];
+        }
+        if constexpr (KEEP) {
+          if (keep) {
+#pragma unroll
+            for (int i = 0; i < QN; ++i) kB_ns[i] = f[i];
+          }
         }
       }
       if (SYM && !fast && P.far) {
@@ -350,8 +398,8 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
     const CT* ph[3];
     phi_planes(m, ph);
     const CT* ps = s_psi + ring_slot(m, 3) * P1::N;
-    CT* dD = s_D + ring_slot(q, 3) * 3 * P1::N;
-    CT* dv = s_v0 + ring_slot(q, 3) * 3 * P1::N;
+    CT* dD = s_D;
+    CT* dv = s_v0;
     for (int k = tid; k < P1::N; k += NT) {
       const int rx = k % P1::X, ry = k / P1::X;
       const int g[2] = {bx0 + rx - 1, by0 + ry - 1};
@@ -381,6 +429,35 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
     }
   };
 
+  // The mass-flux force of the own node at plane z is the divergence
+  // (1/cs2) sum_i w_i (c_i . D(x + c_i)) v0(x + c_i) over the planes z - 1, z,
+  // z + 1.  Each plane's D and v0 are in LDS once, right after they are
+  // formed; the own thread then adds that plane's terms to the sums of the
+  // nodes below (c_i,z = +1), at (c_i,z = 0) and above it (c_i,z = -1):
+  // div_part returns the three groups.
+  auto div_part = [&](CT (&up)[3], CT (&mid)[3], CT (&dn)[3]) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) up[b] = mid[b] = dn[b] = CT(0);
+#pragma unroll
+    for (int i = 1; i < QN; ++i) {
+      const int q1 = P1::at(ly + 1 + LN::c[i][1], lx + 1 + LN::c[i][0]);
+      CT cD = CT(0);
+      if (LN::c[i][0]) cD += CT(LN::c[i][0]) * s_D[q1];
+      if (LN::c[i][1]) cD += CT(LN::c[i][1]) * s_D[P1::N + q1];
+      if (LN::c[i][2]) cD += CT(LN::c[i][2]) * s_D[2 * P1::N + q1];
+      const CT wc = CT(LN::w[i]) * cD;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const CT term = wc * s_v0[b * P1::N + q1];
+        if (LN::c[i][2] > 0) up[b] += term;
+        else if (LN::c[i][2] < 0) dn[b] += term;
+        else mid[b] += term;
+      }
+    }
+  };
+  // running sums for the own node at planes t and t + 1
+  CT dv_t[3] = {CT(0), CT(0), CT(0)}, dv_t1[3] = {CT(0), CT(0), CT(0)};
+
   // phi planes z0 - 2, z0 - 1 before the march when phi runs two planes ahead
   if constexpr (FLOWX) {
     load_phi(z0 - 2);
@@ -390,12 +467,33 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
     load_phi(t + (FLOWX ? 2 : 1));
     load_rest(t + 1);
     __syncthreads();
+    CT dv_t2[3] = {CT(0), CT(0), CT(0)};     // the own node at plane t + 2
     if constexpr (FLOWX) {
       const int q = t + 1;
+      CT up[3], mid[3], dn[3];
+      if (zwall && q == 0) {
+        // the ghost plane -1 (plane t): its terms reach plane t + 1 = 0
+        form_dv(-1, 0, true);
+        __syncthreads();
+        if (own_xy) {
+          div_part(up, mid, dn);
+#pragma unroll
+          for (int b = 0; b < 3; ++b) dv_t1[b] += dn[b];
+        }
+        __syncthreads();
+      }
       if (!zwall || (q >= 0 && q < P.nz)) form_dv(q, q, false);   // a ghost plane waits for its mirror
-      if (zwall && q == 0) form_dv(-1, 0, true);
       if (zwall && q == P.nz) form_dv(q, P.nz - 1, true);
       __syncthreads();
+      if (own_xy && (!zwall || (q >= 0 && q <= P.nz))) {
+        div_part(up, mid, dn);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          dv_t[b] += up[b];
+          dv_t1[b] += mid[b];
+          dv_t2[b] = dn[b];
+        }
+      }
     }
     if (t >= z0 && own_xy) {
       auto node = [&]() {
@@ -426,7 +524,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           }
         }
         if constexpr (NS) {
-          pull3<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, z, fns);
+          if constexpr (KEEP) {
+#pragma unroll
+            for (int i = 0; i < QN; ++i) fns[i] = kA_ns[i];
+          } else {
+            pull3<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, z, fns);
+          }
 #pragma unroll
           for (int i = 0; i < QN; ++i) {
             if (LN::c[i][0]) j[0] += CT(LN::c[i][0]) * fns[i];
@@ -441,13 +544,23 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           phi = r_phi + dphi;
         }
         if constexpr (PSI) {
-          pull3<QS, ST, CT, SYM>(fast, fin_psi, P, x, y, z, fps);
+          if constexpr (KEEP) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) fps[i] = kA_ps[i];
+          } else {
+            pull3<QS, ST, CT, SYM>(fast, fin_psi, P, x, y, z, fps);
+          }
 #pragma unroll
           for (int i = 0; i < QS; ++i) dpsi += fps[i];
           psi = r_psi + dpsi;
         }
         if constexpr (CC) {
-          pull3<QS, ST, CT, SYM>(fast, fin_c, P, x, y, z, fc);
+          if constexpr (KEEP) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) fc[i] = kA_c[i];
+          } else {
+            pull3<QS, ST, CT, SYM>(fast, fin_c, P, x, y, z, fc);
+          }
 #pragma unroll
           for (int i = 0; i < QS; ++i) dC += fc[i];
           C = r_C + dC;
@@ -468,14 +581,10 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
         flow_node3<NS, PHI, R, CT>(K, ph, s_psi + ring_slot(z, 3) * P1::N, nullptr, ly + 1, lx + 1, fo);
         const CT* psp[3];
         const CT* Up[3];
-        const CT* Dp[3];
-        const CT* vp[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           psp[c] = s_psi + ring_slot(z - 1 + c, 3) * P1::N;
           Up[c] = s_U + (CC ? ring_slot(z - 1 + c, 3) * P1::N : 0);
-          Dp[c] = s_D + (FLOWX ? ring_slot(z - 1 + c, 3) * 3 * P1::N : 0);
-          vp[c] = s_v0 + (FLOWX ? ring_slot(z - 1 + c, 3) * 3 * P1::N : 0);
         }
           // ---- phase C: the rest of the step at the own node
           // direction i of the 7-velocity sets leaves across a far-field side, whose
@@ -579,22 +688,10 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           if constexpr (NS) {
             CT Fm[3] = {CT(0), CT(0), CT(0)};
             if constexpr (FLOWX) {
-              // (div X)_b = (1/cs2) sum_i w_i (c_i . D(x + c_i)) v0_b(x + c_i)
+              // (div X)_b = (1/cs2) sum_i w_i (c_i . D(x + c_i)) v0_b(x + c_i), summed
+              // plane by plane as the planes were formed
 #pragma unroll
-              for (int i = 1; i < QN; ++i) {
-                const int q1 = P1::at(ly + 1 + LN::c[i][1], lx + 1 + LN::c[i][0]);
-                const CT* Dq = Dp[LN::c[i][2] + 1];
-                const CT* vq = vp[LN::c[i][2] + 1];
-                CT cD = CT(0);
-                if (LN::c[i][0]) cD += CT(LN::c[i][0]) * Dq[q1];
-                if (LN::c[i][1]) cD += CT(LN::c[i][1]) * Dq[P1::N + q1];
-                if (LN::c[i][2]) cD += CT(LN::c[i][2]) * Dq[2 * P1::N + q1];
-                const CT wc = CT(LN::w[i]) * cD;
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Fm[b] += wc * vq[b * P1::N + q1];
-              }
-#pragma unroll
-              for (int b = 0; b < 3; ++b) Fm[b] = K.drho * CT(3) * Fm[b];
+              for (int b = 0; b < 3; ++b) Fm[b] = K.drho * CT(3) * dv_t[b];
             }
             const CT Fb[3] = {CT(0), -(rho - K.rho_l) * K.g, CT(0)};
             const CT onechi = CT(1) - fo.chi;
@@ -849,6 +946,19 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
           }
       };
       node();
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      dv_t[b] = dv_t1[b];
+      dv_t1[b] = dv_t2[b];
+    }
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int i = 0; i < KN; ++i) kA_ns[i] = kB_ns[i];
+#pragma unroll
+      for (int i = 0; i < KS; ++i) kA_ps[i] = kB_ps[i];
+#pragma unroll
+      for (int i = 0; i < KC; ++i) kA_c[i] = kB_c[i];
     }
     __syncthreads();
   }
