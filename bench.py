@@ -94,7 +94,7 @@ def parse():
                     help="shorten the adjoint workload (profiling runs); default its 2000 steps")
     ap.add_argument("--cpu-window", type=int, default=64,
                     help="edge of the window of the headline workload the CPU oracle steps")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--calib", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -247,13 +247,19 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100, steps=None):
 
 def time_cpu(w, n, steps):
     """The CPU oracle (float64 PyTorch, as it stands) on an n-node window of
-    workload w around its first bubble (or its centre), steps steps."""
+    workload w centred between the closest seed-bubble pair (so that the
+    window holds a growing seed and a bubble; else its centre), steps steps."""
     import torch
     import workloads
     from oracle import OracleParams, OracleSim
     d = w["dim"]
-    c = ([w["bubbles"][0][k] for k in "xyz"[:d]] if w["bubbles"]
-         else [w[k] / 2 for k in ("nx", "ny", "nz")[:d]])
+    ks = "xyz"[:d]
+    pairs = [(math.dist([s[k] for k in ks], [b[k] for k in ks]), s, b) for s in w["seeds"] for b in w["bubbles"]]
+    if pairs:
+        _, s0, b0 = min(pairs, key=lambda t: t[0])
+        c = [(s0[k] + b0[k]) / 2 for k in ks]
+    else:
+        c = [w[k] / 2 for k in ("nx", "ny", "nz")[:d]]
     ww = workloads.window(w, n, c)
     sim = OracleSim(OracleParams.from_workload(ww))
     sim.init_fields()
