@@ -161,8 +161,13 @@ __device__ __forceinline__ Reader reader_of(const DevParams& P, int x, int y, in
 // TAPED: the step's stencil results (grad and Laplacian of phi, grad psi,
 // grad U, mass-flux force) are read from the tape the forward step wrote, so
 // the tile's halo and its LDS stencils are not redone.
+// FP32 compute without symmetry planes or far-field sides: two waves per SIMD
+// asked of the register allocator (it then fits 256 VGPRs without scratch;
+// left alone it takes a few AGPRs beyond them and runs one wave per SIMD).
+// The other instantiations would spill to scratch and keep one wave.
 template <int FIELDS, int QP, class ST, class HT, class CT, bool TAPED, bool SYM = false>
-__global__ __launch_bounds__(NT) void adj_local_kernel(const DevParams P,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((SYM || sizeof(CT) == 8) ? 1 : 2)))
+void adj_local_kernel(const DevParams P,
                                                        const typename Store<ST>::raw* __restrict__ fin,
                                                        const HT* __restrict__ hist,
                                                        const CT* __restrict__ tape,
