@@ -419,17 +419,17 @@ void step2d_kernel(const DevParams P,
   constexpr int QMAX = NS ? QN : ((PHI && QP > QS) ? QP : QS);
   const RoundBits<LOWP ? (QMAX + 1) / 2 : 1> rb(LOWP ? round_seed(P, (uint32_t)idx) : 0u, LOWP && P.sr);
   // store of population i of the set whose first plane is o
+  // (one address form for every grid: the plane's base is uniform, the node
+  // offset one 64-bit shift-add; a run-time choice between two forms would
+  // merge them into a VGPR pointer computed per store)
   auto st = [&](int o, int i, CT v) {
-    const int plane = o + i;
-    typename Store<ST>::raw* p = P.fast ? at_byte<ST>(fout, (uint32_t)plane * (uint32_t)N * S + nbyte)
-                                        : fout + (long long)plane * N + idx;
+    typename Store<ST>::raw* p = fout + (long long)(o + i) * N + idx;
     uint32_t r = 0u;
     if constexpr (LOWP) r = rb.bits(i);
     store_pop<ST, CT, STREAM>(P, p, v, r);
   };
   auto hst = [&](int plane, CT v) {
-    HT* q = P.fast ? (HT*)((char*)hist + (uint32_t)plane * hplane + hbyte) : hist + (long long)plane * N + idx;
-    put<STREAM, HT>(q, (HT)v);
+    put<STREAM, HT>(hist + (long long)plane * N + idx, (HT)v);
   };
 
   // ---- NS collision: f* = feq + F/2 + (1 - s_nu) P_s (f - feq + F/2),
