@@ -273,12 +273,15 @@ __global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_
       dst[k] = hphi;
     }
   };
-  // FP64 with flow and bubble phase: a thread keeps the flow, psi and C
-  // populations it pulls for its own node in phase A, for the plane's phase C
-  // one step later (two planes in registers: that kernel runs one wave per
-  // SIMD, with room to spare), so that phase C pulls only phi and theta.  The
-  // other kernels would lose a wave per SIMD to it.
-  constexpr bool KEEP = sizeof(CT) == 8 && FLOWX;
+  // FP64 and FP32 storage with flow and bubble phase: a thread keeps the
+  // flow, psi and C populations it pulls for its own node in phase A, for the
+  // plane's phase C one step later (two planes in registers), so that phase C
+  // pulls only phi and theta.  The FP64 kernel runs one wave per SIMD with
+  // room to spare, the FP32 one still fits two (256^3 FP64 2.55k -> 2.65k,
+  // FP32 6.03k -> 6.42k MLUPS); with 16-bit storage the kept values spill
+  // (FP16 6.34k -> 6.18k), and the other field combinations would lose a
+  // wave per SIMD.
+  constexpr bool KEEP = FLOWX && sizeof(raw) >= 4;
   constexpr int KN = KEEP && NS ? QN : 1, KS = KEEP && PSI ? QS : 1, KC = KEEP && CC ? QS : 1;
   CT kA_ns[KN], kA_ps[KS], kA_c[KC];       // plane t (phase C of this step)
   CT kB_ns[KN], kB_ps[KS], kB_c[KC];       // plane t + 1 (pulled in this step's phase A)
