@@ -32,12 +32,14 @@ namespace pfl {
 
 namespace {
 
-// Column tile: 32 x 8 in FP32 compute (256 threads; rows of 32 nodes keep
-// each wave's loads and stores in whole or half 128-byte lines), 32 x 4 in
-// FP64 (LDS).
+// Column tile: 32 x 8 nodes, 256 threads (rows of 32 nodes keep each wave's
+// loads and stores in whole or half 128-byte lines).  FP64 runs one wave per
+// SIMD either way; against 32 x 4 the taller column spreads the ring pulls
+// over more nodes (coupled 256^3 FP64 2.65k -> 2.75k MLUPS) and fits the
+// LDS (55 KB).
 template <class CT>
 struct Col3 {
-  static constexpr int TX = 32, TY = sizeof(CT) == 8 ? 4 : 8;
+  static constexpr int TX = 32, TY = 8;
   static constexpr int NT = TX * TY;
 };
 
