@@ -39,7 +39,7 @@ namespace {
 // LDS (55 KB).
 template <class CT>
 struct Col3 {
-  static constexpr int TX = 32, TY = 8;
+  static constexpr int TX = 32, TY = sizeof(CT) == 8 ? 8 : 16;
   static constexpr int NT = TX * TY;
 };
 
@@ -193,7 +193,7 @@ __device__ __forceinline__ void flow_node3(const KP<CT>& K, const CT* const ph[3
 
 template <int FIELDS, class ST, class HT, class CT, bool SYM, bool STREAM>
 // FP32 compute: two waves per SIMD (256 threads per workgroup)
-__global__ __launch_bounds__(Col3<CT>::NT, sizeof(CT) == 4 ? 2 : 1) void step3d_kernel(const DevParams P,
+__global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams P,
                                                                const typename Store<ST>::raw* __restrict__ fin,
                                                                typename Store<ST>::raw* __restrict__ fout,
                                                                HT* hist, double* __restrict__ mout,
