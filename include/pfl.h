@@ -128,7 +128,7 @@ typedef struct {
                                C = 1 and theta = theta0 (Sec. 3.4, Sec. 4): populations of
                                those sets crossing it come back by anti-bounce-back,
                                -f*_i + 2 w_i value; NS and phi see a wall there.
-                               A velocity side (2D, flow without the gas phase) prescribes
+                               A velocity side (flow without the gas phase) prescribes
                                the velocity v_in by non-equilibrium extrapolation (Sec. 3,
                                boundary paragraph): the flow population entering node x
                                from the ghost node x - c_i is f*_i(x) + f^eq_i(p, rho, v_in)

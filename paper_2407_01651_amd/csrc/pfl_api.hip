@@ -88,7 +88,6 @@ int validate(const pfl_params* p) {
   bool vel = false;
   for (int a = 0; a < 3; ++a) vel = vel || (p->wall[a] >= 7 && p->wall[a] <= 11);
   if (vel) {
-    if (p->dim != 2) return fail(PFL_E_UNSUPPORTED, "velocity and pressure sides are built for 2D");
     if (!(f & PFL_NS) || (f & PFL_PHI))
       return fail(PFL_E_UNSUPPORTED, "velocity and pressure sides need the flow and no gas phase");
     for (int a = 0; a < 3; ++a)

@@ -22,6 +22,7 @@ bool step3d_supported(int fields) {
     case F_NS | F_PHI:
     case F_PSI:
     case F_PHI:
+    case F_NS | F_PSI | F_TH:
       return true;
     default:
       return false;

@@ -779,21 +779,46 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
               const CT qyz = (r * CT(0.25)) * (syz - rho * vy * vz + CT(0.5) * (vy * Fz + vz * Fy) + c6 * (vy * gz + vz * gy));
               const CT qxz = (r * CT(0.25)) * (sxz - rho * vx * vz + CT(0.5) * (vx * Fz + vz * Fx) + c6 * (vx * gz + vz * gx));
               const CT rho3 = CT(3) * rho;
-#pragma unroll
-              for (int i = 0; i < QN; ++i) {
+              auto post = [&](int i) -> CT {
                 const int cx = LN::c[i][0], cy = LN::c[i][1], cz = LN::c[i][2];
                 const CT w = CT(LN::w[i]);
-                CT fs;
-                if (i == 0) {
-                  fs = w * A - CT(3) * p;
-                } else {
-                  const CT cv = CT(cx) * vx + CT(cy) * vy + CT(cz) * vz;
-                  const CT cF = CT(cx) * Fx + CT(cy) * Fy + CT(cz) * Fz;
-                  const CT cg = CT(cx) * gx + CT(cy) * gy + CT(cz) * gz;
-                  const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
-                  fs = w * t + (CT(2 * cx * cx - cy * cy - cz * cz) * q9 + CT(cy * cy - cz * cz) * q11 +
+                if (i == 0) return w * A - CT(3) * p;
+                const CT cv = CT(cx) * vx + CT(cy) * vy + CT(cz) * vz;
+                const CT cF = CT(cx) * Fx + CT(cy) * Fy + CT(cz) * Fz;
+                const CT cg = CT(cx) * gx + CT(cy) * gy + CT(cz) * gz;
+                const CT t = cv * (rho3 + CT(4.5) * (rho * cv + cF) + CT(1.5) * cg) + CT(1.5) * cF + A;
+                return w * t + (CT(2 * cx * cx - cy * cy - cz * cz) * q9 + CT(cy * cy - cz * cz) * q11 +
                                 CT(cx * cy) * qxy + CT(cy * cz) * qyz + CT(cx * cz) * qxz);
-                }
+              };
+              // Velocity and pressure sides (non-equilibrium extrapolation, Sec. 3
+              // boundary paragraph): the slot of population i leaving across one
+              // holds what the node pulls back along j = opp(i) next step, its own
+              // f*_j plus f^eq_j(p, rho, v_in) - f^eq_j(p, rho, v) (velocity side)
+              // or f^eq_j(0, rho, v) - f^eq_j(p, rho, v) = -w_j p / cs2 (pressure
+              // side); a velocity side takes precedence where both are crossed.
+              auto nee_out = [&](int i) -> int {
+                if constexpr (!SYM) return 0;
+                if (fast || !(P.vel | P.pres)) return 0;
+                const int dx = LN::c[i][0], dy = LN::c[i][1], dz = LN::c[i][2];
+                auto across = [&](int m) {
+                  return (dx > 0 && x == P.nx - 1 && ((m >> 3) & 1)) || (dx < 0 && x == 0 && (m & 1)) ||
+                         (dy > 0 && y == P.ny - 1 && ((m >> 4) & 1)) || (dy < 0 && y == 0 && ((m >> 1) & 1)) ||
+                         (dz > 0 && z == P.nz - 1 && ((m >> 5) & 1)) || (dz < 0 && z == 0 && ((m >> 2) & 1));
+                };
+                return across(P.vel) ? 1 : (across(P.pres) ? 2 : 0);
+              };
+              auto nee = [&](int j, int kind) -> CT {
+                if (kind == 2) return -CT(LN::w[j]) * p * CT(3);
+                const CT cx = CT(LN::c[j][0]), cy = CT(LN::c[j][1]), cz = CT(LN::c[j][2]);
+                const CT bx = CT(P.vin[0]), by = CT(P.vin[1]), bz = CT(P.vin[2]);
+                const CT cb = cx * bx + cy * by + cz * bz, cv = cx * vx + cy * vy + cz * vz;
+                return rho * CT(LN::w[j]) *
+                       ((cb - cv) * CT(3) + (cb * cb - cv * cv) * CT(4.5) - (bx * bx + by * by + bz * bz - vv) * CT(1.5));
+              };
+#pragma unroll
+              for (int i = 0; i < QN; ++i) {
+                CT fs = post(i);
+                if (const int kind = nee_out(i)) fs = post(LN::opp[i]) + nee(LN::opp[i], kind);
                 st(P.o_ns, i, fs);
               }
             }
@@ -1005,6 +1030,8 @@ hipError_t dispatch3(const DevParams& P, int fields, const void* fin, void* fout
       return launch_step3d_t<F_PSI, ST, HT, CT>(P, fin, fout, hist, mout, mode, s);
     case F_PHI:
       return launch_step3d_t<F_PHI, ST, HT, CT>(P, fin, fout, hist, mout, mode, s);
+    case F_NS | F_PSI | F_TH:
+      return launch_step3d_t<F_NS | F_PSI | F_TH, ST, HT, CT>(P, fin, fout, hist, mout, mode, s);
     default:
       ok = false;
       return hipSuccess;

@@ -55,6 +55,17 @@ CASES = [
                                     seeds=[dict(x=7.0, y=9.5, z=4.0, r=3.5, angle=0.3)]), 25),
     # heat properties varying between gas and liquid
     ("all_varheat_16x14x10", dict(nx=16, ny=14, nz=10, seed=37, th_rho_g=0.7, th_cp_g=0.9, th_k_g=0.5), 20),
+    # flow with the solid and heat, no gas phase; velocity and pressure sides (Sec. 3, boundary paragraph)
+    ("ns_psi_theta_walls_15x11x9", dict(nx=15, ny=11, nz=9, seed=40, fields=("ns", "psi", "theta"),
+                                        periodic=(False, False, False)), 20),
+    ("couette3d_vel_hi_seed_16x12x10", dict(nx=16, ny=12, nz=10, seed=41, fields=("ns", "psi", "theta"),
+                                            periodic=(True, False, True), velocity=(False, "hi", False),
+                                            v_in=(0.02, 0.0, 0.01)), 25),
+    ("inlet3d_xsym_vel_pres_14x10x18", dict(nx=14, ny=10, nz=18, seed=42, fields=("ns", "psi", "theta"),
+                                            periodic=(False, True, False), symmetric=(True, False, False),
+                                            velocity=(False, False, "lo"), outflow=(False, False, "hi"),
+                                            v_in=(0.002, 0.0, 0.01),
+                                            seeds=[dict(x=-0.5, y=5.0, z=9.0, r=4.0, angle=0.2)]), 25),
     # the AAC form for Le = O(1) (Appendix B), F >= 1 above its stability bound
     ("all_le1_18x12x8", dict(nx=18, ny=12, nz=8, seed=38, aac_form="le1", Le=1.0, tau0=50.0), 20),
     ("alloy_theta_le1_16x12x9", dict(nx=16, ny=12, nz=9, seed=39, fields=("psi", "c", "theta"),

@@ -133,6 +133,23 @@ def test_couette_between_a_wall_and_a_velocity_side_is_exact():
     assert couette_error(OracleSim) < 1e-10            # measured 4e-12
 
 
+def test_couette_3d_is_exact():
+    """The same in 3D (D3Q19), the side velocity oblique in the x-z plane."""
+    ny, U, W = 10, 0.02, 0.01
+    w = workloads.small(dim=3, nx=4, ny=ny, nz=4, fields=("ns", "psi", "theta"), periodic=(True, False, True),
+                        Le=1.0, theta0=-0.3, nu_l=0.5, rho_l=2.0)
+    w.update(seeds=[], velocity=(False, "hi", False), v_in=(U, 0.0, W))
+    s = make(w)
+    s.init_fields()
+    s.step(800)
+    m = s.macros()
+    y = torch.arange(ny, dtype=DT)
+    prof = (y + 0.5) / (ny + 0.5)
+    ex = max(float((m["v"][0][:, :, 0] - U * prof.view(1, -1)).abs().max()) / U,
+             float((m["v"][2][:, :, 0] - W * prof.view(1, -1)).abs().max()) / W)
+    assert ex < 1e-10, ex
+
+
 @pytest.mark.parametrize("cls", [EquilibriumOnly, ZeroGradient, NoDensity, ReversedVelocity])
 def test_couette_catches(cls):
     assert couette_error(cls, steps=400) > 1e-2          # measured 0.068, 0.92, 0.068, 1.84
