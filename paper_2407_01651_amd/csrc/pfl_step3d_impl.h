@@ -205,7 +205,13 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   constexpr int TX = Col3<CT>::TX, TY = Col3<CT>::TY, NT = Col3<CT>::NT;
   using PR = Pl<CT, R>;
   using P1 = Pl<CT, 1>;
-  constexpr int NPH = FLOWX ? 4 : 3;       // phi plane slots
+  // LDS plane slots.  Phase C of plane t reads the phi, psi and U planes t - 1,
+  // t, t + 1; phase A of plane t + 1, which a thread may reach while others
+  // are still in that phase C (no barrier between them), writes phi at
+  // t + 1 + (FLOWX ? 2 : 1) and psi, U at t + 2: with these slot counts those
+  // land on planes nobody reads then.
+  constexpr int NPH = FLOWX ? 5 : 4;       // phi plane slots
+  constexpr int NPS = 4;                   // psi and U plane slots
   constexpr int QN = 19, QS = 7, QP = 7;
   using LN = Lat<19>;
   using LS = Lat<7>;
@@ -215,8 +221,8 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   const KP<CT>& K = kp<CT>(P);
 
   __shared__ CT s_phi[NPH * PR::N];
-  __shared__ CT s_psi[3 * P1::N];
-  __shared__ CT s_U[CC ? 3 * P1::N : 1];
+  __shared__ CT s_psi[NPS * P1::N];
+  __shared__ CT s_U[CC ? NPS * P1::N : 1];
   __shared__ CT s_j[NS ? 3 * P1::N : 1];
   // D_phi and v0 of the plane formed last, tile + ring 1: [component][position]
   __shared__ CT s_D[FLOWX ? 3 * P1::N : 1];
@@ -290,8 +296,8 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   // ---- phase A: psi, U and the momentum of plane p on the tile and one ring
   auto load_rest = [&](int p) {
     const bool fast = fast_at(p);
-    CT* dpsi_ = s_psi + ring_slot(p, 3) * P1::N;
-    CT* dU = s_U + (CC ? ring_slot(p, 3) * P1::N : 0);
+    CT* dpsi_ = s_psi + ring_slot(p, NPS) * P1::N;
+    CT* dU = s_U + (CC ? ring_slot(p, NPS) * P1::N : 0);
     // KEEP: the own interior position first, then the ring positions
     // (top row, bottom row, then the two side columns)
     constexpr int NPOS = KEEP ? 1 + (P1::N - NT + NT - 1) / NT : (P1::N + NT - 1) / NT;
@@ -402,7 +408,7 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   auto form_dv = [&](int q, int m, bool flip_z) {
     const CT* ph[3];
     phi_planes(m, ph);
-    const CT* ps = s_psi + ring_slot(m, 3) * P1::N;
+    const CT* ps = s_psi + ring_slot(m, NPS) * P1::N;
     CT* dD = s_D;
     CT* dv = s_v0;
     for (int k = tid; k < P1::N; k += NT) {
@@ -583,13 +589,13 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
         FlowNode3<CT> fo;
         const CT* ph[3];
         phi_planes(z, ph);
-        flow_node3<NS, PHI, R, CT>(K, ph, s_psi + ring_slot(z, 3) * P1::N, nullptr, ly + 1, lx + 1, fo);
+        flow_node3<NS, PHI, R, CT>(K, ph, s_psi + ring_slot(z, NPS) * P1::N, nullptr, ly + 1, lx + 1, fo);
         const CT* psp[3];
         const CT* Up[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          psp[c] = s_psi + ring_slot(z - 1 + c, 3) * P1::N;
-          Up[c] = s_U + (CC ? ring_slot(z - 1 + c, 3) * P1::N : 0);
+          psp[c] = s_psi + ring_slot(z - 1 + c, NPS) * P1::N;
+          Up[c] = s_U + (CC ? ring_slot(z - 1 + c, NPS) * P1::N : 0);
         }
           // ---- phase C: the rest of the step at the own node
           // direction i of the 7-velocity sets leaves across a far-field side, whose
@@ -990,7 +996,9 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
 #pragma unroll
       for (int i = 0; i < KC; ++i) kA_c[i] = kB_c[i];
     }
-    __syncthreads();
+    // no barrier here: the next phase A writes slots this phase C does not
+    // read (the slot counts above), the D_phi/v0 plane is read before the
+    // barrier after phase B, and the momentum plane only in phase B
   }
 }
 
