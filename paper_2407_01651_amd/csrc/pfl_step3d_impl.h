@@ -257,11 +257,20 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   const CT r_C = DEV ? K.C_ref : CT(0), r_H = DEV ? K.theta0 : CT(0);
   const bool first = P.first != 0;
 
+  // FP64 and FP32 storage with flow and bubble phase: a thread keeps the
+  // flow, psi and C populations it pulls for its own node in phase A, for the
+  // plane's phase C one step later (two planes in registers), so that phase C
+  // pulls only phi and theta.  The FP64 kernel runs one wave per SIMD with
+  // room to spare, the FP32 one still fits two (256^3 FP64 2.55k -> 2.65k,
+  // FP32 6.03k -> 6.42k MLUPS); with 16-bit storage the kept values spill
+  // (FP16 6.34k -> 6.18k), and the other field combinations would lose a
+  // wave per SIMD.
+  constexpr bool KEEP = FLOWX && sizeof(raw) >= 4;
   // ---- phase A: phi of plane p on the tile and R rings
   auto load_phi = [&](int p) {
     const bool fast = fast_at(p);
     CT* dst = s_phi + ring_slot(p, NPH) * PR::N;
-    for (int k = tid; k < PR::N; k += NT) {
+    auto one = [&](int k) {
       const int tx = k % PR::X - R, ty = k / PR::X - R;
       int gx = bx0 + tx, gy = by0 + ty, gz = p;
       if (!fast) {
@@ -279,17 +288,41 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
         hphi = r_phi + d;
       }
       dst[k] = hphi;
+    };
+    if constexpr (KEEP) {
+      // positions beyond the first NT go to the last threads (the first ones
+      // take the extra ring positions of load_rest), so no wave does both
+      // (A/B on one box: 256^3 FP64 2.82k -> 2.88k, FP32 7.31k -> 7.39k
+      // MLUPS; the kernels without kept populations measured slower with
+      // this loop and keep the plain one)
+      constexpr int NPASS = (PR::N + NT - 1) / NT;
+#pragma unroll 1
+      for (int it = 0; it < NPASS; ++it) {
+        const int k = it == 0 ? tid : it * NT + (NT - 1 - tid);
+        if (k < PR::N) one(k);
+      }
+    } else {
+      for (int k = tid; k < PR::N; k += NT) {
+        const int tx = k % PR::X - R, ty = k / PR::X - R;
+        int gx = bx0 + tx, gy = by0 + ty, gz = p;
+        if (!fast) {
+          gx = map_coord(gx, P.nx, P.wall[0]);
+          gy = map_coord(gy, P.ny, P.wall[1]);
+          gz = map_coord(gz, P.nz, P.wall[2]);
+        }
+        CT hphi = CT(1);
+        if constexpr (PHI) {
+          CT f[QP];
+          pull3<QP, ST, CT, SYM>(fast, fin_phi, P, gx, gy, gz, f);
+          CT d = CT(0);
+#pragma unroll
+          for (int i = 0; i < QP; ++i) d += f[i];
+          hphi = r_phi + d;
+        }
+        dst[k] = hphi;
+      }
     }
   };
-  // FP64 and FP32 storage with flow and bubble phase: a thread keeps the
-  // flow, psi and C populations it pulls for its own node in phase A, for the
-  // plane's phase C one step later (two planes in registers), so that phase C
-  // pulls only phi and theta.  The FP64 kernel runs one wave per SIMD with
-  // room to spare, the FP32 one still fits two (256^3 FP64 2.55k -> 2.65k,
-  // FP32 6.03k -> 6.42k MLUPS); with 16-bit storage the kept values spill
-  // (FP16 6.34k -> 6.18k), and the other field combinations would lose a
-  // wave per SIMD.
-  constexpr bool KEEP = FLOWX && sizeof(raw) >= 4;
   constexpr int KN = KEEP && NS ? QN : 1, KS = KEEP && PSI ? QS : 1, KC = KEEP && CC ? QS : 1;
   CT kA_ns[KN], kA_ps[KS], kA_c[KC];       // plane t (phase C of this step)
   CT kB_ns[KN], kB_ps[KS], kB_c[KC];       // plane t + 1 (pulled in this step's phase A)
