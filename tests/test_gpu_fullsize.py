@@ -9,7 +9,9 @@ are exported, seeded windows away from walls are cut out, and the oracle
 takes one step on each window (periodic window, grain angle of the nearest
 seed at the window's global coordinates); the interior, four rings in from
 the window edge, is compared element by element:
-* FP64 (alloy 1024^2): 1e-12 normwise relative, as the small-grid parity;
+* FP64 (alloy 1024^2; the coupled 256^3 headline of bench.py; a coupled
+  4608^2 grid whose 4.9 GB population buffer takes the library's 64-bit
+  addressing path): 1e-12 normwise relative, as the small-grid parity;
 * FP16 storage (coupled 2048^2, coupled 256^3): the GPU stores the
   deviation from the rest state rounded (stochastically) to FP16, so each
   population may differ from the FP64 oracle by one FP16 spacing of its
@@ -130,9 +132,9 @@ def _rest_deviation_scale(w, planes):
     return torch.tensor(r, dtype=torch.float64)
 
 
-def _run(name, store, n, size, count, seed, tol_kind):
+def _run(name, store, n, size, count, seed, tol_kind, **over):
     import paper_2407_01651_amd as pfl
-    w = workloads.get(name)
+    w = workloads.get(name, **over)
     dim = w["dim"]
     log(f"[fullsize] {name} {store}: {n} steps, {count + 1} windows of {size}^{dim}")
     sim = pfl.Sim(w, store=store)
@@ -197,3 +199,17 @@ def test_coupled2d_2048_fp16_windows():
 
 def test_coupled3d_256_fp16_windows():
     _run("coupled3d_256", "f16", 10, 16, 4, 3, "fp16")
+
+
+def test_coupled3d_256_fp64_windows():
+    """The bench headline (coupled 256^3, FP64) at its full size."""
+    _run("coupled3d_256", "f64", 10, 16, 4, 4, "fp64")
+
+
+def test_coupled2d_64bit_offsets_fp64_windows():
+    """4608^2 coupled FP64: the population buffer (29 planes of 8 B per node)
+    exceeds 4 GiB, so the step addresses every buffer with 64-bit offsets
+    instead of the 32-bit byte offsets of smaller grids."""
+    n = 4608
+    assert 29 * 8 * n * n > 1 << 32
+    _run("coupled2d_2048", "f64", 20, 26, 4, 5, "fp64", nx=n, ny=n)
