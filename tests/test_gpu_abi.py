@@ -2,7 +2,9 @@
 the GPU: the macro field mask and FP32 output of pfl_get_macros, the
 library's defaults of pfl_init_from_macros against the oracle's, the in-step
 NaN/Inf checks of pfl_step (reduce_every), pfl_last_check, a step-0 state
-re-imported with pfl_set_state, and pfl_adjoint_seed."""
+re-imported with pfl_set_state, pfl_adjoint_seed, and the adjoint's refusal
+of the forms it does not cover (the Le = O(1) AAC form, velocity and
+pressure sides)."""
 import pytest
 import torch
 
@@ -155,4 +157,20 @@ def test_no_adjoint_for_the_le_form():
     with pytest.raises(pfl.PflError) as e:
         g.step_backward(lam, out, dp)
     assert e.value.code == pfl.E_UNSUPPORTED and "Le = O(1)" in str(e.value)
+    g.close()
+
+
+def test_no_adjoint_with_velocity_sides():
+    import paper_2407_01651_amd as pfl
+    w = workloads.small(nx=20, ny=16, seed=47, fields=("ns", "psi", "theta"), periodic=(True, False, True))
+    w.update(velocity=(False, "lo", False), outflow=(False, "hi", False), v_in=(0.0, 0.01, 0.0))
+    g = _sim(w, adjoint=True)
+    g.init_fields()
+    g.step(2)
+    lam = g.adjoint_seed(psi=torch.ones(16, 20, dtype=torch.float64, device="cuda"))
+    out = torch.empty_like(lam)
+    dp = torch.zeros(3 + len(w["bubbles"]), dtype=torch.float64, device="cuda")
+    with pytest.raises(pfl.PflError) as e:
+        g.step_backward(lam, out, dp)
+    assert e.value.code == pfl.E_UNSUPPORTED and "velocity or pressure" in str(e.value)
     g.close()
