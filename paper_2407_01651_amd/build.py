@@ -14,7 +14,15 @@ SRC = ["pfl_api.hip", "pfl_step2d.hip", "pfl_step2d_lowp.hip", "pfl_step3d.hip",
 # built without them.
 LOWP = {"pfl_step2d_lowp.hip", "pfl_step3d_lowp.hip", "pfl_adj2d_lowp.hip"}
 LOWP_FLAGS = ["-ffp-contract=fast", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math",
-              "-freciprocal-math"]
+              "-freciprocal-math", "-ffinite-math-only"]
+# The step and adjoint kernels see finite values only (non-finite states are
+# detected by the reduction kernels, built strict).  Assuming so lets the
+# compiler drop products with a zero lattice component, x * 0 -> 0, which it
+# must keep under IEEE rules for the case x = inf or nan.  In the FP64 units
+# no contraction or reassociation comes with it: every finite result equals the
+# strict IEEE one, up to the sign of a zero.
+FINITE = {"pfl_step2d.hip", "pfl_step3d.hip", "pfl_adj2d.hip"}
+FINITE_FLAGS = ["-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"]
 OUT = os.path.join(HERE, "libpfl.so")
 
 FLAGS = [
@@ -36,6 +44,8 @@ def build(verbose=False, jobs=None):
         flags = [f for f in FLAGS if f != "-shared"]
         if s in LOWP:
             flags = [f for f in flags if f != "-ffp-contract=off"] + LOWP_FLAGS
+        elif s in FINITE:
+            flags = flags + FINITE_FLAGS
         cmd = [hipcc, "-c", os.path.join(HERE, "csrc", s), "-o", obj] + flags + inc
         if verbose:
             print(" ".join(cmd), flush=True)
