@@ -7,7 +7,9 @@ equation is solved, U0 = -Omega otherwise) and the initial bubble radii.
 the final phi and psi; its backward gives dL/dp for any loss L of them.
 
 Forward: one launch per step, with a raw checkpoint of the state (storage
-type, bit-exact) every K steps.  Backward, segment by segment from the last:
+type, bit-exact) every K steps; the last segment steps image to image with
+its tapes (below), so that its images are already there when the backward
+starts.  Backward, segment by segment from the last:
 the segment's states are recomputed from its checkpoint image to image with
 pfl_step_raw_taped (same stochastic rounding keys, so bit-identical), which
 also keeps each step's stencil results (its tape), then one
@@ -72,6 +74,7 @@ class CheckpointedRun:
         self.tapes = [[], []]
         self.sink = None
         self.steps = 0
+        self.kept = False                  # the last segment's images and tapes are current
         if steps is not None:
             self._reserve(int(steps))
 
@@ -98,9 +101,20 @@ class CheckpointedRun:
         self.steps = int(steps)
         self._reserve(self.steps)
         sim.init_fields()
+        n_ck = (self.steps + self.K - 1) // self.K
+        self.kept = False
         for i, s0 in enumerate(range(0, self.steps, self.K)):
             sim.save_raw(self.ckpts[i])
-            sim.step(min(self.K, self.steps - s0))
+            n = min(self.K, self.steps - s0)
+            if i == n_ck - 1 and self.taped:
+                # the last segment steps image to image with its tapes, into the
+                # set its reverse reads first, so that the reverse starts without
+                # a recompute; the final state goes back into the context
+                self._step_segment(sim, i)
+                sim.load_raw(self.sink, self.steps, False)
+                self.kept = True
+            else:
+                sim.step(n)
         return sim.macros()
 
     def lam_from_macros(self, g_phi=None, g_psi=None):
@@ -116,16 +130,23 @@ class CheckpointedRun:
     def _tapes(self, si):
         return self.tapes[si % 2 if self.overlap else 0]
 
+    def _step_segment(self, sim, si):
+        """Every step of segment si from its checkpoint, image to image with
+        its tape; the state after the segment's last step goes to the sink."""
+        s0 = si * self.K
+        n = min(self.K, self.steps - s0)
+        img = self._images(si)
+        tp = self._tapes(si)
+        for j in range(n):
+            out = img[j + 1] if j + 1 < n else self.sink
+            sim.step_raw_taped(img[j], out, s0 + j, s0 + j == 0, tp[j])
+
     def _recompute(self, si):
         s0 = si * self.K
         n = min(self.K, self.steps - s0)
         img = self._images(si)
         if self.taped:
-            # every step of the segment, the last one only for its tape
-            tp = self._tapes(si)
-            for j in range(n):
-                out = img[j + 1] if j + 1 < n else self.sink
-                self.rsim.step_raw_taped(img[j], out, s0 + j, s0 + j == 0, tp[j])
+            self._step_segment(self.rsim, si)
         else:
             for j in range(n - 1):
                 self.rsim.step_raw(img[j], img[j + 1], s0 + j, s0 + j == 0)
@@ -139,6 +160,8 @@ class CheckpointedRun:
         lam = lam.to(sim.adj_dtype).contiguous().clone()
         other = torch.empty_like(lam)
         n_ck = (self.steps + self.K - 1) // self.K
+        # the last segment comes from the forward when it kept its images
+        kept, self.kept = self.kept, False
         if self.overlap:
             # recompute of segment si - 1 (stream 2) runs beside the reverse of
             # segment si (main stream); a set of images is reused once the
@@ -148,8 +171,11 @@ class CheckpointedRun:
             self.rstream.wait_event(start)
             ready = [torch.cuda.Event() for _ in range(n_ck)]
             freed = [torch.cuda.Event(), torch.cuda.Event()]
-            self._recompute(n_ck - 1)
-            ready[n_ck - 1].record(self.rstream)
+            if kept:
+                ready[n_ck - 1].record(main)
+            else:
+                self._recompute(n_ck - 1)
+                ready[n_ck - 1].record(self.rstream)
         for si in range(n_ck - 1, -1, -1):
             s0 = si * self.K
             n = min(self.K, self.steps - s0)
@@ -160,7 +186,7 @@ class CheckpointedRun:
                     self._recompute(si - 1)
                     ready[si - 1].record(self.rstream)
                 main.wait_event(ready[si])
-            else:
+            elif not (kept and si == n_ck - 1):
                 self._recompute(si)
             tp = self._tapes(si)[:n] if self.taped else None
             sim.backward_sweep(self._images(si)[:n], s0, s0 == 0, tp, lam, other, dparams,
