@@ -266,11 +266,24 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   // (FP16 6.34k -> 6.18k), and the other field combinations would lose a
   // wave per SIMD.
   constexpr bool KEEP = FLOWX && sizeof(raw) >= 4;
+  // FP64 storage (one wave per SIMD, registers to spare) also keeps the own
+  // node's phi populations; phase A pulls phi two planes ahead, so three
+  // planes are held: kph0 for this step's phase C (plane t), kph1 (t + 1),
+  // kph2 (t + 2, pulled in this step's phase A)
+  constexpr bool KEEPPHI = KEEP && PHI && sizeof(raw) == 8;
+  constexpr int KP = KEEPPHI ? QP : 1;
+  CT kph0[KP], kph1[KP], kph2[KP];
+  auto rot_phi = [&]() {
+    if constexpr (KEEPPHI) {
+#pragma unroll
+      for (int i = 0; i < KP; ++i) { kph0[i] = kph1[i]; kph1[i] = kph2[i]; }
+    }
+  };
   // ---- phase A: phi of plane p on the tile and R rings
   auto load_phi = [&](int p) {
     const bool fast = fast_at(p);
     CT* dst = s_phi + ring_slot(p, NPH) * PR::N;
-    auto one = [&](int k) {
+    auto one = [&](int k, bool keep) {
       const int tx = k % PR::X - R, ty = k / PR::X - R;
       int gx = bx0 + tx, gy = by0 + ty, gz = p;
       if (!fast) {
@@ -286,10 +299,40 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
 #pragma unroll
         for (int i = 0; i < QP; ++i) d += f[i];
         hphi = r_phi + d;
+        if constexpr (KEEPPHI) {
+          if (keep) {
+#pragma unroll
+            for (int i = 0; i < QP; ++i) kph2[i] = f[i];
+          }
+        }
       }
       dst[k] = hphi;
     };
-    if constexpr (KEEP) {
+    if constexpr (KEEPPHI) {
+      // the own interior position first, then the ring positions (the R top
+      // rows, the R bottom rows, then the side columns), those on the last
+      // threads as below
+      constexpr int NPASS = 1 + (PR::N - NT + NT - 1) / NT;
+#pragma unroll 1
+      for (int it = 0; it < NPASS; ++it) {
+        int k;
+        if (it == 0) {
+          k = PR::at(ly + R, lx + R);
+        } else {
+          const int r = (it - 1) * NT + (NT - 1 - tid);
+          if (r >= PR::N - NT) continue;
+          if (r < R * PR::X) {
+            k = r;
+          } else if (r < 2 * R * PR::X) {
+            k = (PR::Y - R) * PR::X + (r - R * PR::X);
+          } else {
+            const int q = r - 2 * R * PR::X, c = q % (2 * R);
+            k = (R + q / (2 * R)) * PR::X + (c < R ? c : PR::X - 2 * R + c);
+          }
+        }
+        one(k, it == 0);
+      }
+    } else if constexpr (KEEP) {
       // positions beyond the first NT go to the last threads (the first ones
       // take the extra ring positions of load_rest), so no wave does both
       // (A/B on one box: 256^3 FP64 2.82k -> 2.88k, FP32 7.31k -> 7.39k
@@ -299,7 +342,7 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
 #pragma unroll 1
       for (int it = 0; it < NPASS; ++it) {
         const int k = it == 0 ? tid : it * NT + (NT - 1 - tid);
-        if (k < PR::N) one(k);
+        if (k < PR::N) one(k, false);
       }
     } else {
       for (int k = tid; k < PR::N; k += NT) {
@@ -505,7 +548,9 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   // phi planes z0 - 2, z0 - 1 before the march when phi runs two planes ahead
   if constexpr (FLOWX) {
     load_phi(z0 - 2);
+    rot_phi();
     load_phi(z0 - 1);
+    rot_phi();
   }
   for (int t = z0 - 2; t < z1; ++t) {
     load_phi(t + (FLOWX ? 2 : 1));
@@ -582,7 +627,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
           }
         }
         if constexpr (PHI) {
-          pull3<QP, ST, CT, SYM>(fast, fin_phi, P, x, y, z, fph);
+          if constexpr (KEEPPHI) {
+#pragma unroll
+            for (int i = 0; i < QP; ++i) fph[i] = kph0[i];
+          } else {
+            pull3<QP, ST, CT, SYM>(fast, fin_phi, P, x, y, z, fph);
+          }
 #pragma unroll
           for (int i = 0; i < QP; ++i) dphi += fph[i];
           phi = r_phi + dphi;
@@ -1029,6 +1079,7 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
 #pragma unroll
       for (int i = 0; i < KC; ++i) kA_c[i] = kB_c[i];
     }
+    rot_phi();
     // no barrier here: the next phase A writes slots this phase C does not
     // read (the slot counts above), the D_phi/v0 plane is read before the
     // barrier after phase B, and the momentum plane only in phase B
