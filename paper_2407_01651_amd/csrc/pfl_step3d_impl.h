@@ -369,6 +369,13 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
   constexpr int KN = KEEP && NS ? QN : 1, KS = KEEP && PSI ? QS : 1, KC = KEEP && CC ? QS : 1;
   CT kA_ns[KN], kA_ps[KS], kA_c[KC];       // plane t (phase C of this step)
   CT kB_ns[KN], kB_ps[KS], kB_c[KC];       // plane t + 1 (pulled in this step's phase A)
+  // FP16 storage keeps the flow populations only, as their stored bits two to
+  // a register (252 VGPRs, no scratch; 256^3 FP16 7.17k -> 7.35k MLUPS, A/B
+  // on one box; BF16 measured slower with it, 6.71k -> 6.37k, and pulls)
+  constexpr bool KEEP16 = FLOWX && std::is_same<ST, half_dev>::value;
+  constexpr bool OWN1 = KEEP || KEEP16;     // load_rest takes the own position first
+  constexpr int KW = KEEP16 ? (QN + 1) / 2 : 1;
+  uint32_t kA16[KW], kB16[KW];
   // ---- phase A: psi, U and the momentum of plane p on the tile and one ring
   auto load_rest = [&](int p) {
     const bool fast = fast_at(p);
@@ -376,12 +383,12 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
     CT* dU = s_U + (CC ? ring_slot(p, NPS) * P1::N : 0);
     // KEEP: the own interior position first, then the ring positions
     // (top row, bottom row, then the two side columns)
-    constexpr int NPOS = KEEP ? 1 + (P1::N - NT + NT - 1) / NT : (P1::N + NT - 1) / NT;
+    constexpr int NPOS = OWN1 ? 1 + (P1::N - NT + NT - 1) / NT : (P1::N + NT - 1) / NT;
 #pragma unroll 1
     for (int it = 0; it < NPOS; ++it) {
       int k;
-      const bool keep = KEEP && it == 0;
-      if constexpr (KEEP) {
+      const bool keep = OWN1 && it == 0;
+      if constexpr (OWN1) {
         if (it == 0) {
           k = P1::at(ly + 1, lx + 1);
         } else {
@@ -447,6 +454,13 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
           if (keep) {
 #pragma unroll
             for (int i = 0; i < QN; ++i) kB_ns[i] = f[i];
+          }
+        }
+        if constexpr (KEEP16) {
+          if (keep) {
+#pragma unroll
+            for (int w = 0; w < KW; ++w)
+              kB16[w] = keep16<ST>(f[2 * w], 2 * w + 1 < QN ? f[2 * w + 1] : CT(0));
           }
         }
       }
@@ -616,6 +630,9 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
           if constexpr (KEEP) {
 #pragma unroll
             for (int i = 0; i < QN; ++i) fns[i] = kA_ns[i];
+          } else if constexpr (KEEP16) {
+#pragma unroll
+            for (int i = 0; i < QN; ++i) fns[i] = unkeep16<ST>(kA16[i / 2], i % 2);
           } else {
             pull3<QN, ST, CT, SYM>(fast, fin_ns, P, x, y, z, fns);
           }
@@ -1078,6 +1095,10 @@ __global__ __launch_bounds__(Col3<CT>::NT, 1) void step3d_kernel(const DevParams
       for (int i = 0; i < KS; ++i) kA_ps[i] = kB_ps[i];
 #pragma unroll
       for (int i = 0; i < KC; ++i) kA_c[i] = kB_c[i];
+    }
+    if constexpr (KEEP16) {
+#pragma unroll
+      for (int w = 0; w < KW; ++w) kA16[w] = kB16[w];
     }
     rot_phi();
     // no barrier here: the next phase A writes slots this phase C does not

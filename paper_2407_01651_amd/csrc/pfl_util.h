@@ -47,6 +47,19 @@ __device__ __forceinline__ typename Store<ST>::raw* at_byte(typename Store<ST>::
   return (typename Store<ST>::raw*)((char*)base + b);
 }
 
+// Two values read from 16-bit storage, kept as their stored bits in one
+// register (exact: each is a value of the storage type), and one of them back.
+template <class ST>
+__device__ __forceinline__ uint32_t keep16(float a, float b) {
+  return (uint32_t)Store<ST>::enc(a) | ((uint32_t)Store<ST>::enc(b) << 16);
+}
+template <class ST>
+__device__ __forceinline__ float unkeep16(uint32_t w, int hi) {
+  using raw = typename Store<ST>::raw;
+  const raw r = __builtin_bit_cast(raw, (unsigned short)(hi ? w >> 16 : w & 0xffffu));
+  return Store<ST>::template ld<float>(&r);
+}
+
 // Random bits for the stochastic rounding of one node's stores.  The seed is
 // the PCG hash of (node, step); population i of a set takes the 16-bit half
 // i mod 2 of the PCG hash of the Weyl sequence entry seed + (i/2 + 1) * g
