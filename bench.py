@@ -238,6 +238,8 @@ def time_adjoint(name="adjoint2d_512", store="f32", K=100, steps=None):
             "forward_ms": round(t_fwd, 3),
             "forward_with_checkpoints_ms": round(t_ck, 3), "backward_ms": round(t_bwd, 3),
             "ratio": round((t_ck + t_bwd) / t_fwd, 3),
+            "ratio_note": "whole gradient (forward with checkpoints + backward) over the plain forward",
+            "backward_over_forward": round(t_bwd / t_fwd, 3),
             "resident": {"note": "every state and tape kept in HBM, no recompute",
                          "hbm_gb": round(r_gb, 1), "forward_taped_ms": round(r_fwd, 3),
                          "backward_ms": round(r_bwd, 3), "ratio": round((r_fwd + r_bwd) / t_fwd, 3)},
