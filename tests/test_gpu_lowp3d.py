@@ -108,3 +108,28 @@ def test_reduced_precision_3d_against_oracle(case, store):
         assert max(msg[k] for k in ("vx", "vy", "vz")) < b["v"], msg
     if "phi" in w["fields"]:
         assert msg["gas"] < b["gas"], msg
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", ["coupled_walls_22x18x14", "coupled_sym_far_20x16x14"])
+def test_z_chunks_give_the_same_state(case, store, monkeypatch):
+    """The 3D step marches each column through a chunk of z planes, with a
+    prologue of two planes and the own populations carried in registers
+    between phases; splitting z into more chunks (PFL_ZCHUNK) changes where
+    the marches start but no arithmetic, so the states agree bit for bit."""
+    import paper_2407_01651_amd as pfl
+    w = CASES[case][0]()
+    states = []
+    for zc in (None, "3"):
+        if zc is None:
+            monkeypatch.delenv("PFL_ZCHUNK", raising=False)
+        else:
+            monkeypatch.setenv("PFL_ZCHUNK", zc)
+        sim = pfl.Sim(w, store=store)
+        sim.init_fields()
+        sim.step(12)
+        states.append(sim.get_state().cpu())
+        sim.close()
+    monkeypatch.delenv("PFL_ZCHUNK", raising=False)
+    log(f"[lowp3d] z chunks {case} {store}: equal {torch.equal(states[0], states[1])}")
+    assert torch.equal(states[0], states[1])
