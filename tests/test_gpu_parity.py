@@ -187,6 +187,28 @@ def test_nonfinite_state_is_reported():
     assert r["nonfinite"] == 1
 
 
+@pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nonfinite_value_survives_steps(dim, store):
+    """The step kernels are compiled assuming finite values; a NaN in the
+    state still reaches the populations after steps of every form, 2D and
+    3D, and the FP64 reduction (compiled strictly) reports it."""
+    import paper_2407_01651_amd as pfl
+    if dim == 2:
+        w = _small(dict(nx=16, ny=12, seed=24))
+    else:
+        w = workloads.small(dim=3, nx=16, ny=12, nz=8, seed=24)
+    g = pfl.Sim(w, store=store)
+    phi = torch.ones(g.shape, dtype=torch.float64)
+    phi[(1,) * (dim - 2) + (5, 7)] = float("nan")
+    g.init_from_macros(phi=phi)
+    g.step(3)
+    r = g.reduce()
+    g.close()
+    log(f"[parity] nonfinite {dim}D {store}: {r['nonfinite']}")
+    assert r["nonfinite"] == 1
+
+
 def test_coupled_128_full_500_steps():
     """The coupled 128 x 128 workload, all 500 steps, FP64, full fields."""
     w = workloads.get("coupled2d_128")
